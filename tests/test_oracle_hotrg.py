@@ -1,0 +1,239 @@
+"""Pins of the oracle's HOTRG step and run against brute force, closed forms,
+symmetries and gauge invariances (none of them re-uses the oracle's own
+contraction code)."""
+import math
+import string
+
+import numpy as np
+import pytest
+
+from oracle import exact, hotrg, ising
+from trg_inputs import random_site_tensor
+
+
+def _explicit_two_site(A, B, mu):
+    """The two-site tensor M of the join along mu, legs (x0, x2, then for each
+    transverse nu: a_nu, b_nu, a'_nu, b'_nu), by one direct einsum."""
+    d = A.ndim // 2
+    L = iter(string.ascii_letters)
+    i, x0, x2 = next(L), next(L), next(L)
+    sa, sb, out = [], [], [x0, x2]
+    for ax in range(d):
+        if ax == mu:
+            sa += [x0, i]
+            sb += [i, x2]
+        else:
+            a, ap, b, bp = next(L), next(L), next(L), next(L)
+            sa += [a, ap]
+            sb += [b, bp]
+            out += [a, b, ap, bp]
+    return np.einsum("".join(sa) + "," + "".join(sb) + "->" + "".join(out), A, B)
+
+
+@pytest.mark.parametrize("d,dims,mu", [(3, (2, 3, 2), 0), (3, (2, 2, 3), 2), (4, (2, 3, 2, 2), 1), (4, (3, 2, 2, 2), 3)])
+def test_gram_equals_explicit_two_site_gram(d, dims, mu):
+    T = random_site_tensor(dims, seed=7)
+    M = _explicit_two_site(T, T, mu)
+    others = [nu for nu in range(d) if nu != mu]
+    for j, nu in enumerate(others):
+        for side in (0, 1):
+            # legs of M: x0, x2, then 4 per transverse axis (a, b, a', b')
+            pos = 2 + 4 * j + 2 * side
+            Mm = np.moveaxis(M, (pos, pos + 1), (0, 1))
+            n = Mm.shape[0] * Mm.shape[1]
+            Mm = Mm.reshape(n, -1)
+            G = hotrg.gram(T, T, mu, nu, side)
+            assert np.allclose(G, Mm @ Mm.T, rtol=0, atol=1e-12 * np.abs(G).max())
+
+
+def _definition_full(A, B, U, mu):
+    """C(A, B) by a single einsum of the defining sum over all legs."""
+    d = A.ndim // 2
+    M = _explicit_two_site(A, B, mu)
+    L = iter(string.ascii_letters)
+    x0, x2 = next(L), next(L)
+    sm, ops, subs, out = [x0, x2], [M], [], []
+    for ax in range(d):
+        if ax == mu:
+            out += [x0, x2]
+            continue
+        a, b, ap, bp, K, Kp = (next(L) for _ in range(6))
+        sm += [a, b, ap, bp]
+        subs += [a + b + K, ap + bp + Kp]
+        ops += [U[ax], U[ax]]
+        out += [K, Kp]
+    expr = "".join(sm) + "," + ",".join(subs) + "->" + "".join(out)
+    return np.einsum(expr, *ops, optimize="optimal")
+
+
+@pytest.mark.parametrize("d,dims,mu", [(2, (3, 2), 0), (2, (2, 3), 1), (3, (2, 3, 2), 1), (4, (2, 2, 3, 2), 0), (4, (2, 3, 2, 2), 2)])
+def test_coarse_grain_equals_definition(d, dims, mu, monkeypatch):
+    A = random_site_tensor(dims, seed=11)
+    B = random_site_tensor(dims, seed=12)
+    rng = np.random.default_rng(3)
+    U = {}
+    for nu in range(d):
+        if nu != mu:
+            dn = dims[nu]
+            U[nu] = rng.standard_normal((dn, dn, min(dn * dn, 3)))
+    ref = _definition_full(A, B, U, mu)
+    got = hotrg.coarse_grain(A, B, U, mu)
+    assert np.allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # the (x0, x2)-sliced evaluation gives the same tensor
+    monkeypatch.setattr(hotrg, "SLICE_ELEMENTS", 1)
+    got2 = hotrg.coarse_grain(A, B, U, mu)
+    assert np.allclose(got2, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    sub = hotrg.coarse_grain(A, B, U, mu, x0s=[1], x2s=[0, 1])
+    idx = [slice(None)] * (2 * d)
+    idx[2 * mu], idx[2 * mu + 1] = slice(1, 2), slice(0, 2)
+    assert np.allclose(sub, ref[tuple(idx)], rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_kept_vectors_do_not_depend_on_eigenbasis():
+    """The canonical basis of a degenerate eigenspace is a function of the
+    space: rotating the eigenvectors inside it leaves the kept vectors equal."""
+    rng = np.random.default_rng(5)
+    n = 9
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    w = np.array([5.0, 3.0, 3.0, 3.0, 1.0, 0.5, 0.5, 0.1, 0.0])
+    v1 = Q.copy()
+    R, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    v2 = Q.copy()
+    v2[:, 1:4] = Q[:, 1:4] @ R
+    S, _ = np.linalg.qr(rng.standard_normal((2, 2)))
+    v2[:, 5:7] = Q[:, 5:7] @ S
+    v2[:, 0] *= -1
+    for k in (1, 2, 3, 4, 6, 7):
+        a = hotrg._kept_vectors(w, v1, k)
+        b = hotrg._kept_vectors(w, v2, k)
+        assert np.allclose(a, b, atol=1e-13)
+        assert np.allclose(a.T @ a, np.eye(k), atol=1e-13)
+
+
+@pytest.mark.parametrize("d,L", [(2, 4), (3, 2), (4, 2)])
+def test_beta_zero_gives_ln2(d, L):
+    r = hotrg.run(0.0, 0.3, d, 4, L, impure=False)
+    assert abs(r.ln_z_per_site - math.log(2.0)) < 1e-14
+
+
+@pytest.mark.parametrize("beta,h", [(0.1, 0.0), (0.4407, 0.0), (0.8, 0.1), (0.3, -0.1)])
+def test_2d_L4_untruncated_equals_brute_force(beta, h):
+    r = hotrg.run(beta, h, 2, 16, 4)
+    lnz, E, M = exact.brute_force(beta, h, 2, 4)
+    assert abs(r.ln_z_per_site - lnz) < 1e-12
+    assert abs(r.energy - E) < 1e-12
+    assert abs(r.magnetization - M) < 1e-12
+
+
+@pytest.mark.parametrize("beta,h", [(0.25, 0.05)])
+def test_3d_L2_untruncated_equals_brute_force(beta, h):
+    r = hotrg.run(beta, h, 3, 16, 2)
+    lnz, E, M = exact.brute_force(beta, h, 3, 2)
+    assert abs(r.ln_z_per_site - lnz) < 1e-12
+    assert abs(r.energy - E) < 1e-12
+    assert abs(r.magnetization - M) < 1e-12
+
+
+def _two_steps_then_exact(beta, h, order):
+    """4D 2^4 periodic lattice: two untruncated HOTRG steps, then the x/y
+    legs closed on themselves and the remaining periodic 2x2 network in the
+    other two axes contracted exactly."""
+    T0, SM, SE = ising.site_tensors(beta, h, 4)
+    c0 = math.sqrt(float(np.sum(T0 * T0)))
+    T, imps = T0 / c0, [SE / c0, SM / c0]
+    lnz = math.log(c0)
+    for n, mu in enumerate(order, 1):
+        T, imps, c, _ = hotrg.hotrg_step(T, mu, 256, imps)
+        lnz += 2.0 ** -n * math.log(c)
+    rest = [a for a in range(4) if a not in order]
+
+    def close(X):
+        sub = list("abcdefgh")
+        for a in order:
+            sub[2 * a + 1] = sub[2 * a]
+        return np.einsum("".join(sub) + "->" + "".join(sub[2 * a] + sub[2 * a + 1] for a in rest), X)
+
+    Q, QE, QM = close(T), close(imps[0]), close(imps[1])
+    net = lambda A, B, C, D: np.einsum("abcd,baef,ghdc,hgfe->", A, B, C, D, optimize=True)
+    z = net(Q, Q, Q, Q)
+    return lnz + math.log(z) / 16, -net(QE, Q, Q, Q) / z, net(QM, Q, Q, Q) / z
+
+
+@pytest.mark.parametrize("beta,h,order", [(0.15, 0.0, (0, 1)), (0.2, 0.1, (2, 3)), (0.1497, 1e-2, (1, 3))])
+def test_4d_two_steps_equal_brute_force(beta, h, order):
+    lnz, E, M = _two_steps_then_exact(beta, h, order)
+    bl, bE, bM = exact.brute_force(beta, h, 4, 2)
+    assert abs(lnz - bl) < 1e-12
+    assert abs(E - bE) < 1e-12
+    assert abs(M - bM) < 1e-12
+
+
+@pytest.mark.parametrize("K,tol_f,tol_e", [(0.2, 1e-11, 1e-6), (0.4, 1e-6, 2e-4)])
+def test_2d_large_lattice_approaches_onsager(K, tol_f, tol_e):
+    r = hotrg.run(K, 0.0, 2, 16, 2 ** 20)
+    assert abs(r.ln_z_per_site - exact.onsager_lnz(K)) < tol_f
+    assert abs(r.energy - exact.onsager_energy(K)) < tol_e
+
+
+def test_2d_ordered_phase_magnetization_matches_yang():
+    K = 0.6
+    r = hotrg.run(K, 1e-10, 2, 16, 2 ** 20)
+    # Dcut = 16 truncation error of the impure-tensor M is about 2.4e-6 here
+    assert abs(r.magnetization - exact.yang_magnetization(K)) < 1e-5
+
+
+@pytest.mark.parametrize("beta", [0.05, 0.1])
+def test_high_temperature_series_2d(beta):
+    """Square lattice: ln Z/N = ln 2 + 2 ln cosh b + t^4 + 2 t^6 + (9/2) t^8 + O(t^10)
+    (closed polygons of length 4, 6, 8 on the infinite lattice, t = tanh b).
+    In 3D/4D the truncation error at small Dcut exceeds the t^6 term."""
+    r = hotrg.run(beta, 0.0, 2, 8, 64, impure=False)
+    t = math.tanh(beta)
+    series = exact.high_temp_lnz(beta, 2) + 2 * t ** 6 + 4.5 * t ** 8
+    assert abs(r.ln_z_per_site - series) <= 30 * t ** 10
+
+
+@pytest.mark.parametrize("d,L,dcut", [(2, 64, 8), (4, 4, 4)])
+def test_field_reversal_symmetry(d, L, dcut):
+    a = hotrg.run(0.1497 if d == 4 else 0.42, 1e-3, d, dcut, L)
+    b = hotrg.run(0.1497 if d == 4 else 0.42, -1e-3, d, dcut, L)
+    assert abs(a.ln_z_per_site - b.ln_z_per_site) < 1e-13
+    assert abs(a.energy - b.energy) < 1e-12
+    assert abs(a.magnetization + b.magnetization) < 1e-12
+
+
+def test_zero_field_disordered_magnetization_vanishes():
+    r = hotrg.run(0.1490, 0.0, 4, 4, 4)
+    assert abs(r.magnetization) < 1e-13
+
+
+def _rotate(seed):
+    rng = np.random.default_rng(seed)
+
+    def f(U):
+        out = {}
+        for nu, u in U.items():
+            k = u.shape[2]
+            O, _ = np.linalg.qr(rng.standard_normal((k, k)))
+            out[nu] = u @ O
+        return out
+    return f
+
+
+@pytest.mark.parametrize("d,L,dcut,beta,h", [(2, 16, 6, 0.42, 1e-3), (3, 4, 5, 0.2, 1e-3)])
+def test_gauge_invariance(d, L, dcut, beta, h):
+    """Side choice, normalisation and an orthogonal rotation of every
+    isometry's kept space leave ln Z/V, E and M unchanged.  (Only where no
+    cut splits a degenerate eigenspace: there the kept vectors depend on the
+    gauge of the input legs, and so does the truncated result.)"""
+    ref = hotrg.run(beta, h, d, dcut, L)
+    assert not any(a.degenerate_cut for s in ref.steps[1:] for a in s.axes)
+    variants = [
+        hotrg.run(beta, h, d, dcut, L, force_side=0),
+        hotrg.run(beta, h, d, dcut, L, norm="max"),
+        hotrg.run(beta, h, d, dcut, L, transform_u=_rotate(1)),
+    ]
+    for v in variants:
+        assert abs(v.ln_z_per_site - ref.ln_z_per_site) < 1e-12
+        assert abs(v.energy - ref.energy) < 1e-10
+        assert abs(v.magnetization - ref.magnetization) < 1e-10
