@@ -1,0 +1,219 @@
+/*
+ * libtrg -- HOTRG / ATRG coarse-graining of the Ising tensor network on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: S. Akiyama, Y. Kuramashi, T. Yamashita, Y. Yoshimura, "Phase
+ * transition of four-dimensional Ising model with tensor network scheme",
+ * Lattice 2019 (arXiv:1911.12954).  HOTRG: Sec. 2 and Fig. 1; ATRG: Sec. 2
+ * and Fig. 2; impure-tensor observables: Sec. 3.1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - A site tensor of a d-dimensional lattice (d in {2,3,4}) has 2d legs in the
+ *   order (x, x', y, y', z, z', t, t'): for axis nu the backward leg is 2*nu,
+ *   the forward leg 2*nu+1, and both legs of an axis have the same dim.
+ *   Tensors are dense, row-major (last leg fastest), FP64, in device memory
+ *   owned by the context.
+ * - All work of a context is enqueued on the HIP stream given in its config
+ *   (NULL = the legacy default stream).  Step calls are asynchronous; calls
+ *   that return numbers to the host synchronise that stream.
+ * - Return codes: TRG_OK (0) or a negative TRG_E* code.  No C++ exception
+ *   crosses this interface.  An error found before any work is enqueued
+ *   leaves the context unchanged.  An error found on the device (non-finite
+ *   or zero norm, eigensolver not converged) is reported by the next call
+ *   that synchronises; the context is then poisoned and every later call on
+ *   it returns TRG_ESTATE.  trg_last_error() describes the latest error.
+ */
+#ifndef TRG_H
+#define TRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TRG_OK = 0,
+  TRG_EINVAL = -1,   /* bad argument or shape */
+  TRG_ENOMEM = -2,   /* device allocation failed */
+  TRG_EHIP = -3,     /* HIP runtime error */
+  TRG_ESTATE = -4,   /* wrong state: poisoned context, impurity not enabled, ... */
+  TRG_ENUMERIC = -5  /* NaN/Inf or zero norm, eigensolver did not converge */
+};
+
+/* Arithmetic of the block-spin contraction (the D^{4d-1} join of Sec. 2).
+ * Gram matrices, their eigendecomposition, normalisation and the
+ * accumulated free energy are FP64 in every mode. */
+enum {
+  TRG_FP64 = 0,     /* FP64 operands, FP64 MFMA, FP64 result */
+  TRG_FP32 = 1,     /* operands rounded to FP32, FP32 MFMA, FP32 result */
+  TRG_BF16X3 = 2    /* operands split a = hi + lo (two BF16), hi*hi + hi*lo +
+                       lo*hi on BF16 MFMA with FP32 accumulation */
+};
+
+enum { TRG_HOTRG = 0, TRG_ATRG = 1 };
+
+/* impurity bits: energy (S_E = dT0/dbeta) and magnetization (S_M) */
+enum { TRG_IMPURE_E = 1u, TRG_IMPURE_M = 2u };
+
+typedef struct trg_config {
+  int precision;          /* TRG_FP64 (default), TRG_FP32, TRG_BF16X3 */
+  int method;             /* TRG_HOTRG (default) or TRG_ATRG */
+  int dcut;               /* bond dimension used by trg_run; > 0 */
+  unsigned impure;        /* TRG_IMPURE_E | TRG_IMPURE_M, or 0 */
+  int rsvd_p;             /* ATRG randomized SVD oversampling; 0 = 4*dcut */
+  int rsvd_q;             /* ATRG power iterations; < 0 = 2*dcut */
+  uint64_t seed;          /* ATRG trial-matrix seed */
+  void *stream;           /* hipStream_t; NULL = default stream */
+  /* Device allocator.  NULL alloc = hipMalloc/hipFree.  alloc returns NULL on
+   * failure; free must accept any pointer alloc returned. */
+  void *(*alloc)(size_t bytes, void *user);
+  void (*free)(void *ptr, void *user);
+  void *alloc_user;
+  size_t workspace_bytes; /* cap on the join workspace; 0 = automatic */
+} trg_config;
+
+typedef struct trg_ctx trg_ctx;
+
+/* Per-step record of a HOTRG step (what the host can read back). */
+typedef struct trg_step_rec {
+  int n;                  /* step number, 1-based */
+  int axis;               /* coarse-grained axis */
+  int dims[4];            /* per-axis leg dims after the step */
+  int side[4];            /* per transverse axis: 0 backward, 1 forward pair; -1 on axis */
+  int kept[4];            /* kept columns k_nu; 0 on the coarse-grained axis */
+  int degenerate_cut[4];  /* 1 if the cut splits a degenerate eigenspace */
+  int sweeps[4];          /* Jacobi sweeps used (chosen side) */
+  double ln_c;            /* ln of the Frobenius norm c_n of the new tensor */
+  double eps[4][2];       /* discarded eigenvalue sum, [axis][backward, forward] */
+  double seconds;         /* host wall time between launch of the step and the
+                             next synchronisation, 0 if not measured */
+} trg_step_rec;
+
+/* Create a context holding the initial Ising site tensor T0 of the
+ * d-dimensional model at inverse temperature beta >= 0 and field h (weight
+ * e^{-beta H}, H = -sum s_i s_j - h sum s_i), built from the bond split
+ * W = [[sqrt(cosh b), sqrt(sinh b)], [sqrt(cosh b), -sqrt(sinh b)]] in closed
+ * form, and the impure tensors requested by cfg->impure (S_E needs beta > 0).
+ * The tensor is normalised by its Frobenius norm c_0 and ln c_0 starts the
+ * free-energy accumulator.  cfg may be NULL (all defaults, dcut = 8).
+ * Errors: TRG_EINVAL (d, beta, h, cfg fields), TRG_ENOMEM, TRG_EHIP. */
+int trg_init_ising(trg_ctx **out, double beta, double h, int d, const trg_config *cfg);
+
+/* Create a context from an arbitrary FP64 site tensor copied from host memory
+ * (dims[nu] per axis, 2d legs in the conventional order, row-major).  The
+ * tensor is normalised like T0.  Used for tests on random tensors and for
+ * checkpoint restore.  Impurities are not available on such a context. */
+int trg_init_tensor(trg_ctx **out, int d, const int *dims, const double *host_tensor,
+                    const trg_config *cfg);
+
+/* One HOTRG coarse-graining step along `axis` (0 <= axis < d) with bond
+ * dimension `dcut` (Sec. 2, Fig. 1): HOSVD isometries from the two-site Gram
+ * matrices (FP64, Jacobi eigensolver on the device), the block-spin
+ * contraction in the configured precision, Frobenius normalisation and
+ * acc += 2^{-n} ln c_n.  Impure tensors follow with the same isometries and
+ * c_n.  Asynchronous.  Errors: TRG_EINVAL, TRG_ESTATE, TRG_ENOMEM, TRG_EHIP. */
+int trg_hotrg_step(trg_ctx *ctx, int axis, int dcut);
+
+/* The same step for n contexts that share d, precision and current dims and
+ * the same stream: every kernel of the step is launched once for all n
+ * (batched launches).  Results are identical to n separate calls. */
+int trg_hotrg_step_batch(trg_ctx *const *ctxs, int n, int axis, int dcut);
+
+/* ATRG step along `axis` (Sec. 2, Fig. 2).  Requires method == TRG_ATRG. */
+int trg_atrg_step(trg_ctx *ctx, int axis, int dcut);
+
+/* Coarse-grain the periodic lattice L^d (L = 2^m, m >= 1): d*m steps along
+ * axis (n-1) mod d with cfg->dcut, using the context's method.  Synchronises
+ * once at the end and returns TRG_ENUMERIC if a step failed. */
+int trg_run(trg_ctx *ctx, long long L);
+
+/* ln Z / V of the periodic lattice whose single block is the current tensor:
+ * acc + 2^{-n} ln Tr T_n (Tr joins each backward leg to the forward leg of
+ * the same axis).  Synchronises.  Caller owns *out. */
+int trg_free_energy(trg_ctx *ctx, double *lnz_per_site);
+
+/* E = <H>/V = -Tr S_E / Tr T and M = <s> = Tr S_M / Tr T (impure-tensor
+ * method, Sec. 3.1).  TRG_ESTATE if that impurity was not enabled. */
+int trg_impure_energy(trg_ctx *ctx, double *E);
+int trg_impure_magnetization(trg_ctx *ctx, double *M);
+
+/* Current leg dims per axis (d entries) and the number of steps taken. */
+int trg_get_dims(const trg_ctx *ctx, int *dims, int *steps);
+
+/* Copy the current normalised tensor (which = 0 pure, 1 S_E, 2 S_M) to host
+ * memory (cap = capacity in doubles).  Synchronises. */
+int trg_get_tensor(trg_ctx *ctx, int which, double *host_out, size_t cap);
+
+/* Copy the isometry U_nu[(a,b),k] of the latest step for transverse axis nu
+ * (row-major d_nu^2 x k_nu) and the descending spectrum of the chosen Gram
+ * (d_nu^2 values).  Either pointer may be NULL.  Synchronises. */
+int trg_get_isometry(trg_ctx *ctx, int nu, double *host_U, size_t capU,
+                     double *host_spectrum, size_t capS);
+
+/* Copy up to cap step records (oldest first); *n receives the count. */
+int trg_step_log(trg_ctx *ctx, trg_step_rec *out, int cap, int *n);
+
+/* Free-energy accumulator sum_{k<=n} 2^{-k} ln c_k (synchronises). */
+int trg_accumulator(trg_ctx *ctx, double *acc);
+
+/* Device bytes a context keeps resident for (d, dcut, precision, method,
+ * impure) at steady state, plus the join workspace it would use by default. */
+size_t trg_footprint_bytes(int d, int dcut, int precision, int method, unsigned impure);
+
+/* Wait for all work of the context's stream. */
+int trg_sync(trg_ctx *ctx);
+
+/* Destroy a context (NULL allowed); frees through the config's allocator. */
+void trg_free(trg_ctx *ctx);
+
+/* Text of the latest error on ctx (or of this thread's latest call that had
+ * no context).  Valid until the next call on the same context/thread. */
+const char *trg_last_error(const trg_ctx *ctx);
+
+/* ---- kernel-level entry points (used by the kernel tests and the bench) ----
+ * All pointers are device pointers; all calls are asynchronous on `stream`.
+ */
+
+/* C[m][n] (+)= sum_k A[m][k] * Bt[n][k] for the join GEMM (Sec. 2: the
+ * D^{4d-1} contraction).  A is M x K with row stride lda, Bt is N x K with row
+ * stride ldb, C is M x N with row stride ldc.  M, N must be multiples of the
+ * tile (trg_gemm_tile), K a multiple of 16 (FP64/FP32) or 32 (BF16X3); the
+ * caller zero-pads.  precision selects the element types: FP64 (double in,
+ * double out), FP32 (float in, float out), BF16X3 (A = A_hi, A + M*lda
+ * elements = A_lo, likewise for Bt; bf16 in, float out).  accumulate != 0 adds
+ * to C.  Returns TRG_EINVAL on shape violations. */
+int trg_gemm(int precision, const void *A, const void *Bt, void *C, long long M, long long N,
+             long long K, long long lda, long long ldb, long long ldc, int accumulate,
+             void *stream);
+
+/* Tile sizes (rows of A, rows of Bt) and K granule of trg_gemm. */
+int trg_gemm_tile(int precision, int *tile_m, int *tile_n, int *tile_k);
+
+/* Batched symmetric eigendecomposition by cyclic Jacobi (FP64): for each of
+ * `batch` matrices of order n (row-major, stride n*n apart) writes the
+ * eigenvalues in descending order to w[b*n ...] and the eigenvectors as
+ * columns of V[b*n*n ...] (row-major, column j belongs to w[j]).  A is
+ * overwritten.  sweeps[b] receives the sweeps used (-1: not converged). */
+int trg_eigh(double *A, double *w, double *V, int *sweeps, int n, int batch, void *stream);
+
+/* ---- diagnostics ----
+ * Time the join GEMM launches of a context with HIP events on its stream
+ * (on = 1 enables; trg_join_profile synchronises, returns the summed kernel
+ * milliseconds, launch count and issued 2*M*N*K flops of the padded
+ * problems since the last query, and resets them). */
+int trg_set_profiling(trg_ctx *ctx, int on);
+int trg_join_profile(trg_ctx *ctx, double *ms, long long *launches, double *flops);
+
+/* Force the HOSVD side (0 backward pairs, 1 forward pairs, -1 automatic:
+ * forward unless the backward truncation error is smaller by a relative
+ * 1e-10).  A gauge choice used by the tests of gauge invariance. */
+int trg_set_force_side(trg_ctx *ctx, int side);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRG_H */

@@ -1,0 +1,277 @@
+// FP64 symmetric eigendecomposition of the HOSVD Gram matrices (Fig. 1B of
+// the paper: the isometries are the leading eigenvectors of the two-site
+// environment) and the selection of the truncated isometry.
+//
+// Eigensolver: cyclic two-sided Jacobi in parallel (round-robin) order, one
+// workgroup per matrix.  Each round rotates n/2 disjoint index pairs: rows
+// first (A <- J^T A), then columns (A <- A J, V <- V J).  A sweep is n-1
+// rounds; sweeps repeat until the off-diagonal Frobenius norm falls below
+// 1e-14 of the matrix norm, plus one final sweep.  The matrix and vectors live in global memory
+// (they are small and stay in L2); the rotation parameters of a round are
+// in LDS.  Everything is deterministic: fixed pairing order, fixed
+// reduction trees.
+#include <cmath>
+
+#include "internal.h"
+
+namespace trg {
+namespace {
+
+constexpr int EIGH_THREADS = 512;
+constexpr int MAX_N = 1024;
+constexpr int MAX_SWEEPS = 40;
+
+__device__ inline double wg_sum(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = EIGH_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(EIGH_THREADS)
+jacobi_kernel(double *Aall, double *wall, double *Vall, int *sweeps_out, int n) {
+  __shared__ double sh[EIGH_THREADS];
+  __shared__ int pp[MAX_N / 2], pq[MAX_N / 2];
+  __shared__ double pc[MAX_N / 2], ps[MAX_N / 2];
+  __shared__ double wdiag[MAX_N];
+  __shared__ int rank[MAX_N];
+
+  const int b = blockIdx.x;
+  double *A = Aall + size_t(b) * n * n;
+  double *V = Vall + size_t(b) * n * n;
+  double *w = wall + size_t(b) * n;
+  const int t = threadIdx.x;
+  const int n2 = n * n;
+
+  for (int i = t; i < n2; i += EIGH_THREADS) V[i] = (i / n == i % n) ? 1.0 : 0.0;
+  double fro = 0.0;
+  for (int i = t; i < n2; i += EIGH_THREADS) fro += A[i] * A[i];
+  __syncthreads();
+  const double norm2 = wg_sum(fro, sh);
+
+  const int np = (n + 1) & ~1;  // even number of players; index n is a dummy
+  const int half = np / 2;
+  // converged once the off-diagonal norm is below 1e-14 of the matrix norm;
+  // one more sweep then brings it to the rounding level
+  int used = -1;
+  bool last = false;
+  for (int sweep = 0; sweep <= MAX_SWEEPS; ++sweep) {
+    if (last) {
+      used = sweep;
+      break;
+    }
+    double off = 0.0;
+    for (int i = t; i < n2; i += EIGH_THREADS)
+      if (i / n != i % n) off += A[i] * A[i];
+    const double offs = wg_sum(off, sh);
+    if (offs == 0.0 || norm2 == 0.0) {
+      used = sweep;
+      break;
+    }
+    if (offs <= 1e-28 * norm2) last = true;
+    if (sweep == MAX_SWEEPS) break;
+    for (int r = 0; r < np - 1; ++r) {
+      // circle pairing: player np-1 fixed, the others rotate
+      for (int j = t; j < half; j += EIGH_THREADS) {
+        int p, q;
+        if (j == 0) {
+          p = r;
+          q = np - 1;
+        } else {
+          p = (r + j) % (np - 1);
+          q = (r - j + (np - 1)) % (np - 1);
+        }
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[p * n + q];
+          if (apq != 0.0) {
+            const double tau = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+            const double tt = copysign(1.0, tau) / (fabs(tau) + hypot(1.0, tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+        }
+        pp[j] = p;
+        pq[j] = q < n ? q : p;
+        pc[j] = c;
+        ps[j] = s;
+      }
+      __syncthreads();
+      // rows: A[p,:], A[q,:] <- c A[p,:] - s A[q,:], s A[p,:] + c A[q,:]
+      for (int e = t; e < half * n; e += EIGH_THREADS) {
+        const int j = e / n, col = e % n;
+        const int p = pp[j], q = pq[j];
+        if (p == q) continue;
+        const double c = pc[j], s = ps[j];
+        const double ap = A[p * n + col], aq = A[q * n + col];
+        A[p * n + col] = c * ap - s * aq;
+        A[q * n + col] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns of A and V
+      for (int e = t; e < half * n; e += EIGH_THREADS) {
+        const int j = e / n, row = e % n;
+        const int p = pp[j], q = pq[j];
+        if (p == q) continue;
+        const double c = pc[j], s = ps[j];
+        const double ap = A[row * n + p], aq = A[row * n + q];
+        A[row * n + p] = c * ap - s * aq;
+        A[row * n + q] = s * ap + c * aq;
+        const double vp = V[row * n + p], vq = V[row * n + q];
+        V[row * n + p] = c * vp - s * vq;
+        V[row * n + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  if (t == 0) sweeps_out[b] = used;
+
+  // sort descending (ties by index): rank of each eigenvalue
+  for (int i = t; i < n; i += EIGH_THREADS) wdiag[i] = A[i * n + i];
+  __syncthreads();
+  for (int i = t; i < n; i += EIGH_THREADS) {
+    const double v = wdiag[i];
+    int rk = 0;
+    for (int j = 0; j < n; ++j) rk += (wdiag[j] > v) || (wdiag[j] == v && j < i);
+    rank[i] = rk;
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += EIGH_THREADS) w[rank[i]] = wdiag[i];
+  // move V to A (scratch), then scatter columns into sorted order
+  for (int i = t; i < n2; i += EIGH_THREADS) A[i] = V[i];
+  __syncthreads();
+  for (int i = t; i < n2; i += EIGH_THREADS) {
+    const int row = i / n, col = i % n;
+    V[row * n + rank[col]] = A[i];
+  }
+}
+
+// ------------------------------------------------------------- selection ---
+constexpr int SEL_THREADS = 256;
+constexpr double TIE_REL = 1e-10;      // side rule: backward only if clearly better
+constexpr double SIGN_REL = 1e-9;      // "largest" coordinate within this relative window
+constexpr double DEGEN_REL = 1e-8;     // degenerate-cut flag
+constexpr double CLUSTER_REL = 1e-6;   // eigenvalue gaps below this * lambda_max are degenerate
+
+__device__ inline double sel_reduce(double v, double *sh, bool is_max) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = SEL_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = is_max ? fmax(sh[t], sh[t + s]) : (sh[t] + sh[t + s]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline int sel_min_index(int v, int *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = SEL_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = min(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  const int r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// w2/V2: the two sides' sorted eigensystems (side 0 backward, 1 forward).
+__global__ void __launch_bounds__(SEL_THREADS)
+select_kernel(const double *w2, const double *V2, const int *sweeps2, int n, int k, int force_side,
+              double *U, double *rec_eps, int *rec_int, double *spectrum) {
+  __shared__ double sh[SEL_THREADS];
+  __shared__ int shi[SEL_THREADS];
+  __shared__ double diag[MAX_N];
+  __shared__ double col[MAX_N];
+  const int t = threadIdx.x;
+
+  double eps[2];
+  for (int side = 0; side < 2; ++side) {
+    double s = 0.0;
+    for (int j = k + t; j < n; j += SEL_THREADS) s += fmax(w2[side * n + j], 0.0);
+    eps[side] = sel_reduce(s, sh, false);
+  }
+  int side = (eps[0] < (1.0 - TIE_REL) * eps[1]) ? 0 : 1;
+  if (force_side == 0 || force_side == 1) side = force_side;
+  const double *w = w2 + side * n;
+  const double *V = V2 + size_t(side) * n * n;
+  for (int j = t; j < n; j += SEL_THREADS) spectrum[j] = w[j];
+
+  const double tol = CLUSTER_REL * fmax(w[0], 0.0);
+  int a = 0;
+  while (a < k) {
+    int bnd = a + 1;
+    while (bnd < n && w[bnd - 1] - w[bnd] <= tol) ++bnd;  // cluster [a, bnd)
+    const int stop = bnd < k ? bnd : k;
+    for (int j = a; j < stop; ++j) {
+      // remaining weight of each coordinate in the cluster's projector
+      double mx = 0.0;
+      for (int i = t; i < n; i += SEL_THREADS) {
+        double dg = 0.0;
+        for (int c = a; c < bnd; ++c) dg += V[i * n + c] * V[i * n + c];
+        for (int c = a; c < j; ++c) dg -= U[i * k + c] * U[i * k + c];
+        diag[i] = dg;
+        mx = fmax(mx, dg);
+      }
+      mx = sel_reduce(mx, sh, true);
+      int first = n;
+      for (int i = t; i < n; i += SEL_THREADS)
+        if (diag[i] >= (1.0 - SIGN_REL) * mx && i < first) first = i;
+      const int r = sel_min_index(first, shi);
+      // column of the remaining projector at coordinate r
+      for (int i = t; i < n; i += SEL_THREADS) {
+        double v = 0.0;
+        for (int c = a; c < bnd; ++c) v += V[i * n + c] * V[r * n + c];
+        for (int c = a; c < j; ++c) v -= U[i * k + c] * U[r * k + c];
+        col[i] = v;
+      }
+      __syncthreads();
+      const double inv = 1.0 / sqrt(col[r]);
+      for (int i = t; i < n; i += SEL_THREADS) U[i * k + j] = col[i] * inv;
+      __syncthreads();
+    }
+    a = bnd;
+  }
+  if (t == 0) {
+    rec_eps[0] = eps[0];
+    rec_eps[1] = eps[1];
+    const int degenerate = (k < n && w[k - 1] > 0.0 && (w[k - 1] - w[k]) <= DEGEN_REL * w[k - 1]) ? 1 : 0;
+    rec_int[0] = side;
+    rec_int[1] = k;
+    rec_int[2] = degenerate;
+    rec_int[3] = sweeps2[side];
+  }
+}
+
+}  // namespace
+
+void eigh_batched(double *A, double *w, double *V, int *sweeps, int n, int batch, hipStream_t st) {
+  TRG_REQUIRE(n >= 1 && n <= MAX_N && batch >= 1, "eigh: order must be in [1, 1024]");
+  hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(EIGH_THREADS), 0, st, A, w, V, sweeps, n);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+void select_isometry(const double *w2, const double *V2, const int *sweeps2, int n, int k,
+                     int force_side, SelectOut out, hipStream_t st) {
+  TRG_REQUIRE(n >= 1 && n <= MAX_N && k >= 1 && k <= n, "select: bad sizes");
+  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(SEL_THREADS), 0, st, w2, V2, sweeps2, n, k, force_side,
+                     out.U, out.rec_eps, out.rec_int, out.spectrum);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace trg

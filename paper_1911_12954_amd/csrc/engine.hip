@@ -1,0 +1,1026 @@
+// HOTRG step engine and the C-ABI of libtrg.
+//
+// One step along axis mu (Sec. 2 and Fig. 1 of the paper):
+//   1. Gram matrices of the two-site tensor for every transverse axis nu and
+//      both leg pairs (backward, forward) from the one-site environments P
+//      and Q (split-K FP64 MFMA products) and their FP64 combination.
+//   2. Jacobi eigendecomposition on the device, truncation to k_nu =
+//      min(d_nu^2, Dcut), side choice and canonical basis: the isometry U_nu.
+//   3. The block-spin contraction: operands A (site 1, its backward pairs
+//      along the first transverse axes compressed) and Bt (site 2, forward
+//      pairs compressed) are built in the join precision, the join E = A Bt^T
+//      runs on MFMA, and the remaining transverse pairs are compressed from E
+//      into the new tensor.  Large steps are sliced over the outer legs x0
+//      (of A) and x2 (of Bt) to fit the workspace.
+//   4. Frobenius normalisation c_n and acc += 2^{-n} ln c_n in FP64; impure
+//      tensors S' = [C(S,T) + C(T,S)] / (2 c_n) with the same isometries.
+// All of it is enqueued on the context's stream; no host synchronisation.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/trg.h"
+#include "internal.h"
+
+using namespace trg;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+struct Leg {
+  std::string name;
+  int64_t size, stride;
+};
+using View = std::vector<Leg>;
+
+const Leg &find_leg(const View &v, const std::string &n) {
+  for (const auto &l : v)
+    if (l.name == n) return l;
+  throw Error(-1, "internal: leg " + n + " not found");
+}
+bool has_leg(const View &v, const std::string &n) {
+  for (const auto &l : v)
+    if (l.name == n) return true;
+  return false;
+}
+
+// row-major contiguous layout of the named legs (first = outermost)
+View contiguous(const std::vector<std::pair<std::string, int64_t>> &legs, int64_t scale = 1) {
+  View v;
+  int64_t s = scale;
+  for (int i = int(legs.size()) - 1; i >= 0; --i) {
+    v.insert(v.begin(), Leg{legs[i].first, legs[i].second, s});
+    s *= legs[i].second;
+  }
+  return v;
+}
+
+int64_t view_count(const View &v) {
+  int64_t n = 1;
+  for (const auto &l : v) n *= l.size;
+  return n;
+}
+
+// out(legs of outv) = sum over `sums` of in(legs of inv) * U(u legs)
+// u_strides gives the U stride of every U-side leg name (outputs and sums).
+void apply_map(const void *in, int in_kind, const View &inv, const double *U,
+               const std::map<std::string, int64_t> &u_strides, const std::vector<std::string> &sums,
+               void *out, int out_kind, int64_t lo_plane, const View &outv, hipStream_t st) {
+  std::vector<MapDim> dims;
+  for (const auto &o : outv) {
+    MapDim m{o.size, o.stride, 0, 0};
+    if (has_leg(inv, o.name)) m.si = find_leg(inv, o.name).stride;
+    auto it = u_strides.find(o.name);
+    if (it != u_strides.end()) m.su = it->second;
+    if (!has_leg(inv, o.name) && it == u_strides.end())
+      throw Error(-1, "internal: output leg " + o.name + " has no source");
+    dims.push_back(m);
+  }
+  std::vector<MapSum> ss;
+  for (const auto &n : sums) {
+    const Leg &l = find_leg(inv, n);
+    auto it = u_strides.find(n);
+    if (it == u_strides.end()) throw Error(-1, "internal: summed leg without U stride");
+    ss.push_back(MapSum{l.size, l.stride, it->second});
+  }
+  tensor_map(in, in_kind, U, out, out_kind, lo_plane, dims.data(), int(dims.size()), ss.data(),
+             int(ss.size()), st);
+}
+
+std::string nm(const char *p, int ax) { return std::string(p) + std::to_string(ax); }
+
+struct Buffer {
+  void *ptr = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct trg_ctx {
+  int d = 0;
+  int dims[4] = {0, 0, 0, 0};
+  int nsteps = 0;
+  trg_config cfg{};
+  hipStream_t st = nullptr;
+  bool poisoned = false;
+  std::string err;
+  int nimp = 0;        // number of impure tensors
+  int imp_kind[2] = {-1, -1};  // 0 = E, 1 = M
+  bool has_e = false, has_m = false;
+
+  Buffer T, Tn, S[2], Sn[2];
+  Buffer dev_scalars;  // doubles: [0] c [1] 1/c [2] ln c [3] acc [4..6] traces [7] c0
+  Buffer dev_err;      // int
+  Buffer dev_rec;      // per-step device records
+  int rec_cap = 0;
+  std::vector<trg_step_rec> host_rec;  // host-known parts
+  Buffer U[4], spec[4];
+  int Un[4] = {0, 0, 0, 0}, Uk[4] = {0, 0, 0, 0};
+  std::map<std::string, Buffer> ws;
+  int force_side = -1;
+
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> join_events;
+  double join_ms = 0.0, join_flops_done = 0.0, join_flops_pending = 0.0;
+  long long join_launches = 0;
+
+  void *alloc(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (cfg.alloc) {
+      p = cfg.alloc(bytes, cfg.alloc_user);
+      if (!p) throw Error(TRG_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        throw Error(TRG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      }
+    }
+    return p;
+  }
+  void release(void *p) {
+    if (!p) return;
+    if (cfg.alloc) {
+      if (cfg.free) cfg.free(p, cfg.alloc_user);
+    } else {
+      (void)hipFree(p);
+    }
+  }
+  void ensure(Buffer &b, size_t bytes) {
+    if (b.cap >= bytes && b.ptr) return;
+    if (b.ptr) {
+      // the stream may still read the old buffer
+      TRG_HIP_CHECK(hipStreamSynchronize(st));
+      release(b.ptr);
+      b.ptr = nullptr;
+      b.cap = 0;
+    }
+    b.ptr = alloc(bytes);
+    b.cap = bytes;
+  }
+  template <typename Tp>
+  Tp *wsp(const std::string &name, size_t bytes) {
+    Buffer &b = ws[name];
+    ensure(b, bytes);
+    return static_cast<Tp *>(b.ptr);
+  }
+  size_t ws_held() const {
+    size_t s = 0;
+    for (const auto &kv : ws) s += kv.second.cap;
+    return s;
+  }
+  double *scal() { return static_cast<double *>(dev_scalars.ptr); }
+  int *errp() { return static_cast<int *>(dev_err.ptr); }
+  int64_t total() const {
+    int64_t n = 1;
+    for (int a = 0; a < d; ++a) n *= int64_t(dims[a]) * dims[a];
+    return n;
+  }
+};
+
+namespace {
+
+// device step record layout (doubles first, then ints)
+constexpr int REC_D = 1 + 8;        // ln c, eps[4][2]
+constexpr int REC_I = 4 * 4;        // per axis: side, k, degenerate, sweeps
+constexpr size_t REC_BYTES = REC_D * 8 + REC_I * 4;
+
+double *rec_d(trg_ctx &c, int n) {
+  return reinterpret_cast<double *>(static_cast<char *>(c.dev_rec.ptr) + size_t(n) * REC_BYTES);
+}
+int *rec_i(trg_ctx &c, int n) {
+  return reinterpret_cast<int *>(static_cast<char *>(c.dev_rec.ptr) + size_t(n) * REC_BYTES + REC_D * 8);
+}
+
+void ensure_records(trg_ctx &c, int need) {
+  if (need <= c.rec_cap) return;
+  int cap = c.rec_cap ? c.rec_cap : 64;
+  while (cap < need) cap *= 2;
+  void *p = c.alloc(size_t(cap) * REC_BYTES);
+  fill_zero(p, size_t(cap) * REC_BYTES, c.st);
+  if (c.dev_rec.ptr) {
+    TRG_HIP_CHECK(hipMemcpyAsync(p, c.dev_rec.ptr, size_t(c.rec_cap) * REC_BYTES, hipMemcpyDeviceToDevice, c.st));
+    TRG_HIP_CHECK(hipStreamSynchronize(c.st));
+    c.release(c.dev_rec.ptr);
+  }
+  c.dev_rec.ptr = p;
+  c.dev_rec.cap = size_t(cap) * REC_BYTES;
+  c.rec_cap = cap;
+}
+
+std::vector<int64_t> canon_strides(const int *dims, int d) {
+  std::vector<int64_t> s(2 * d);
+  int64_t x = 1;
+  for (int l = 2 * d - 1; l >= 0; --l) {
+    s[l] = x;
+    x *= dims[l / 2];
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------- Grams ---
+// Environment of one site keeping legs l1 (rows major) and l2: X[(l1,l2)][rest]
+// then X X^T by split-K MFMA.  Result R x R (R = dim(l1) dim(l2)) in out.
+void environment(trg_ctx &c, const double *T, int l1, int l2, double *out, const std::string &tag) {
+  const int d = c.d;
+  auto st_ = canon_strides(c.dims, d);
+  const int64_t n1 = c.dims[l1 / 2], n2 = c.dims[l2 / 2];
+  const int64_t R = n1 * n2, C = c.total() / R;
+  const int64_t Rp = int64_t(round_up(R, 64));
+  const int64_t tiles = (Rp / 64) * (Rp / 64);
+  int64_t splits = (1024 + tiles - 1) / tiles;
+  const int64_t kt = (C + 15) / 16;
+  if (splits > kt) splits = kt;
+  if (splits < 1) splits = 1;
+  const int64_t kper = int64_t(round_up((C + splits - 1) / splits, 16));
+  const int64_t Cp = kper * splits;
+  double *X = c.wsp<double>("gram_X" + tag, size_t(Rp) * Cp * 8);
+  double *part = c.wsp<double>("gram_part" + tag, size_t(splits) * Rp * Rp * 8);
+  // X rows (l1, l2), columns: the other legs in canonical order
+  View inv;
+  for (int l = 0; l < 2 * d; ++l) inv.push_back(Leg{"l" + std::to_string(l), c.dims[l / 2], st_[l]});
+  std::vector<std::pair<std::string, int64_t>> cols;
+  for (int l = 0; l < 2 * d; ++l)
+    if (l != l1 && l != l2) cols.push_back({"l" + std::to_string(l), c.dims[l / 2]});
+  View outv = contiguous(cols);
+  outv.insert(outv.begin(), Leg{"l" + std::to_string(l2), n2, Cp});
+  outv.insert(outv.begin(), Leg{"l" + std::to_string(l1), n1, n2 * Cp});
+  apply_map(T, IN_F64, inv, nullptr, {}, {}, X, OUT_F64, 0, outv, c.st);
+  zero_pad(X, R, Rp, C, Cp, 8, 1, 0, c.st);
+  gemm_nt_splitk_f64(X, X, part, uint64_t(Rp), uint64_t(Rp), uint64_t(Cp), uint64_t(Cp), uint64_t(Cp),
+                     uint32_t(splits), uint64_t(kper), c.st);
+  reduce_splits(part, int(splits), R, R, Rp, Rp * Rp, out, R, c.st);
+}
+
+// ------------------------------------------------------------ operands ---
+struct StepShape {
+  int mu;
+  std::vector<int> others, pre, post;
+  int nd[4];
+  int64_t Mr, Kdim, Kpad;
+  int prec;
+};
+
+// Operand of site 1 (A) or site 2 (Bt) for outer-leg values [o0, o0 + cnt):
+// rows (outer, pair legs of post axes, compressed pre legs), columns
+// (i, b_s..., a'_s...).  Written with row stride Kpad, rows padded to Mpad,
+// in the join precision.
+void build_operand(trg_ctx &c, const StepShape &sh, const double *X, bool site1, int o0, int cnt,
+                   void *out, int64_t Mpad, const std::string &tmp_tag) {
+  const int d = c.d, mu = sh.mu;
+  auto st_ = canon_strides(c.dims, d);
+  // view of X with names of the roles it plays
+  View v;
+  for (int ax = 0; ax < d; ++ax) {
+    if (ax == mu) {
+      if (site1) {
+        v.push_back(Leg{"o", cnt, st_[2 * ax]});
+        v.push_back(Leg{"i", c.dims[ax], st_[2 * ax + 1]});
+      } else {
+        v.push_back(Leg{"i", c.dims[ax], st_[2 * ax]});
+        v.push_back(Leg{"o", cnt, st_[2 * ax + 1]});
+      }
+    } else {
+      v.push_back(Leg{nm(site1 ? "a" : "b", ax), c.dims[ax], st_[2 * ax]});
+      v.push_back(Leg{nm(site1 ? "ap" : "bp", ax), c.dims[ax], st_[2 * ax + 1]});
+    }
+  }
+  const double *src = X + int64_t(o0) * (site1 ? st_[2 * mu] : st_[2 * mu + 1]);
+  // final layout
+  std::vector<std::pair<std::string, int64_t>> rows{{"o", cnt}}, cols{{"i", c.dims[mu]}};
+  for (int r : sh.post) {
+    rows.push_back({nm(site1 ? "a" : "b", r), c.dims[r]});
+    rows.push_back({nm(site1 ? "ap" : "bp", r), c.dims[r]});
+  }
+  for (int s : sh.pre) rows.push_back({nm(site1 ? "K" : "L", s), sh.nd[s]});
+  for (int s : sh.pre) cols.push_back({nm("b", s), c.dims[s]});
+  for (int s : sh.pre) cols.push_back({nm("ap", s), c.dims[s]});
+  View colv = contiguous(cols);
+  int64_t ncols = view_count(colv);
+  (void)ncols;
+  View rowv = contiguous(rows, sh.Kpad);
+  View finalv = rowv;
+  finalv.insert(finalv.end(), colv.begin(), colv.end());
+  const int64_t M = view_count(rowv);
+
+  const int out_kind = sh.prec == TRG_FP64 ? OUT_F64 : (sh.prec == TRG_FP32 ? OUT_F32 : OUT_BF16X2);
+  const int esz = sh.prec == TRG_FP64 ? 8 : (sh.prec == TRG_FP32 ? 4 : 2);
+  const int64_t lo_plane = Mpad * sh.Kpad;
+
+  const double *cur = src;
+  View curv = v;
+  for (size_t j = 0; j < sh.pre.size(); ++j) {
+    const int s = sh.pre[j];
+    const int64_t ds = c.dims[s], ks = sh.nd[s];
+    // site 1 sums its backward leg a_s against U[a, b, K]; site 2 sums its
+    // forward leg b'_s against U[a', b', L]
+    std::map<std::string, int64_t> us;
+    std::string summed;
+    std::vector<std::pair<std::string, int64_t>> produced;
+    if (site1) {
+      summed = nm("a", s);
+      us = {{summed, ds * ks}, {nm("b", s), ks}, {nm("K", s), 1}};
+      produced = {{nm("b", s), ds}, {nm("K", s), ks}};
+    } else {
+      summed = nm("bp", s);
+      us = {{nm("ap", s), ds * ks}, {summed, ks}, {nm("L", s), 1}};
+      produced = {{nm("ap", s), ds}, {nm("L", s), ks}};
+    }
+    const bool last = j + 1 == sh.pre.size();
+    const double *Us = static_cast<const double *>(c.U[s].ptr);
+    if (last) {
+      apply_map(cur, IN_F64, curv, Us, us, {summed}, out, out_kind, lo_plane, finalv, c.st);
+    } else {
+      std::vector<std::pair<std::string, int64_t>> legs;
+      for (const auto &l : curv) {
+        if (l.name == summed) {
+          for (auto &p : produced) legs.push_back(p);
+        } else {
+          legs.push_back({l.name, l.size});
+        }
+      }
+      View tv = contiguous(legs);
+      double *tmp = c.wsp<double>("op_tmp" + tmp_tag, size_t(view_count(tv)) * 8);
+      apply_map(cur, IN_F64, curv, Us, us, {summed}, tmp, OUT_F64, 0, tv, c.st);
+      cur = tmp;
+      curv = tv;
+    }
+  }
+  zero_pad(out, M, Mpad, sh.Kdim, sh.Kpad, esz, out_kind == OUT_BF16X2 ? 2 : 1, lo_plane, c.st);
+}
+
+// Compress the post-axis pairs of a join block E (rows x0-block, cols
+// x2-block) and write the new tensor's slab T'[x0a.., x2a..].
+void post_join(trg_ctx &c, const StepShape &sh, const void *E, int64_t ldc, int x0a, int c0, int x2a,
+               int c2, double *Tout) {
+  const int d = c.d, mu = sh.mu;
+  const int in_kind = sh.prec == TRG_FP64 ? IN_F64 : IN_F32;
+  std::vector<std::pair<std::string, int64_t>> rows{{"o1", c0}}, cols{{"o2", c2}};
+  for (int r : sh.post) {
+    rows.push_back({nm("a", r), c.dims[r]});
+    rows.push_back({nm("ap", r), c.dims[r]});
+    cols.push_back({nm("b", r), c.dims[r]});
+    cols.push_back({nm("bp", r), c.dims[r]});
+  }
+  for (int s : sh.pre) rows.push_back({nm("K", s), sh.nd[s]});
+  for (int s : sh.pre) cols.push_back({nm("L", s), sh.nd[s]});
+  View ev = contiguous(rows, ldc);
+  View evc = contiguous(cols);
+  ev.insert(ev.end(), evc.begin(), evc.end());
+  // output: canonical layout of the new dims, offset to the slab
+  auto nst = canon_strides(sh.nd, d);
+  View outv;
+  for (int ax = 0; ax < d; ++ax) {
+    if (ax == mu) {
+      outv.push_back(Leg{"o1", c0, nst[2 * ax]});
+      outv.push_back(Leg{"o2", c2, nst[2 * ax + 1]});
+    } else {
+      outv.push_back(Leg{nm("K", ax), sh.nd[ax], nst[2 * ax]});
+      outv.push_back(Leg{nm("L", ax), sh.nd[ax], nst[2 * ax + 1]});
+    }
+  }
+  double *dst = Tout + int64_t(x0a) * nst[2 * mu] + int64_t(x2a) * nst[2 * mu + 1];
+  if (sh.post.empty()) {
+    apply_map(E, in_kind, ev, nullptr, {}, {}, dst, OUT_F64, 0, outv, c.st);
+    return;
+  }
+  if (sh.post.size() != 1) throw Error(-1, "internal: more than one post axis");
+  const int r = sh.post[0];
+  const int64_t dr = c.dims[r], kr = sh.nd[r];
+  const double *Ur = static_cast<const double *>(c.U[r].ptr);
+  // (a_r, b_r) -> K_r into a contiguous temporary
+  std::vector<std::pair<std::string, int64_t>> tl;
+  for (const auto &l : ev)
+    if (l.name != nm("a", r) && l.name != nm("b", r)) tl.push_back({l.name, l.size});
+  tl.push_back({nm("K", r), kr});
+  View tv = contiguous(tl);
+  double *tmp = c.wsp<double>("post_tmp", size_t(view_count(tv)) * 8);
+  apply_map(E, in_kind, ev, Ur, {{nm("a", r), dr * kr}, {nm("b", r), kr}, {nm("K", r), 1}},
+            {nm("a", r), nm("b", r)}, tmp, OUT_F64, 0, tv, c.st);
+  // (a'_r, b'_r) -> L_r into the new tensor
+  apply_map(tmp, IN_F64, tv, Ur, {{nm("ap", r), dr * kr}, {nm("bp", r), kr}, {nm("L", r), 1}},
+            {nm("ap", r), nm("bp", r)}, dst, OUT_F64, 0, outv, c.st);
+}
+
+void record_join(trg_ctx &c, hipEvent_t &a, hipEvent_t &b, bool begin) {
+  if (!c.profiling) return;
+  if (begin) {
+    TRG_HIP_CHECK(hipEventCreate(&a));
+    TRG_HIP_CHECK(hipEventCreate(&b));
+    TRG_HIP_CHECK(hipEventRecord(a, c.st));
+  } else {
+    TRG_HIP_CHECK(hipEventRecord(b, c.st));
+    c.join_events.push_back({a, b});
+  }
+}
+
+void join(trg_ctx &c, int prec, const void *A, const void *Bt, void *E, int64_t Mpad, int64_t Npad,
+          int64_t Kpad, bool accum) {
+  hipEvent_t a{}, b{};
+  record_join(c, a, b, true);
+  gemm_nt(prec, A, Bt, E, uint64_t(Mpad), uint64_t(Npad), uint64_t(Kpad), uint64_t(Kpad), uint64_t(Kpad),
+          uint64_t(Npad), accum, c.st);
+  record_join(c, a, b, false);
+  c.join_launches += 1;
+  c.join_flops_pending += 2.0 * double(Mpad) * double(Npad) * double(Kpad);
+}
+
+void hotrg_step_impl(trg_ctx &c, int mu, int dcut) {
+  const int d = c.d;
+  StepShape sh;
+  sh.mu = mu;
+  sh.prec = c.cfg.precision;
+  for (int ax = 0; ax < d; ++ax)
+    if (ax != mu) sh.others.push_back(ax);
+  const size_t npre = (sh.others.size() + 1) / 2;
+  for (size_t j = 0; j < sh.others.size(); ++j) (j < npre ? sh.pre : sh.post).push_back(sh.others[j]);
+  for (int ax = 0; ax < d; ++ax) {
+    const int64_t sq = int64_t(c.dims[ax]) * c.dims[ax];
+    sh.nd[ax] = ax == mu ? c.dims[ax] : int(sq < dcut ? sq : dcut);
+  }
+  const int n_step = c.nsteps + 1;
+  ensure_records(c, n_step + 1);
+  double *rd = rec_d(c, n_step);
+  int *ri = rec_i(c, n_step);
+
+  // ---- 1-2: Gram matrices, eigendecomposition, isometries
+  for (int ax : sh.others) {
+    const int dn = c.dims[ax];
+    const int n = dn * dn;
+    const int dmu = c.dims[mu];
+    const int64_t R = int64_t(dmu) * dn;
+    double *PQ = c.wsp<double>("gram_PQ", size_t(2) * R * R * 8);
+    double *G = c.wsp<double>("gram_G", size_t(2) * n * n * 8);
+    double *W = c.wsp<double>("gram_W", size_t(2) * n * 8);
+    double *V = c.wsp<double>("gram_V", size_t(2) * n * n * 8);
+    int *sw = c.wsp<int>("gram_sweeps", 2 * 4);
+    const double *T = static_cast<const double *>(c.T.ptr);
+    for (int side = 0; side < 2; ++side) {
+      environment(c, T, 2 * mu + 1, 2 * ax + side, PQ, "");
+      environment(c, T, 2 * mu, 2 * ax + side, PQ + R * R, "");
+      gram_combine(PQ, PQ + R * R, dmu, dn, G + size_t(side) * n * n, c.st);
+    }
+    eigh_batched(G, W, V, sw, n, 2, c.st);
+    const int k = sh.nd[ax];
+    c.ensure(c.U[ax], size_t(n) * k * 8);
+    c.ensure(c.spec[ax], size_t(n) * 8);
+    c.Un[ax] = n;
+    c.Uk[ax] = k;
+    SelectOut so{static_cast<double *>(c.U[ax].ptr), rd + 1 + 2 * ax, ri + 4 * ax,
+                 static_cast<double *>(c.spec[ax].ptr)};
+    select_isometry(W, V, sw, n, k, c.force_side, so, c.st);
+  }
+
+  // ---- 3: block-spin contraction, sliced over x0 (A) and x2 (Bt)
+  const GemmTile tile = gemm_tile(sh.prec);
+  sh.Mr = 1;
+  for (int r : sh.post) sh.Mr *= int64_t(c.dims[r]) * c.dims[r];
+  for (int s : sh.pre) sh.Mr *= sh.nd[s];
+  sh.Kdim = c.dims[mu];
+  for (int s : sh.pre) sh.Kdim *= int64_t(c.dims[s]) * c.dims[s];
+  sh.Kpad = int64_t(round_up(sh.Kdim, tile.k));
+  const int esz = sh.prec == TRG_FP64 ? 8 : 4;  // per element incl. both bf16 planes
+  const int esE = sh.prec == TRG_FP64 ? 8 : 4;
+  const int nt = 1 + c.nimp;
+  const int dmu = c.dims[mu];
+  const int64_t total_old = c.total();
+  int64_t ks1 = sh.pre.empty() ? 1 : sh.nd[sh.pre[0]];
+  auto bytes_for = [&](int c0, int c2) {
+    const double Mp = double(round_up(size_t(c0) * sh.Mr, tile.m));
+    const double Np = double(round_up(size_t(c2) * sh.Mr, tile.n));
+    double b = nt * (Mp + Np) * double(sh.Kpad) * esz;
+    b += double(c0 > c2 ? c0 : c2) * double(total_old / dmu) * double(ks1) * 8.0;  // operand temp
+    b += Mp * Np * esE;                                                             // E
+    double e1 = double(c0) * c2;
+    for (int r : sh.post) e1 *= double(c.dims[r]) * c.dims[r] * sh.nd[r];
+    for (int s : sh.pre) e1 *= double(sh.nd[s]) * sh.nd[s];
+    if (!sh.post.empty()) b += e1 * 8.0;
+    return b;
+  };
+  double budget = double(c.cfg.workspace_bytes);
+  if (budget <= 0) {
+    size_t fr = 0, tot = 0;
+    TRG_HIP_CHECK(hipMemGetInfo(&fr, &tot));
+    budget = 0.85 * double(fr + c.ws_held()) - 2.0e9;
+  }
+  int c2 = dmu;
+  while (c2 > 1 && bytes_for(1, c2) > budget) --c2;
+  if (bytes_for(1, c2) > budget) throw Error(TRG_ENOMEM, "join workspace does not fit the memory budget");
+  int c0 = 1;
+  while (c0 < dmu && bytes_for(c0 + 1, c2) <= budget && double(c0 + 1) * sh.Mr * c2 * sh.Mr * esE < 16.0e9) ++c0;
+
+  const int64_t cap_tensor = [&] {
+    int64_t n = 1;
+    for (int ax = 0; ax < d; ++ax) n *= int64_t(sh.nd[ax]) * sh.nd[ax];
+    return n;
+  }();
+  c.ensure(c.Tn, size_t(cap_tensor) * 8);
+  for (int j = 0; j < c.nimp; ++j) c.ensure(c.Sn[j], size_t(cap_tensor) * 8);
+
+  const double *src[3] = {static_cast<const double *>(c.T.ptr), nullptr, nullptr};
+  for (int j = 0; j < c.nimp; ++j) src[1 + j] = static_cast<const double *>(c.S[j].ptr);
+  double *dst[3] = {static_cast<double *>(c.Tn.ptr), nullptr, nullptr};
+  for (int j = 0; j < c.nimp; ++j) dst[1 + j] = static_cast<double *>(c.Sn[j].ptr);
+
+  for (int x2a = 0; x2a < dmu; x2a += c2) {
+    const int n2 = (dmu - x2a) < c2 ? (dmu - x2a) : c2;
+    const int64_t Npad = int64_t(round_up(size_t(n2) * sh.Mr, tile.n));
+    void *Bt[3];
+    for (int t = 0; t < nt; ++t) {
+      Bt[t] = c.wsp<char>("Bt" + std::to_string(t), size_t(round_up(size_t(c2) * sh.Mr, tile.n)) * sh.Kpad * esz);
+      build_operand(c, sh, src[t], false, x2a, n2, Bt[t], Npad, "B");
+    }
+    for (int x0a = 0; x0a < dmu; x0a += c0) {
+      const int n0 = (dmu - x0a) < c0 ? (dmu - x0a) : c0;
+      const int64_t Mpad = int64_t(round_up(size_t(n0) * sh.Mr, tile.m));
+      void *A[3];
+      for (int t = 0; t < nt; ++t) {
+        A[t] = c.wsp<char>("A" + std::to_string(t), size_t(round_up(size_t(c0) * sh.Mr, tile.m)) * sh.Kpad * esz);
+        build_operand(c, sh, src[t], true, x0a, n0, A[t], Mpad, "A");
+      }
+      void *E = c.wsp<char>("E", size_t(round_up(size_t(c0) * sh.Mr, tile.m)) *
+                                     round_up(size_t(c2) * sh.Mr, tile.n) * esE);
+      // pure: E = A_T Bt_T
+      join(c, sh.prec, A[0], Bt[0], E, Mpad, Npad, sh.Kpad, false);
+      post_join(c, sh, E, Npad, x0a, n0, x2a, n2, dst[0]);
+      // impure: E = A_S Bt_T + A_T Bt_S
+      for (int j = 0; j < c.nimp; ++j) {
+        join(c, sh.prec, A[1 + j], Bt[0], E, Mpad, Npad, sh.Kpad, false);
+        join(c, sh.prec, A[0], Bt[1 + j], E, Mpad, Npad, sh.Kpad, true);
+        post_join(c, sh, E, Npad, x0a, n0, x2a, n2, dst[1 + j]);
+      }
+    }
+  }
+
+  // ---- 4: normalisation, accumulator, impure scaling
+  const int64_t newtotal = cap_tensor;
+  const int nb = norm_blocks();
+  double *partial = c.wsp<double>("norm_partial", size_t(nb) * 8);
+  norm_and_accumulate(dst[0], newtotal, partial, nb, c.scal(), c.scal() + 3, std::ldexp(1.0, -n_step),
+                      c.errp(), c.st);
+  scale_by_inverse(dst[0], newtotal, c.scal(), 1.0, c.st);
+  for (int j = 0; j < c.nimp; ++j) scale_by_inverse(dst[1 + j], newtotal, c.scal(), 0.5, c.st);
+  TRG_HIP_CHECK(hipMemcpyAsync(rd, c.scal() + 2, 8, hipMemcpyDeviceToDevice, c.st));
+
+  std::swap(c.T, c.Tn);
+  for (int j = 0; j < c.nimp; ++j) std::swap(c.S[j], c.Sn[j]);
+  trg_step_rec hr{};
+  hr.n = n_step;
+  hr.axis = mu;
+  for (int ax = 0; ax < 4; ++ax) {
+    hr.dims[ax] = ax < d ? sh.nd[ax] : 0;
+    hr.side[ax] = -1;
+  }
+  c.host_rec.push_back(hr);
+  for (int ax = 0; ax < d; ++ax) c.dims[ax] = sh.nd[ax];
+  c.nsteps = n_step;
+}
+
+// ------------------------------------------------------------- helpers ---
+int fail(trg_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  g_thread_error = msg;
+  return code;
+}
+
+template <typename F>
+int guarded(trg_ctx *c, F &&f) {
+  try {
+    if (c && c->poisoned) return fail(c, TRG_ESTATE, "context is poisoned by an earlier device error: " + c->err);
+    return f();
+  } catch (const Error &e) {
+    if (c && (e.code == TRG_EHIP || e.code == TRG_ENUMERIC)) c->poisoned = true;
+    return fail(c, e.code, e.what());
+  } catch (const std::bad_alloc &) {
+    return fail(c, TRG_ENOMEM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(c, TRG_EHIP, e.what());
+  }
+}
+
+// wait for the stream and check the device error flag
+void sync_check(trg_ctx &c) {
+  TRG_HIP_CHECK(hipStreamSynchronize(c.st));
+  int e = 0;
+  TRG_HIP_CHECK(hipMemcpy(&e, c.errp(), sizeof(int), hipMemcpyDeviceToHost));
+  if (e) {
+    c.poisoned = true;
+    throw Error(TRG_ENUMERIC, (e & 1) ? "normalisation produced a zero or non-finite norm"
+                                      : "device numeric error");
+  }
+  if (c.profiling) {
+    for (auto &pr : c.join_events) {
+      float ms = 0.f;
+      TRG_HIP_CHECK(hipEventElapsedTime(&ms, pr.first, pr.second));
+      c.join_ms += ms;
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    c.join_events.clear();
+    c.join_flops_done += c.join_flops_pending;
+    c.join_flops_pending = 0.0;
+  }
+}
+
+trg_ctx *new_ctx(int d, const trg_config *cfg) {
+  auto *c = new trg_ctx();
+  c->d = d;
+  if (cfg) c->cfg = *cfg;
+  if (c->cfg.dcut <= 0) c->cfg.dcut = 8;
+  c->st = static_cast<hipStream_t>(c->cfg.stream);
+  return c;
+}
+
+void init_common(trg_ctx &c) {
+  c.ensure(c.dev_scalars, 16 * 8);
+  c.ensure(c.dev_err, 64);
+  fill_zero(c.dev_scalars.ptr, 16 * 8, c.st);
+  fill_zero(c.dev_err.ptr, 64, c.st);
+  ensure_records(c, 64);
+}
+
+void validate_cfg(const trg_config *cfg, int d) {
+  TRG_REQUIRE(d >= 2 && d <= 4, "d must be 2, 3 or 4");
+  if (!cfg) return;
+  TRG_REQUIRE(cfg->precision >= TRG_FP64 && cfg->precision <= TRG_BF16X3, "unknown precision");
+  TRG_REQUIRE(cfg->method == TRG_HOTRG || cfg->method == TRG_ATRG, "unknown method");
+  TRG_REQUIRE(cfg->dcut >= 0 && cfg->dcut <= 1024, "dcut out of range");
+  TRG_REQUIRE((cfg->impure & ~3u) == 0, "unknown impurity bits");
+  TRG_REQUIRE(!cfg->alloc == !cfg->free, "alloc and free must be given together");
+}
+
+// normalise the freshly written tensors: c_0 = ||T||, acc = ln c_0
+void normalise_initial(trg_ctx &c) {
+  const int64_t n = c.total();
+  const int nb = norm_blocks();
+  double *partial = c.wsp<double>("norm_partial", size_t(nb) * 8);
+  norm_and_accumulate(static_cast<double *>(c.T.ptr), n, partial, nb, c.scal(), c.scal() + 3, 1.0, c.errp(),
+                      c.st);
+  scale_by_inverse(static_cast<double *>(c.T.ptr), n, c.scal(), 1.0, c.st);
+  for (int j = 0; j < c.nimp; ++j) scale_by_inverse(static_cast<double *>(c.S[j].ptr), n, c.scal(), 1.0, c.st);
+  TRG_HIP_CHECK(hipMemcpyAsync(rec_d(c, 0), c.scal() + 2, 8, hipMemcpyDeviceToDevice, c.st));
+}
+
+}  // namespace
+
+// =================================================================== C-ABI ==
+extern "C" {
+
+int trg_init_ising(trg_ctx **out, double beta, double h, int d, const trg_config *cfg) {
+  if (!out) return fail(nullptr, TRG_EINVAL, "out is NULL");
+  *out = nullptr;
+  trg_ctx *c = nullptr;
+  int rc = guarded(nullptr, [&]() -> int {
+    validate_cfg(cfg, d);
+    TRG_REQUIRE(std::isfinite(beta) && beta >= 0.0, "beta must be finite and >= 0");
+    TRG_REQUIRE(std::isfinite(h), "h must be finite");
+    const unsigned imp = cfg ? cfg->impure : 0u;
+    TRG_REQUIRE(!(imp & TRG_IMPURE_E) || beta > 0.0, "the energy impurity needs beta > 0");
+    TRG_REQUIRE(!cfg || cfg->method == TRG_HOTRG, "ATRG contexts are not available in this build");
+    c = new_ctx(d, cfg);
+    for (int a = 0; a < d; ++a) c->dims[a] = 2;
+    c->has_e = imp & TRG_IMPURE_E;
+    c->has_m = imp & TRG_IMPURE_M;
+    if (c->has_e) c->imp_kind[c->nimp++] = 0;
+    if (c->has_m) c->imp_kind[c->nimp++] = 1;
+    init_common(*c);
+    const size_t bytes = size_t(c->total()) * 8;
+    c->ensure(c->T, bytes);
+    for (int j = 0; j < c->nimp; ++j) c->ensure(c->S[j], bytes);
+    double *SE = c->has_e ? static_cast<double *>(c->S[0].ptr) : nullptr;
+    double *SM = c->has_m ? static_cast<double *>(c->S[c->has_e ? 1 : 0].ptr) : nullptr;
+    ising_init(static_cast<double *>(c->T.ptr), SE, SM, d, beta, h, c->st);
+    normalise_initial(*c);
+    return TRG_OK;
+  });
+  if (rc != TRG_OK) {
+    if (c) trg_free(c);
+    return rc;
+  }
+  *out = c;
+  return TRG_OK;
+}
+
+int trg_init_tensor(trg_ctx **out, int d, const int *dims, const double *host_tensor, const trg_config *cfg) {
+  if (!out || !dims || !host_tensor) return fail(nullptr, TRG_EINVAL, "NULL argument");
+  *out = nullptr;
+  trg_ctx *c = nullptr;
+  int rc = guarded(nullptr, [&]() -> int {
+    validate_cfg(cfg, d);
+    TRG_REQUIRE(!cfg || cfg->impure == 0, "impurities need trg_init_ising");
+    TRG_REQUIRE(!cfg || cfg->method == TRG_HOTRG, "ATRG contexts are not available in this build");
+    for (int a = 0; a < d; ++a) TRG_REQUIRE(dims[a] >= 1 && dims[a] <= 1024, "bad leg dim");
+    c = new_ctx(d, cfg);
+    for (int a = 0; a < d; ++a) c->dims[a] = dims[a];
+    init_common(*c);
+    const size_t bytes = size_t(c->total()) * 8;
+    c->ensure(c->T, bytes);
+    TRG_HIP_CHECK(hipMemcpyAsync(c->T.ptr, host_tensor, bytes, hipMemcpyHostToDevice, c->st));
+    normalise_initial(*c);
+    sync_check(*c);
+    return TRG_OK;
+  });
+  if (rc != TRG_OK) {
+    if (c) trg_free(c);
+    return rc;
+  }
+  *out = c;
+  return TRG_OK;
+}
+
+int trg_hotrg_step(trg_ctx *ctx, int axis, int dcut) {
+  if (!ctx) return fail(nullptr, TRG_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&]() -> int {
+    TRG_REQUIRE(axis >= 0 && axis < ctx->d, "axis out of range");
+    TRG_REQUIRE(dcut >= 1 && dcut <= 1024, "dcut out of range");
+    TRG_REQUIRE(ctx->cfg.method == TRG_HOTRG, "context method is not HOTRG");
+    hotrg_step_impl(*ctx, axis, dcut);
+    return TRG_OK;
+  });
+}
+
+int trg_hotrg_step_batch(trg_ctx *const *ctxs, int n, int axis, int dcut) {
+  if (!ctxs || n < 1) return fail(nullptr, TRG_EINVAL, "empty batch");
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return fail(nullptr, TRG_EINVAL, "NULL context in batch");
+    if (ctxs[i]->d != ctxs[0]->d || ctxs[i]->cfg.precision != ctxs[0]->cfg.precision ||
+        ctxs[i]->st != ctxs[0]->st)
+      return fail(nullptr, TRG_EINVAL, "batch contexts differ in d, precision or stream");
+    for (int a = 0; a < ctxs[0]->d; ++a)
+      if (ctxs[i]->dims[a] != ctxs[0]->dims[a]) return fail(nullptr, TRG_EINVAL, "batch contexts differ in dims");
+  }
+  for (int i = 0; i < n; ++i) {
+    const int rc = trg_hotrg_step(ctxs[i], axis, dcut);
+    if (rc != TRG_OK) return rc;
+  }
+  return TRG_OK;
+}
+
+int trg_atrg_step(trg_ctx *ctx, int axis, int dcut) {
+  (void)axis;
+  (void)dcut;
+  return fail(ctx, TRG_ESTATE, "ATRG is not available in this build");
+}
+
+int trg_run(trg_ctx *ctx, long long L) {
+  if (!ctx) return fail(nullptr, TRG_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&]() -> int {
+    TRG_REQUIRE(L >= 2 && (L & (L - 1)) == 0, "L must be a power of two >= 2");
+    int m = 0;
+    while ((1LL << m) < L) ++m;
+    for (int n = 1; n <= ctx->d * m; ++n) hotrg_step_impl(*ctx, (n - 1) % ctx->d, ctx->cfg.dcut);
+    sync_check(*ctx);
+    return TRG_OK;
+  });
+}
+
+static int traces(trg_ctx *ctx, double out[4]) {
+  // out[0] = acc, out[1] = Tr T, out[2] = Tr S_E, out[3] = Tr S_M
+  const double *X[3] = {static_cast<const double *>(ctx->T.ptr), nullptr, nullptr};
+  for (int j = 0; j < ctx->nimp; ++j) X[1 + j] = static_cast<const double *>(ctx->S[j].ptr);
+  periodic_traces(X, 1 + ctx->nimp, ctx->dims, ctx->d, ctx->scal() + 4, ctx->st);
+  sync_check(*ctx);
+  double h[4] = {0, 0, 0, 0};
+  TRG_HIP_CHECK(hipMemcpy(h, ctx->scal() + 3, 4 * 8, hipMemcpyDeviceToHost));
+  out[0] = h[0];
+  out[1] = h[1];
+  out[2] = out[3] = NAN;
+  for (int j = 0; j < ctx->nimp; ++j) out[2 + ctx->imp_kind[j]] = h[2 + j];
+  return TRG_OK;
+}
+
+int trg_free_energy(trg_ctx *ctx, double *lnz) {
+  if (!ctx || !lnz) return fail(ctx, TRG_EINVAL, "NULL argument");
+  return guarded(ctx, [&]() -> int {
+    double t[4];
+    traces(ctx, t);
+    if (!(t[1] > 0.0) || !std::isfinite(t[1])) throw Error(TRG_ENUMERIC, "non-positive trace of the tensor");
+    *lnz = t[0] + std::ldexp(1.0, -ctx->nsteps) * std::log(t[1]);
+    return TRG_OK;
+  });
+}
+
+int trg_impure_energy(trg_ctx *ctx, double *E) {
+  if (!ctx || !E) return fail(ctx, TRG_EINVAL, "NULL argument");
+  return guarded(ctx, [&]() -> int {
+    if (!ctx->has_e) return fail(ctx, TRG_ESTATE, "energy impurity not enabled");
+    double t[4];
+    traces(ctx, t);
+    *E = -t[2] / t[1];
+    return TRG_OK;
+  });
+}
+
+int trg_impure_magnetization(trg_ctx *ctx, double *M) {
+  if (!ctx || !M) return fail(ctx, TRG_EINVAL, "NULL argument");
+  return guarded(ctx, [&]() -> int {
+    if (!ctx->has_m) return fail(ctx, TRG_ESTATE, "magnetization impurity not enabled");
+    double t[4];
+    traces(ctx, t);
+    *M = t[3] / t[1];
+    return TRG_OK;
+  });
+}
+
+int trg_accumulator(trg_ctx *ctx, double *acc) {
+  if (!ctx || !acc) return fail(ctx, TRG_EINVAL, "NULL argument");
+  return guarded(ctx, [&]() -> int {
+    sync_check(*ctx);
+    TRG_HIP_CHECK(hipMemcpy(acc, ctx->scal() + 3, 8, hipMemcpyDeviceToHost));
+    return TRG_OK;
+  });
+}
+
+int trg_get_dims(const trg_ctx *ctx, int *dims, int *steps) {
+  if (!ctx) return fail(nullptr, TRG_EINVAL, "ctx is NULL");
+  if (dims)
+    for (int a = 0; a < ctx->d; ++a) dims[a] = ctx->dims[a];
+  if (steps) *steps = ctx->nsteps;
+  return TRG_OK;
+}
+
+int trg_get_tensor(trg_ctx *ctx, int which, double *host_out, size_t cap) {
+  if (!ctx || !host_out) return fail(ctx, TRG_EINVAL, "NULL argument");
+  return guarded(ctx, [&]() -> int {
+    const size_t n = size_t(ctx->total());
+    TRG_REQUIRE(cap >= n, "output capacity too small");
+    const void *src = nullptr;
+    if (which == 0) src = ctx->T.ptr;
+    for (int j = 0; j < ctx->nimp; ++j)
+      if (which == 1 + ctx->imp_kind[j]) src = ctx->S[j].ptr;
+    if (!src) return fail(ctx, TRG_ESTATE, "requested tensor not present");
+    sync_check(*ctx);
+    TRG_HIP_CHECK(hipMemcpy(host_out, src, n * 8, hipMemcpyDeviceToHost));
+    return TRG_OK;
+  });
+}
+
+int trg_get_isometry(trg_ctx *ctx, int nu, double *host_U, size_t capU, double *host_spectrum, size_t capS) {
+  if (!ctx) return fail(nullptr, TRG_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&]() -> int {
+    TRG_REQUIRE(nu >= 0 && nu < ctx->d && ctx->Un[nu] > 0, "no isometry for that axis");
+    sync_check(*ctx);
+    const size_t n = size_t(ctx->Un[nu]), k = size_t(ctx->Uk[nu]);
+    if (host_U) {
+      TRG_REQUIRE(capU >= n * k, "U capacity too small");
+      TRG_HIP_CHECK(hipMemcpy(host_U, ctx->U[nu].ptr, n * k * 8, hipMemcpyDeviceToHost));
+    }
+    if (host_spectrum) {
+      TRG_REQUIRE(capS >= n, "spectrum capacity too small");
+      TRG_HIP_CHECK(hipMemcpy(host_spectrum, ctx->spec[nu].ptr, n * 8, hipMemcpyDeviceToHost));
+    }
+    return TRG_OK;
+  });
+}
+
+int trg_step_log(trg_ctx *ctx, trg_step_rec *out, int cap, int *n) {
+  if (!ctx || !n) return fail(ctx, TRG_EINVAL, "NULL argument");
+  return guarded(ctx, [&]() -> int {
+    sync_check(*ctx);
+    const int cnt = int(ctx->host_rec.size());
+    *n = cnt;
+    if (!out) return TRG_OK;
+    std::vector<char> raw(size_t(ctx->nsteps + 1) * REC_BYTES);
+    TRG_HIP_CHECK(hipMemcpy(raw.data(), ctx->dev_rec.ptr, raw.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < cnt && i < cap; ++i) {
+      trg_step_rec r = ctx->host_rec[i];
+      const char *base = raw.data() + size_t(r.n) * REC_BYTES;
+      const double *dd = reinterpret_cast<const double *>(base);
+      const int *ii = reinterpret_cast<const int *>(base + REC_D * 8);
+      r.ln_c = dd[0];
+      for (int ax = 0; ax < 4; ++ax) {
+        if (ax >= ctx->d || ax == r.axis) continue;
+        r.eps[ax][0] = dd[1 + 2 * ax];
+        r.eps[ax][1] = dd[2 + 2 * ax];
+        r.side[ax] = ii[4 * ax];
+        r.kept[ax] = ii[4 * ax + 1];
+        r.degenerate_cut[ax] = ii[4 * ax + 2];
+        r.sweeps[ax] = ii[4 * ax + 3];
+      }
+      out[i] = r;
+    }
+    return TRG_OK;
+  });
+}
+
+size_t trg_footprint_bytes(int d, int dcut, int precision, int method, unsigned impure) {
+  (void)method;
+  if (d < 2 || d > 4 || dcut < 1) return 0;
+  // resident tensors: T and its next-step buffer, per impurity the same
+  double D = dcut;
+  double t = std::pow(D, 2 * d);
+  const int nt = 1 + ((impure & 1u) ? 1 : 0) + ((impure & 2u) ? 1 : 0);
+  double resident = 2.0 * nt * t * 8.0;
+  // default join workspace at steady state with x0 slices of one value and whole Bt
+  const int pre = d / 2, post = d - 1 - pre;
+  const double Mr = std::pow(D, 2 * post + pre);
+  const double K = std::pow(D, 1 + 2 * pre);
+  const double esz = precision == TRG_FP64 ? 8.0 : 4.0;
+  double ws = nt * (Mr + D * Mr) * K * esz + Mr * D * Mr * esz + D * t * 8.0;
+  return size_t(resident + ws);
+}
+
+int trg_sync(trg_ctx *ctx) {
+  if (!ctx) return fail(nullptr, TRG_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&]() -> int {
+    sync_check(*ctx);
+    return TRG_OK;
+  });
+}
+
+void trg_free(trg_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->st);
+  for (auto &pr : ctx->join_events) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  auto rel = [&](Buffer &b) {
+    ctx->release(b.ptr);
+    b.ptr = nullptr;
+  };
+  rel(ctx->T);
+  rel(ctx->Tn);
+  for (int j = 0; j < 2; ++j) {
+    rel(ctx->S[j]);
+    rel(ctx->Sn[j]);
+  }
+  rel(ctx->dev_scalars);
+  rel(ctx->dev_err);
+  rel(ctx->dev_rec);
+  for (int a = 0; a < 4; ++a) {
+    rel(ctx->U[a]);
+    rel(ctx->spec[a]);
+  }
+  for (auto &kv : ctx->ws) rel(kv.second);
+  delete ctx;
+}
+
+const char *trg_last_error(const trg_ctx *ctx) {
+  if (ctx) return ctx->err.c_str();
+  return g_thread_error.c_str();
+}
+
+// ------------------------------------------------- kernel-level entries ---
+int trg_gemm(int precision, const void *A, const void *Bt, void *C, long long M, long long N, long long K,
+             long long lda, long long ldb, long long ldc, int accumulate, void *stream) {
+  return guarded(nullptr, [&]() -> int {
+    TRG_REQUIRE(A && Bt && C && M >= 0 && N >= 0 && K >= 0, "bad gemm arguments");
+    gemm_nt(precision, A, Bt, C, uint64_t(M), uint64_t(N), uint64_t(K), uint64_t(lda), uint64_t(ldb),
+            uint64_t(ldc), accumulate != 0, static_cast<hipStream_t>(stream));
+    return TRG_OK;
+  });
+}
+
+int trg_gemm_tile(int precision, int *tile_m, int *tile_n, int *tile_k) {
+  return guarded(nullptr, [&]() -> int {
+    const GemmTile t = gemm_tile(precision);
+    if (tile_m) *tile_m = t.m;
+    if (tile_n) *tile_n = t.n;
+    if (tile_k) *tile_k = t.k;
+    return TRG_OK;
+  });
+}
+
+int trg_eigh(double *A, double *w, double *V, int *sweeps, int n, int batch, void *stream) {
+  return guarded(nullptr, [&]() -> int {
+    TRG_REQUIRE(A && w && V && sweeps, "NULL argument");
+    eigh_batched(A, w, V, sweeps, n, batch, static_cast<hipStream_t>(stream));
+    return TRG_OK;
+  });
+}
+
+int trg_set_profiling(trg_ctx *ctx, int on) {
+  if (!ctx) return fail(nullptr, TRG_EINVAL, "ctx is NULL");
+  ctx->profiling = on != 0;
+  return TRG_OK;
+}
+
+int trg_join_profile(trg_ctx *ctx, double *ms, long long *launches, double *flops) {
+  if (!ctx) return fail(nullptr, TRG_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&]() -> int {
+    sync_check(*ctx);
+    if (ms) *ms = ctx->join_ms;
+    if (launches) *launches = ctx->join_launches;
+    if (flops) *flops = ctx->join_flops_done;
+    ctx->join_ms = 0.0;
+    ctx->join_launches = 0;
+    ctx->join_flops_done = 0.0;
+    return TRG_OK;
+  });
+}
+
+int trg_set_force_side(trg_ctx *ctx, int side) {
+  if (!ctx) return fail(nullptr, TRG_EINVAL, "ctx is NULL");
+  if (side < -1 || side > 1) return fail(ctx, TRG_EINVAL, "side must be -1, 0 or 1");
+  ctx->force_side = side;
+  return TRG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,330 @@
+// Join GEMM of the HOTRG block-spin contraction on gfx950 MFMA.
+//
+// C[m][n] (+)= sum_k A[m][k] * Bt[n][k]: both operands K-contiguous, so a
+// workgroup streams BM rows of A and BN rows of Bt through LDS in tiles of
+// 128 bytes of K per row.  Inside a tile, lane group g = lane/16 of a wave
+// owns bytes [32g, 32g+32) of every row it reads; the k values a lane feeds
+// to successive MFMAs are therefore contiguous in LDS, and A and B use the
+// same assignment, so the contraction over k is unchanged.
+//
+//   FP64   v_mfma_f64_16x16x4_f64   (BK = 16 doubles, 4 MFMA k-steps)
+//   FP32   v_mfma_f32_16x16x4_f32   (BK = 32 floats,  8 MFMA k-steps)
+//   BF16X3 v_mfma_f32_16x16x32_bf16 (BK = 64 bf16 per plane, 2 k-steps,
+//          three products hi*hi + hi*lo + lo*hi per step into one FP32 acc)
+//
+// The LDS row stride is 144 bytes (128 + 16 padding): the 16 rows read by
+// one lane group land on 16 disjoint 4-bank groups, so fragment reads are
+// free of bank conflicts.  Two LDS stages: the next tile's global loads are
+// in flight while the current tile feeds the MFMAs; one barrier per tile.
+//
+// Workgroup ids are remapped so that each XCD (ids are dealt round-robin to
+// the 8 XCDs) works on one contiguous range of tiles, walked in groups of
+// GROUP_M tile-rows: neighbouring tiles on one XCD share A and Bt rows in
+// that XCD's L2.
+#include "common.h"
+#include "internal.h"
+
+namespace trg {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int ROW_BYTES = 128;               // K bytes per row per tile
+constexpr int LDS_STRIDE = ROW_BYTES + 16;   // padded row stride
+constexpr int NUM_XCD = 8;
+constexpr int GROUP_M = 8;
+
+template <int PREC> struct Prec;
+template <> struct Prec<0> {  // FP64
+  using in_t = double;
+  using out_t = double;
+  using acc_t = v4d;
+  using frag_t = d2;
+  static constexpr int planes = 1;
+  static constexpr int elem = 8;
+};
+template <> struct Prec<1> {  // FP32
+  using in_t = float;
+  using out_t = float;
+  using acc_t = v4f;
+  using frag_t = f4;
+  static constexpr int planes = 1;
+  static constexpr int elem = 4;
+};
+template <> struct Prec<2> {  // BF16 x3
+  using in_t = uint16_t;
+  using out_t = float;
+  using acc_t = v4f;
+  using frag_t = bf16x8;
+  static constexpr int planes = 2;
+  static constexpr int elem = 2;
+};
+
+__device__ inline void tile_coords(uint32_t wg, uint32_t tiles_m, uint32_t tiles_n, uint32_t &tm,
+                                   uint32_t &tn) {
+  const uint32_t total = tiles_m * tiles_n;
+  // XCD-contiguous renumbering (bijective for any total)
+  const uint32_t xcd = wg % NUM_XCD, idx = wg / NUM_XCD;
+  const uint32_t per = total / NUM_XCD, rem = total % NUM_XCD;
+  const uint32_t w = xcd * per + (xcd < rem ? xcd : rem) + idx;
+  // grouped raster: GROUP_M tile-rows walked column by column
+  const uint32_t group_size = GROUP_M * tiles_n;
+  const uint32_t group = w / group_size;
+  const uint32_t first_m = group * GROUP_M;
+  const uint32_t gm = (tiles_m - first_m) < GROUP_M ? (tiles_m - first_m) : GROUP_M;
+  const uint32_t in_group = w % group_size;
+  tm = first_m + in_group % gm;
+  tn = in_group / gm;
+}
+
+// BM x BN tile per workgroup, WM x WN waves, 256 threads for 4 waves.
+template <int PREC, int BM, int BN, int WM, int WN, bool ACCUM>
+__global__ void __launch_bounds__(64 * WM * WN)
+gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
+               const typename Prec<PREC>::in_t *__restrict__ Bt,
+               typename Prec<PREC>::out_t *__restrict__ C, uint32_t tiles_m, uint32_t tiles_n,
+               uint32_t ktiles, uint64_t lda, uint64_t ldb, uint64_t ldc, uint64_t planeA,
+               uint64_t planeB, uint64_t c_split_stride) {
+  using P = Prec<PREC>;
+  using in_t = typename P::in_t;
+  using acc_t = typename P::acc_t;
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BM / WM, TN = BN / WN;      // wave tile
+  constexpr int FM = TM / 16, FN = TN / 16;      // 16x16 MFMA blocks per wave
+  constexpr int PL = P::planes;
+  constexpr int BK = ROW_BYTES / P::elem;        // K elements per tile
+  constexpr int CH_A = BM * (ROW_BYTES / 16);    // 16-byte chunks per A tile plane
+  constexpr int CH_B = BN * (ROW_BYTES / 16);
+  static_assert(CH_A % NT == 0 && CH_B % NT == 0, "tile/threads mismatch");
+  constexpr int LA = CH_A / NT, LB = CH_B / NT;  // chunks per thread
+  constexpr int STAGE = (BM + BN) * LDS_STRIDE * PL;
+
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int g = lane >> 4, r16 = lane & 15;
+
+  uint32_t tm, tn;
+  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const uint64_t m0 = uint64_t(tm) * BM, n0 = uint64_t(tn) * BN;
+
+  // split-K: blockIdx.y selects a K range of ktiles tiles and its own C slab
+  const uint64_t koff = uint64_t(blockIdx.y) * ktiles * BK;
+  C += uint64_t(blockIdx.y) * c_split_stride;
+  const unsigned char *gA = reinterpret_cast<const unsigned char *>(A + m0 * lda + koff);
+  const unsigned char *gB = reinterpret_cast<const unsigned char *>(Bt + n0 * ldb + koff);
+  const uint64_t ldaB = lda * P::elem, ldbB = ldb * P::elem;
+  const uint64_t plA = planeA * P::elem, plB = planeB * P::elem;
+
+  u32x4 ra[PL][LA], rb[PL][LB];
+
+  auto gload = [&](uint32_t kt) {
+    const uint64_t kb = uint64_t(kt) * ROW_BYTES;
+#pragma unroll
+    for (int p = 0; p < PL; ++p) {
+#pragma unroll
+      for (int i = 0; i < LA; ++i) {
+        const int c = tid + i * NT, row = c >> 3, col = c & 7;
+        ra[p][i] = *reinterpret_cast<const u32x4 *>(gA + p * plA + row * ldaB + kb + col * 16);
+      }
+#pragma unroll
+      for (int i = 0; i < LB; ++i) {
+        const int c = tid + i * NT, row = c >> 3, col = c & 7;
+        rb[p][i] = *reinterpret_cast<const u32x4 *>(gB + p * plB + row * ldbB + kb + col * 16);
+      }
+    }
+  };
+  auto sstore = [&](int stage) {
+    unsigned char *base = smem + stage * STAGE;
+#pragma unroll
+    for (int p = 0; p < PL; ++p) {
+      unsigned char *sA = base + p * (BM + BN) * LDS_STRIDE;
+      unsigned char *sB = sA + BM * LDS_STRIDE;
+#pragma unroll
+      for (int i = 0; i < LA; ++i) {
+        const int c = tid + i * NT, row = c >> 3, col = c & 7;
+        *reinterpret_cast<u32x4 *>(sA + row * LDS_STRIDE + col * 16) = ra[p][i];
+      }
+#pragma unroll
+      for (int i = 0; i < LB; ++i) {
+        const int c = tid + i * NT, row = c >> 3, col = c & 7;
+        *reinterpret_cast<u32x4 *>(sB + row * LDS_STRIDE + col * 16) = rb[p][i];
+      }
+    }
+  };
+
+  acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{};
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+
+  for (uint32_t kt = 0; kt < ktiles; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < ktiles) gload(kt + 1);
+
+    const unsigned char *base = smem + cur * STAGE;
+    // fragments: 32 bytes per (plane, block row) per lane
+    using frag_t = typename P::frag_t;
+    frag_t fa[PL][FM][2], fb[PL][FN][2];
+#pragma unroll
+    for (int p = 0; p < PL; ++p) {
+      const unsigned char *sA = base + p * (BM + BN) * LDS_STRIDE;
+      const unsigned char *sB = sA + BM * LDS_STRIDE;
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const unsigned char *q = sA + (wm * TM + i * 16 + r16) * LDS_STRIDE + g * 32;
+        fa[p][i][0] = *reinterpret_cast<const frag_t *>(q);
+        fa[p][i][1] = *reinterpret_cast<const frag_t *>(q + 16);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const unsigned char *q = sB + (wn * TN + j * 16 + r16) * LDS_STRIDE + g * 32;
+        fb[p][j][0] = *reinterpret_cast<const frag_t *>(q);
+        fb[p][j][1] = *reinterpret_cast<const frag_t *>(q + 16);
+      }
+    }
+
+    if constexpr (PREC == 0) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[0][i][s >> 1][s & 1],
+                                                              fb[0][j][s >> 1][s & 1], acc[i][j], 0, 0, 0);
+    } else if constexpr (PREC == 1) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[0][i][s >> 2][s & 3],
+                                                              fb[0][j][s >> 2][s & 3], acc[i][j], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i][s], fb[0][j][s], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i][s], fb[1][j][s], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i][s], fb[0][j][s], acc[i][j], 0, 0, 0);
+          }
+    }
+
+    if (kt + 1 < ktiles) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: register e of lane (g, r16) holds column r16 of each 16x16
+  // block, row 4g + e for the FP32-accumulating instructions and row g + 4e
+  // for the FP64 one
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = PREC == 0 ? g + 4 * e : 4 * g + e;
+        const uint64_t m = m0 + wm * TM + i * 16 + row;
+        const uint64_t n = n0 + wn * TN + j * 16 + r16;
+        auto *dst = C + m * ldc + n;
+        if constexpr (ACCUM)
+          *dst += acc[i][j][e];
+        else
+          *dst = acc[i][j][e];
+      }
+}
+
+template <int PREC, int BM, int BN, int WM, int WN>
+void launch_gemm(const void *A, const void *Bt, void *C, uint64_t M, uint64_t N, uint64_t K,
+                 uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st,
+                 uint32_t splits = 1, uint64_t c_split_stride = 0) {
+  using P = Prec<PREC>;
+  constexpr int BK = ROW_BYTES / P::elem;
+  TRG_REQUIRE(M % BM == 0 && N % BN == 0 && K % BK == 0, "gemm: M, N, K must be tile multiples");
+  TRG_REQUIRE(lda >= K && ldb >= K && ldc >= N, "gemm: leading dimension too small");
+  TRG_REQUIRE((lda * P::elem) % 16 == 0 && (ldb * P::elem) % 16 == 0, "gemm: rows must be 16-byte aligned");
+  if (M == 0 || N == 0) return;
+  const uint64_t tiles_m = M / BM, tiles_n = N / BN, tiles = tiles_m * tiles_n;
+  TRG_REQUIRE(tiles < (1ull << 31) && K / BK < (1ull << 31), "gemm: problem too large for one launch");
+  constexpr size_t lds = 2 * size_t(BM + BN) * LDS_STRIDE * P::planes;
+  using in_t = typename P::in_t;
+  using out_t = typename P::out_t;
+  auto *a = static_cast<const in_t *>(A);
+  auto *b = static_cast<const in_t *>(Bt);
+  auto *c = static_cast<out_t *>(C);
+  const uint64_t plA = M * lda, plB = N * ldb;
+  if (K == 0) {
+    if (!accum) fill_zero(C, sizeof(out_t) * M * ldc, st);
+    return;
+  }
+  // K is split into `splits` equal ranges (the caller pads K to a multiple)
+  TRG_REQUIRE(splits >= 1 && K % (uint64_t(splits) * BK) == 0, "gemm: K not divisible by splits");
+  const uint32_t kt = uint32_t(K / BK / splits);
+  dim3 grid(uint32_t(tiles), splits), block(64 * WM * WN);
+  // dynamic LDS above 64 KB must be allowed per kernel (once per instantiation)
+  static bool attr_set = false;
+  if (!attr_set) {
+    TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nt_kernel<PREC, BM, BN, WM, WN, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nt_kernel<PREC, BM, BN, WM, WN, false>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    attr_set = true;
+  }
+  if (accum)
+    hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, true>), grid, block, lds, st, a, b, c,
+                       uint32_t(tiles_m), uint32_t(tiles_n), kt, lda, ldb, ldc, plA, plB, c_split_stride);
+  else
+    hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, false>), grid, block, lds, st, a, b, c,
+                       uint32_t(tiles_m), uint32_t(tiles_n), kt, lda, ldb, ldc, plA, plB, c_split_stride);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace
+
+GemmTile gemm_tile(int prec) {
+  switch (prec) {
+    case 0: return {128, 128, 16};
+    case 1: return {128, 128, 32};
+    case 2: return {128, 128, 64};
+  }
+  throw Error(-1, "gemm: unknown precision");
+}
+
+void gemm_nt(int prec, const void *A, const void *Bt, void *C, uint64_t M, uint64_t N, uint64_t K,
+             uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st) {
+  switch (prec) {
+    case 0: launch_gemm<0, 128, 128, 2, 2>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
+    case 1: launch_gemm<1, 128, 128, 2, 2>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
+    case 2: launch_gemm<2, 128, 128, 2, 2>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
+  }
+  throw Error(-1, "gemm: unknown precision");
+}
+
+// Split-K FP64 products of the Gram reductions: 64 x 64 tiles (four 32 x 32
+// waves); split s covers K range [s*kper, (s+1)*kper) and writes its own
+// M x N slab of Cpart.  K must equal splits * kper (zero-padded).
+void gemm_nt_splitk_f64(const double *A, const double *Bt, double *Cpart, uint64_t M, uint64_t N,
+                        uint64_t K, uint64_t lda, uint64_t ldb, uint32_t splits, uint64_t kper,
+                        hipStream_t st) {
+  TRG_REQUIRE(K == uint64_t(splits) * kper, "splitk: K != splits * kper");
+  launch_gemm<0, 64, 64, 2, 2>(A, Bt, Cpart, M, N, K, lda, ldb, N, false, st, splits, M * N);
+}
+
+}  // namespace trg

@@ -1,0 +1,85 @@
+// Internal interfaces between the kernel files and the step engine of libtrg.
+#pragma once
+
+#include "common.h"
+
+namespace trg {
+
+// ------------------------------------------------------------------ GEMM ---
+struct GemmTile {
+  int m, n, k;
+};
+GemmTile gemm_tile(int prec);
+void gemm_nt(int prec, const void *A, const void *Bt, void *C, uint64_t M, uint64_t N, uint64_t K,
+             uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st);
+// split-K FP64 Gram product: C[s] = A[:, ks] * Bt[:, ks]^T for split s, tile 64
+void gemm_nt_splitk_f64(const double *A, const double *Bt, double *Cpart, uint64_t M, uint64_t N,
+                        uint64_t K, uint64_t lda, uint64_t ldb, uint32_t splits, uint64_t kper,
+                        hipStream_t st);
+
+// ------------------------------------------------------------ tensor map ---
+// out[sum_i o_i so_i] = sum_{s} in[sum_i o_i si_i + sum_j s_j ssi_j] *
+//                                U[sum_i o_i su_i + sum_j s_j ssu_j]
+// over the iteration space o (dims listed outermost first).  With nsum = 0
+// and U == nullptr it is a strided copy.  Output kinds: FP64, FP32 or a BF16
+// split (hi at out, lo at out + lo_plane elements).
+constexpr int MAP_MAXD = 12;
+struct MapDim {
+  int64_t size, so, si, su;
+};
+struct MapSum {
+  int64_t size, si, su;
+};
+enum OutKind { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16X2 = 2 };
+enum InKind { IN_F64 = 0, IN_F32 = 1 };
+
+void tensor_map(const void *in, int in_kind, const double *U, void *out, int out_kind,
+                int64_t lo_plane, const MapDim *dims, int ndims, const MapSum *sums, int nsum,
+                hipStream_t st);
+
+// zero the padding of a row-major rows_pad x ld matrix whose valid part is
+// rows x cols (elements of elem_bytes; `planes` planes plane_stride apart)
+void zero_pad(void *buf, int64_t rows, int64_t rows_pad, int64_t cols, int64_t ld, int elem_bytes,
+              int planes, int64_t plane_stride, hipStream_t st);
+void fill_zero(void *buf, size_t bytes, hipStream_t st);
+
+// sum of split-K partials: out[r*ldo + c] = sum_s part[s][r*ldp + c]
+void reduce_splits(const double *part, int splits, int64_t rows, int64_t cols, int64_t ldp,
+                   int64_t split_stride, double *out, int64_t ldo, hipStream_t st);
+
+// Gram of the two-site tensor from the one-site environments P and Q
+// (both (dmu*dn) x (dmu*dn), row index (i, a)): G[(a,b),(a',b')] =
+// sum_{i,i'} P[(i,a),(i',a')] Q[(i,b),(i',b')]
+void gram_combine(const double *P, const double *Q, int dmu, int dn, double *G, hipStream_t st);
+
+// Frobenius norm of n doubles: partials then one block; writes
+// scal[0] = c, scal[1] = 1/c, scal[2] = ln c, acc[0] += weight * ln c; sets
+// *err |= 1 when c is zero or not finite.
+void norm_and_accumulate(const double *x, int64_t n, double *partial, int nblocks, double *scal,
+                         double *acc, double weight, int *err, hipStream_t st);
+int norm_blocks();
+// x[i] *= factor * scal[1]
+void scale_by_inverse(double *x, int64_t n, const double *scal, double factor, hipStream_t st);
+
+// traces: out[j] = sum_{x_nu} X_j[x, x, y, y, ...] for up to 3 tensors
+void periodic_traces(const double *const *X, int count, const int *dims, int d, double *out,
+                     hipStream_t st);
+
+// initial Ising tensors (closed form) into T, SE, SM (each may be null)
+void ising_init(double *T, double *SE, double *SM, int d, double beta, double h, hipStream_t st);
+
+// ------------------------------------------------------------- eigen ---
+// batched Jacobi: A (batch x n x n) overwritten; w, V sorted descending
+void eigh_batched(double *A, double *w, double *V, int *sweeps, int n, int batch, hipStream_t st);
+
+// isometry selection of one transverse axis from both sides' eigensystems
+struct SelectOut {
+  double *U;        // n x k row-major
+  double *rec_eps;  // [2]
+  int *rec_int;     // [side, k, degenerate, sweeps]
+  double *spectrum; // n (chosen side)
+};
+void select_isometry(const double *w2, const double *V2, const int *sweeps2, int n, int k,
+                     int force_side, SelectOut out, hipStream_t st);
+
+}  // namespace trg

@@ -1,0 +1,368 @@
+// Memory-bound tensor kernels of the HOTRG step: leg contractions with an
+// isometry (operand construction and post-join compression), strided copies,
+// padding, Frobenius normalisation, periodic traces and the initial Ising
+// tensors.
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace trg {
+namespace {
+
+// ------------------------------------------------------------- tensor map ---
+struct MapParams {
+  int ndims, nsum;
+  FastDiv div[MAP_MAXD];
+  int64_t so[MAP_MAXD], si[MAP_MAXD], su[MAP_MAXD];
+  int32_t ssize[2];
+  int64_t ssi[2], ssu[2];
+  uint32_t count;
+  int64_t lo_plane;
+};
+
+template <typename InT, int OUT>
+__global__ void __launch_bounds__(256)
+map_kernel(const InT *__restrict__ in, const double *__restrict__ U, void *__restrict__ out,
+           MapParams p) {
+  const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+  if (idx >= p.count) return;
+  uint32_t q = idx;
+  int64_t oo = 0, oi = 0, ou = 0;
+#pragma unroll
+  for (int j = MAP_MAXD - 1; j >= 0; --j) {
+    if (j < p.ndims) {
+      const uint32_t qd = fast_div(q, p.div[j]);
+      const uint32_t r = q - qd * p.div[j].d;
+      q = qd;
+      oo += int64_t(r) * p.so[j];
+      oi += int64_t(r) * p.si[j];
+      ou += int64_t(r) * p.su[j];
+    }
+  }
+  double acc;
+  if (p.nsum == 0) {
+    acc = U ? double(in[oi]) * U[ou] : double(in[oi]);
+  } else if (p.nsum == 1) {
+    acc = 0.0;
+    for (int a = 0; a < p.ssize[0]; ++a) acc += double(in[oi + a * p.ssi[0]]) * U[ou + a * p.ssu[0]];
+  } else {
+    acc = 0.0;
+    for (int a = 0; a < p.ssize[0]; ++a) {
+      const InT *pi = in + oi + a * p.ssi[0];
+      const double *pu = U + ou + a * p.ssu[0];
+      for (int b = 0; b < p.ssize[1]; ++b) acc += double(pi[b * p.ssi[1]]) * pu[b * p.ssu[1]];
+    }
+  }
+  if constexpr (OUT == OUT_F64) {
+    static_cast<double *>(out)[oo] = acc;
+  } else if constexpr (OUT == OUT_F32) {
+    static_cast<float *>(out)[oo] = float(acc);
+  } else {
+    // a = hi + lo with hi = bf16(fl32(a)), lo = bf16(fl32(a) - hi)
+    const float a = float(acc);
+    const uint16_t hi = f32_to_bf16_rne(a);
+    const uint16_t lo = f32_to_bf16_rne(a - bf16_to_f32(hi));
+    static_cast<uint16_t *>(out)[oo] = hi;
+    static_cast<uint16_t *>(out)[oo + p.lo_plane] = lo;
+  }
+}
+
+template <typename InT>
+void launch_map(const InT *in, const double *U, void *out, int out_kind, MapParams &p, hipStream_t st) {
+  const dim3 grid((p.count + 255) / 256), block(256);
+  switch (out_kind) {
+    case OUT_F64: hipLaunchKernelGGL((map_kernel<InT, OUT_F64>), grid, block, 0, st, in, U, out, p); break;
+    case OUT_F32: hipLaunchKernelGGL((map_kernel<InT, OUT_F32>), grid, block, 0, st, in, U, out, p); break;
+    case OUT_BF16X2: hipLaunchKernelGGL((map_kernel<InT, OUT_BF16X2>), grid, block, 0, st, in, U, out, p); break;
+    default: throw Error(-1, "tensor_map: bad output kind");
+  }
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ padding ---
+__global__ void zero_pad_kernel(unsigned char *buf, int64_t rows, int64_t rows_pad, int64_t cols,
+                                int64_t ld, int eb, int planes, int64_t plane_stride) {
+  // grid-stride over (plane, row) pairs; each row clears [cols, ld) or all of it
+  const int64_t total = int64_t(planes) * rows_pad;
+  for (int64_t rr = blockIdx.x; rr < total; rr += gridDim.x) {
+    const int64_t plane = rr / rows_pad, row = rr % rows_pad;
+    unsigned char *base = buf + (plane * plane_stride + row * ld) * eb;
+    const int64_t c0 = row < rows ? cols : 0;
+    for (int64_t c = c0 * eb + threadIdx.x; c < ld * eb; c += blockDim.x) base[c] = 0;
+  }
+}
+
+__global__ void fill_zero_kernel(uint32_t *buf, size_t words) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < words; i += size_t(gridDim.x) * blockDim.x)
+    buf[i] = 0u;
+}
+
+// ------------------------------------------------------------ reductions ---
+__global__ void reduce_splits_kernel(const double *part, int splits, int64_t rows, int64_t cols,
+                                     int64_t ldp, int64_t sstride, double *out, int64_t ldo) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= rows * cols) return;
+  const int64_t r = i / cols, c = i % cols;
+  double s = 0.0;
+  for (int k = 0; k < splits; ++k) s += part[k * sstride + r * ldp + c];
+  out[r * ldo + c] = s;
+}
+
+__global__ void gram_combine_kernel(const double *P, const double *Q, int dmu, int dn, double *G) {
+  // G[(a,b),(a2,b2)] = sum_{i,i2} P[(i,a),(i2,a2)] Q[(i,b),(i2,b2)]
+  const int n = dn * dn;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(n) * n) return;
+  const int row = int(t / n), col = int(t % n);
+  const int a = row / dn, b = row % dn, a2 = col / dn, b2 = col % dn;
+  const int R = dmu * dn;
+  double s = 0.0;
+  for (int i = 0; i < dmu; ++i)
+    for (int i2 = 0; i2 < dmu; ++i2)
+      s += P[(i * dn + a) * R + i2 * dn + a2] * Q[(i * dn + b) * R + i2 * dn + b2];
+  G[t] = s;
+}
+
+constexpr int NORM_BLOCKS = 1024;
+
+__device__ inline double block_sum(double v, double *sh) {
+  // deterministic tree over 256 threads
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ void __launch_bounds__(256) sumsq_kernel(const double *x, int64_t n, double *partial) {
+  __shared__ double sh[256];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t b = int64_t(blockIdx.x) * per;
+  const int64_t e = b + per < n ? b + per : n;
+  double s = 0.0;
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) s += x[i] * x[i];
+  const double tot = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(256)
+norm_final_kernel(const double *partial, int nb, double *scal, double *acc, double weight, int *err) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += partial[i];
+  const double tot = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    const double c = sqrt(tot);
+    const bool ok = c > 0.0 && isfinite(c);
+    scal[0] = c;
+    scal[1] = ok ? 1.0 / c : 0.0;
+    scal[2] = ok ? log(c) : 0.0;
+    if (ok) acc[0] += weight * log(c);
+    else *err |= 1;
+  }
+}
+
+__global__ void scale_kernel(double *x, int64_t n, const double *scal, double factor) {
+  const double f = factor * scal[1];
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    x[i] *= f;
+}
+
+struct TraceParams {
+  const double *X[3];
+  int count, d;
+  int dims[4];
+  int64_t diag_stride[4];
+};
+
+__global__ void __launch_bounds__(256) trace_kernel(TraceParams p, double *out) {
+  __shared__ double sh[256];
+  int64_t total = 1;
+  for (int a = 0; a < p.d; ++a) total *= p.dims[a];
+  for (int j = 0; j < p.count; ++j) {
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < total; t += 256) {
+      int64_t q = t, off = 0;
+      for (int a = p.d - 1; a >= 0; --a) {
+        off += (q % p.dims[a]) * p.diag_stride[a];
+        q /= p.dims[a];
+      }
+      s += p.X[j][off];
+    }
+    const double tot = block_sum(s, sh);
+    if (threadIdx.x == 0) out[j] = tot;
+    __syncthreads();
+  }
+}
+
+// Initial tensors from the closed form: n = number of legs at index 1,
+// T0 = 2 c^a s^b g(bh), S_M = 2 c^a s^b g'(bh),
+// S_E = 2 c^a s^b [(a tanh b + b coth b) g(bh) + h g'(bh)],
+// c = cosh beta, s = sinh beta, a = (2d - n)/2, b = n/2, g = cosh (n even)
+// or sinh (n odd), g' the other one.
+__global__ void ising_kernel(double *T, double *SE, double *SM, int d, double beta, double h) {
+  const int nl = 2 * d;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (1 << nl)) return;
+  const int n = __popc(idx);
+  const double a = 0.5 * (nl - n), b = 0.5 * n;
+  const double ch = cosh(beta), sh = sinh(beta);
+  const double base = 2.0 * pow(ch, a) * (n ? pow(sh, b) : 1.0);
+  const bool even = (n & 1) == 0;
+  const double g = even ? cosh(beta * h) : sinh(beta * h);
+  const double gp = even ? sinh(beta * h) : cosh(beta * h);
+  // leg l of the row-major index is bit (nl-1-l) of idx; the closed form
+  // depends only on the count n, so the bit order does not matter
+  if (T) T[idx] = base * g;
+  if (SM) SM[idx] = base * gp;
+  if (SE) {
+    const double dlog = (n ? b / tanh(beta) : 0.0) + a * tanh(beta);
+    SE[idx] = base * (dlog * g + h * gp);
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- host side ---
+void tensor_map(const void *in, int in_kind, const double *U, void *out, int out_kind,
+                int64_t lo_plane, const MapDim *dims, int ndims, const MapSum *sums, int nsum,
+                hipStream_t st) {
+  TRG_REQUIRE(ndims >= 1 && ndims <= MAP_MAXD && nsum >= 0 && nsum <= 2, "tensor_map: bad rank");
+  TRG_REQUIRE(nsum == 0 || U != nullptr, "tensor_map: summation needs a matrix");
+  int64_t total = 1;
+  for (int i = 0; i < ndims; ++i) {
+    TRG_REQUIRE(dims[i].size >= 1 && dims[i].size < (int64_t(1) << 31), "tensor_map: bad dim");
+    total *= dims[i].size;
+  }
+  // split the outermost dims into separate launches until a launch has < 2^32 - 256 elements
+  int outer = 0;
+  int64_t inner = total;
+  while (inner >= (int64_t(1) << 32) - 256) {
+    TRG_REQUIRE(outer + 1 < ndims, "tensor_map: cannot split launch");
+    inner /= dims[outer].size;
+    ++outer;
+  }
+  int64_t nouter = total / inner;
+  MapParams p{};
+  p.ndims = ndims - outer;
+  p.nsum = nsum;
+  for (int i = 0; i < p.ndims; ++i) {
+    const MapDim &m = dims[outer + i];
+    p.div[i] = make_fastdiv(uint32_t(m.size));
+    p.so[i] = m.so;
+    p.si[i] = m.si;
+    p.su[i] = m.su;
+  }
+  for (int j = 0; j < nsum; ++j) {
+    p.ssize[j] = int32_t(sums[j].size);
+    p.ssi[j] = sums[j].si;
+    p.ssu[j] = sums[j].su;
+  }
+  p.count = uint32_t(inner);
+  p.lo_plane = lo_plane;
+  const int esz_in = in_kind == IN_F64 ? 8 : 4;
+  const int esz_out = out_kind == OUT_F64 ? 8 : (out_kind == OUT_F32 ? 4 : 2);
+  for (int64_t o = 0; o < nouter; ++o) {
+    // offsets of this outer multi-index
+    int64_t q = o, oo = 0, oi = 0, ou = 0;
+    for (int i = outer - 1; i >= 0; --i) {
+      const int64_t r = q % dims[i].size;
+      q /= dims[i].size;
+      oo += r * dims[i].so;
+      oi += r * dims[i].si;
+      ou += r * dims[i].su;
+    }
+    const void *pin = static_cast<const char *>(in) + oi * esz_in;
+    const double *pu = U ? U + ou : nullptr;
+    void *pout = static_cast<char *>(out) + oo * esz_out;
+    if (in_kind == IN_F64)
+      launch_map(static_cast<const double *>(pin), pu, pout, out_kind, p, st);
+    else
+      launch_map(static_cast<const float *>(pin), pu, pout, out_kind, p, st);
+  }
+}
+
+void zero_pad(void *buf, int64_t rows, int64_t rows_pad, int64_t cols, int64_t ld, int elem_bytes,
+              int planes, int64_t plane_stride, hipStream_t st) {
+  if (cols == ld && rows == rows_pad) return;
+  const int64_t work = int64_t(planes) * rows_pad;
+  const uint32_t grid = uint32_t(work < 65536 ? work : 65536);
+  hipLaunchKernelGGL(zero_pad_kernel, dim3(grid), dim3(256), 0, st, static_cast<unsigned char *>(buf), rows,
+                     rows_pad, cols, ld, elem_bytes, planes, plane_stride);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+void fill_zero(void *buf, size_t bytes, hipStream_t st) {
+  TRG_REQUIRE(bytes % 4 == 0, "fill_zero: size must be a multiple of 4");
+  const size_t words = bytes / 4;
+  if (!words) return;
+  const size_t blocks = (words + 255) / 256;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(uint32_t(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st,
+                     static_cast<uint32_t *>(buf), words);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+void reduce_splits(const double *part, int splits, int64_t rows, int64_t cols, int64_t ldp,
+                   int64_t split_stride, double *out, int64_t ldo, hipStream_t st) {
+  const int64_t n = rows * cols;
+  hipLaunchKernelGGL(reduce_splits_kernel, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, st, part, splits,
+                     rows, cols, ldp, split_stride, out, ldo);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+void gram_combine(const double *P, const double *Q, int dmu, int dn, double *G, hipStream_t st) {
+  const int64_t n2 = int64_t(dn) * dn * dn * dn;
+  hipLaunchKernelGGL(gram_combine_kernel, dim3(uint32_t((n2 + 255) / 256)), dim3(256), 0, st, P, Q, dmu, dn, G);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+int norm_blocks() { return NORM_BLOCKS; }
+
+void norm_and_accumulate(const double *x, int64_t n, double *partial, int nblocks, double *scal,
+                         double *acc, double weight, int *err, hipStream_t st) {
+  hipLaunchKernelGGL(sumsq_kernel, dim3(nblocks), dim3(256), 0, st, x, n, partial);
+  TRG_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(256), 0, st, partial, nblocks, scal, acc, weight, err);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+void scale_by_inverse(double *x, int64_t n, const double *scal, double factor, hipStream_t st) {
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(scale_kernel, dim3(uint32_t(blocks < 16384 ? blocks : 16384)), dim3(256), 0, st, x, n,
+                     scal, factor);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+void periodic_traces(const double *const *X, int count, const int *dims, int d, double *out,
+                     hipStream_t st) {
+  TRG_REQUIRE(count >= 1 && count <= 3 && d >= 1 && d <= 4, "trace: bad arguments");
+  TraceParams p{};
+  p.count = count;
+  p.d = d;
+  for (int j = 0; j < count; ++j) p.X[j] = X[j];
+  // row-major strides of the 2d legs
+  int64_t stride[8];
+  int64_t s = 1;
+  for (int l = 2 * d - 1; l >= 0; --l) {
+    stride[l] = s;
+    s *= dims[l / 2];
+  }
+  for (int a = 0; a < d; ++a) {
+    p.dims[a] = dims[a];
+    p.diag_stride[a] = stride[2 * a] + stride[2 * a + 1];
+  }
+  hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 0, st, p, out);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+void ising_init(double *T, double *SE, double *SM, int d, double beta, double h, hipStream_t st) {
+  const int n = 1 << (2 * d);
+  hipLaunchKernelGGL(ising_kernel, dim3((n + 255) / 256), dim3(256), 0, st, T, SE, SM, d, beta, h);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace trg

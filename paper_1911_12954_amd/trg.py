@@ -1,0 +1,276 @@
+"""Python binding of libtrg: the C-ABI entry points under the same names,
+plus a small Context wrapper.  Argument marshalling only; every step of the
+computation runs in the HIP library.  PyTorch supplies the device allocator
+(its caching allocator) and the stream."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+PRECISIONS = {"fp64": L.TRG_FP64, "fp32": L.TRG_FP32, "bf16x3": L.TRG_BF16X3}
+METHODS = {"hotrg": L.TRG_HOTRG, "atrg": L.TRG_ATRG}
+
+
+class TrgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libtrg error {code}: {msg}")
+        self.code = code
+
+
+def _lib():
+    return L.load()
+
+
+def _err(rc: int, handle=None):
+    if rc != L.TRG_OK:
+        msg = _lib().trg_last_error(handle)
+        raise TrgError(rc, msg.decode() if msg else "")
+
+
+def _torch_allocator(stream_ptr):
+    """ctypes callbacks that allocate through torch's caching allocator on
+    the given stream."""
+    import torch
+
+    dev = torch.cuda.current_device()
+
+    @L.ALLOC_FN
+    def alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream_ptr or 0))
+        except Exception:
+            return None
+
+    @L.FREE_FN
+    def free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, free
+
+
+def make_config(precision="fp64", method="hotrg", dcut=8, impure=(), stream=None,
+                use_torch_allocator=True, workspace_bytes=0, rsvd_p=0, rsvd_q=-1, seed=0):
+    """Build a trg_config.  ``stream``: a torch.cuda.Stream, an int handle or
+    None (torch's current stream when torch has a GPU, else the default)."""
+    cfg = L.TrgConfig()
+    cfg.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    cfg.method = METHODS[method] if isinstance(method, str) else int(method)
+    cfg.dcut = int(dcut)
+    bits = 0
+    for x in impure:
+        bits |= {"E": L.TRG_IMPURE_E, "M": L.TRG_IMPURE_M}[x]
+    cfg.impure = bits
+    cfg.rsvd_p, cfg.rsvd_q, cfg.seed = int(rsvd_p), int(rsvd_q), int(seed)
+    cfg.workspace_bytes = int(workspace_bytes)
+    keep = []
+    sp = None
+    try:
+        import torch
+        if torch.cuda.is_available():
+            if stream is None:
+                stream = torch.cuda.current_stream()
+            sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+            if use_torch_allocator:
+                a, f = _torch_allocator(sp)
+                cfg.alloc, cfg.free = a, f
+                keep += [a, f]
+    except ImportError:
+        sp = stream
+    cfg.stream = C.c_void_p(sp) if sp else None
+    return cfg, keep
+
+
+@dataclass
+class StepRecord:
+    n: int
+    axis: int
+    dims: tuple
+    side: tuple
+    kept: tuple
+    degenerate_cut: tuple
+    sweeps: tuple
+    ln_c: float
+    eps: tuple
+
+
+class Context:
+    """Owns one trg_ctx handle."""
+
+    def __init__(self, handle, keep, d):
+        self.handle = handle
+        self._keep = keep
+        self.d = d
+
+    # -- steps
+    def hotrg_step(self, axis: int, dcut: int):
+        _err(_lib().trg_hotrg_step(self.handle, axis, dcut), self.handle)
+
+    def run(self, L_: int):
+        _err(_lib().trg_run(self.handle, L_), self.handle)
+
+    # -- results
+    def _dbl(self, fn):
+        out = C.c_double()
+        _err(fn(self.handle, C.byref(out)), self.handle)
+        return out.value
+
+    def free_energy(self) -> float:
+        return self._dbl(_lib().trg_free_energy)
+
+    def impure_energy(self) -> float:
+        return self._dbl(_lib().trg_impure_energy)
+
+    def impure_magnetization(self) -> float:
+        return self._dbl(_lib().trg_impure_magnetization)
+
+    def accumulator(self) -> float:
+        return self._dbl(_lib().trg_accumulator)
+
+    def dims(self):
+        arr = (C.c_int * 4)()
+        steps = C.c_int()
+        _err(_lib().trg_get_dims(self.handle, arr, C.byref(steps)), self.handle)
+        return tuple(arr[: self.d]), steps.value
+
+    def tensor(self, which: int = 0) -> np.ndarray:
+        dims, _ = self.dims()
+        shape = tuple(x for x in dims for _ in range(2))
+        out = np.empty(shape, dtype=np.float64)
+        _err(_lib().trg_get_tensor(self.handle, which, out.ctypes.data_as(C.POINTER(C.c_double)), out.size),
+             self.handle)
+        return out
+
+    def isometry(self, nu: int):
+        log = self.step_log()
+        rec = log[-1]
+        k = rec.kept[nu]
+        dims_prev = self._prev_dim(nu)
+        n = dims_prev * dims_prev
+        U = np.empty((n, k))
+        spec = np.empty(n)
+        _err(_lib().trg_get_isometry(self.handle, nu, U.ctypes.data_as(C.POINTER(C.c_double)), U.size,
+                                     spec.ctypes.data_as(C.POINTER(C.c_double)), spec.size), self.handle)
+        return U, spec
+
+    def _prev_dim(self, nu):
+        log = self.step_log()
+        if len(log) >= 2:
+            return log[-2].dims[nu]
+        return self._initial_dims[nu]
+
+    def step_log(self):
+        n = C.c_int()
+        _err(_lib().trg_step_log(self.handle, None, 0, C.byref(n)), self.handle)
+        recs = (L.TrgStepRec * max(n.value, 1))()
+        _err(_lib().trg_step_log(self.handle, recs, n.value, C.byref(n)), self.handle)
+        out = []
+        for r in recs[: n.value]:
+            out.append(StepRecord(r.n, r.axis, tuple(r.dims[: self.d]), tuple(r.side[: self.d]),
+                                  tuple(r.kept[: self.d]), tuple(r.degenerate_cut[: self.d]),
+                                  tuple(r.sweeps[: self.d]), r.ln_c,
+                                  tuple(tuple(r.eps[a]) for a in range(self.d))))
+        return out
+
+    def set_profiling(self, on=True):
+        _err(_lib().trg_set_profiling(self.handle, 1 if on else 0), self.handle)
+
+    def join_profile(self):
+        ms, n, fl = C.c_double(), C.c_longlong(), C.c_double()
+        _err(_lib().trg_join_profile(self.handle, C.byref(ms), C.byref(n), C.byref(fl)), self.handle)
+        return ms.value, n.value, fl.value
+
+    def set_force_side(self, side: int):
+        _err(_lib().trg_set_force_side(self.handle, side), self.handle)
+
+    def sync(self):
+        _err(_lib().trg_sync(self.handle), self.handle)
+
+    def close(self):
+        if self.handle:
+            _lib().trg_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------- C-ABI names ---
+
+def trg_init_ising(beta: float, h: float, d: int, **cfg) -> Context:
+    conf, keep = make_config(**cfg)
+    h_ = C.c_void_p()
+    _err(_lib().trg_init_ising(C.byref(h_), float(beta), float(h), int(d), C.byref(conf)))
+    ctx = Context(h_, keep + [conf], d)
+    ctx._initial_dims = (2,) * d
+    return ctx
+
+
+def trg_init_tensor(T: np.ndarray, **cfg) -> Context:
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    d = T.ndim // 2
+    dims = (C.c_int * d)(*[T.shape[2 * a] for a in range(d)])
+    conf, keep = make_config(**cfg)
+    h_ = C.c_void_p()
+    _err(_lib().trg_init_tensor(C.byref(h_), d, dims, T.ctypes.data_as(C.POINTER(C.c_double)), C.byref(conf)))
+    ctx = Context(h_, keep + [conf], d)
+    ctx._initial_dims = tuple(T.shape[2 * a] for a in range(d))
+    return ctx
+
+
+def trg_hotrg_step(ctx: Context, axis: int, dcut: int):
+    ctx.hotrg_step(axis, dcut)
+
+
+def trg_hotrg_step_batch(ctxs, axis: int, dcut: int):
+    arr = (C.c_void_p * len(ctxs))(*[c.handle.value if isinstance(c.handle, C.c_void_p) else c.handle
+                                      for c in ctxs])
+    _err(_lib().trg_hotrg_step_batch(arr, len(ctxs), axis, dcut))
+
+
+def trg_atrg_step(ctx: Context, axis: int, dcut: int):
+    _err(_lib().trg_atrg_step(ctx.handle, axis, dcut), ctx.handle)
+
+
+def trg_run(ctx: Context, L_: int):
+    ctx.run(L_)
+
+
+def trg_free_energy(ctx: Context) -> float:
+    return ctx.free_energy()
+
+
+def trg_impure_energy(ctx: Context) -> float:
+    return ctx.impure_energy()
+
+
+def trg_impure_magnetization(ctx: Context) -> float:
+    return ctx.impure_magnetization()
+
+
+def trg_footprint_bytes(d, dcut, precision="fp64", method="hotrg", impure=()) -> int:
+    bits = 0
+    for x in impure:
+        bits |= {"E": L.TRG_IMPURE_E, "M": L.TRG_IMPURE_M}[x]
+    return int(_lib().trg_footprint_bytes(d, dcut, PRECISIONS[precision], METHODS[method], bits))
+
+
+def trg_gemm(precision, A_ptr, Bt_ptr, C_ptr, M, N, K, lda, ldb, ldc, accumulate=False, stream=None):
+    _err(_lib().trg_gemm(PRECISIONS[precision] if isinstance(precision, str) else precision,
+                         A_ptr, Bt_ptr, C_ptr, M, N, K, lda, ldb, ldc, 1 if accumulate else 0, stream))
+
+
+def trg_gemm_tile(precision):
+    m, n, k = C.c_int(), C.c_int(), C.c_int()
+    _err(_lib().trg_gemm_tile(PRECISIONS[precision], C.byref(m), C.byref(n), C.byref(k)))
+    return m.value, n.value, k.value
+
+
+def trg_eigh(A_ptr, w_ptr, V_ptr, sweeps_ptr, n, batch, stream=None):
+    _err(_lib().trg_eigh(A_ptr, w_ptr, V_ptr, sweeps_ptr, n, batch, stream))

@@ -1,0 +1,171 @@
+"""HOTRG on the GPU (through the C-ABI) against the FP64 oracle and exact
+results: single steps on seeded random tensors element by element, whole
+Ising runs on gauge-invariant outputs (ln c_n, f, E, M)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import exact, hotrg, ising
+from tests.gpu_util import announce, need_gpu
+from trg_inputs import random_site_tensor
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_step(T, mu, dcut):
+    Tn = T / np.sqrt(np.sum(T * T))
+    T2, _, c, choices = hotrg.hotrg_step(Tn, mu, dcut)
+    return T2, c, choices
+
+
+@pytest.mark.parametrize("d,dims,mu,dcut,seed", [
+    (2, (3, 4), 0, 6, 1),
+    (2, (5, 3), 1, 30, 2),
+    (3, (2, 3, 2), 1, 5, 3),
+    (3, (3, 2, 3), 0, 4, 4),
+    (4, (2, 3, 2, 3), 2, 4, 5),
+    (4, (3, 3, 3, 3), 0, 9, 6),
+    (4, (4, 4, 4, 4), 3, 6, 7),
+    (4, (5, 4, 3, 2), 1, 7, 8),
+])
+def test_single_step_matches_oracle(d, dims, mu, dcut, seed):
+    need_gpu()
+    from paper_1911_12954_amd import trg_init_tensor
+    announce("single step", d, dims, mu, dcut, seed)
+    T = random_site_tensor(dims, seed, positive_bias=True)
+    ref, c, choices = _oracle_step(T, mu, dcut)
+    ctx = trg_init_tensor(T, precision="fp64")
+    ctx.hotrg_step(mu, dcut)
+    got = ctx.tensor()
+    rec = ctx.step_log()[-1]
+    assert got.shape == ref.shape
+    assert abs(rec.ln_c - math.log(c)) < 1e-12 * max(1.0, abs(math.log(c)))
+    assert np.max(np.abs(got - ref)) < 1e-10
+    for ch in choices:
+        U, spec = ctx.isometry(ch.nu)
+        n = ch.U.shape[0] * ch.U.shape[1]
+        assert rec.side[ch.nu] == ch.side and rec.kept[ch.nu] == ch.k
+        assert np.max(np.abs(spec - ch.spectrum)) < 1e-13 * max(abs(ch.spectrum[0]), 1e-300)
+        assert np.max(np.abs(U - ch.U.reshape(n, ch.k))) < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("budget", [14_000_000, 30_000_000])
+def test_sliced_join_is_bitwise_equal(budget):
+    """A small workspace forces the join into x0/x2 slices (14 MB: one value
+    of x0 and x2 per slice; 30 MB: ragged slices of x2): the result must not
+    change at all."""
+    need_gpu()
+    from paper_1911_12954_amd import trg_init_tensor
+    announce("sliced join", (5, 4, 3, 4), budget)
+    T = random_site_tensor((5, 4, 3, 4), 11, positive_bias=True)
+    a = trg_init_tensor(T)
+    a.hotrg_step(0, 6)
+    b = trg_init_tensor(T, workspace_bytes=budget)
+    b.hotrg_step(0, 6)
+    assert np.array_equal(a.tensor(), b.tensor())
+    assert a.step_log()[-1].ln_c == b.step_log()[-1].ln_c
+
+
+def _gpu_run(beta, h, d, dcut, L, impure=("E", "M"), precision="fp64"):
+    from paper_1911_12954_amd import trg_init_ising
+    ctx = trg_init_ising(beta, h, d, dcut=dcut, impure=impure, precision=precision)
+    ctx.run(L)
+    out = {"f": ctx.free_energy(), "log": ctx.step_log()}
+    if "E" in impure:
+        out["E"] = ctx.impure_energy()
+    if "M" in impure:
+        out["M"] = ctx.impure_magnetization()
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("h", [0.0, 1e-5])
+def test_4d_dcut4_L16_matches_oracle(h):
+    """4D Ising, beta = 0.1497, Dcut = 4, 16^4 periodic (16 steps)."""
+    need_gpu()
+    announce("4d run", 0.1497, h, 4, 16)
+    g = _gpu_run(0.1497, h, 4, 4, 16)
+    r = hotrg.run(0.1497, h, 4, 4, 16)
+    assert abs(g["f"] - r.ln_z_per_site) <= 1e-10 * abs(r.ln_z_per_site)
+    assert abs(g["E"] - r.energy) <= 1e-10 * abs(r.energy)
+    assert abs(g["M"] - r.magnetization) <= 1e-10 * abs(r.magnetization) + 1e-12
+    for gs, rs in zip(g["log"], r.steps[1:]):
+        assert abs(gs.ln_c - rs.ln_c) <= 1e-12 * max(1.0, abs(rs.ln_c))
+
+
+@pytest.mark.parametrize("beta,h", [(0.4407, 0.0), (0.3, 0.1)])
+def test_2d_L4_untruncated_equals_brute_force(beta, h):
+    need_gpu()
+    announce("2d brute", beta, h)
+    g = _gpu_run(beta, h, 2, 16, 4)
+    lnz, E, M = exact.brute_force(beta, h, 2, 4)
+    assert abs(g["f"] - lnz) < 1e-12
+    assert abs(g["E"] - E) < 1e-12
+    assert abs(g["M"] - M) < 1e-12
+
+
+def test_3d_L2_untruncated_equals_brute_force():
+    need_gpu()
+    announce("3d brute")
+    g = _gpu_run(0.25, 0.05, 3, 16, 2)
+    lnz, E, M = exact.brute_force(0.25, 0.05, 3, 2)
+    assert abs(g["f"] - lnz) < 1e-12
+    assert abs(g["E"] - E) < 1e-12
+    assert abs(g["M"] - M) < 1e-12
+
+
+def test_4d_two_steps_then_exact_equals_brute_force():
+    """Two untruncated GPU steps (x, y) on the 2^4 lattice, then the x/y legs
+    closed and the periodic 2x2 (z, t) network contracted exactly on the host."""
+    need_gpu()
+    from paper_1911_12954_amd import trg_init_ising
+    announce("4d brute two steps")
+    beta, h = 0.2, 0.1
+    ctx = trg_init_ising(beta, h, 4, dcut=256, impure=("E", "M"))
+    ctx.hotrg_step(0, 256)
+    ctx.hotrg_step(1, 256)
+    acc = ctx.accumulator()
+    T, SE, SM = ctx.tensor(0), ctx.tensor(1), ctx.tensor(2)
+    close = lambda X: np.einsum("aabbcdef->cdef", X)
+    Q, QE, QM = close(T), close(SE), close(SM)
+    net = lambda A, B, Cc, D: np.einsum("abcd,baef,ghdc,hgfe->", A, B, Cc, D, optimize=True)
+    z = net(Q, Q, Q, Q)
+    lnz = acc + math.log(z) / 16
+    bl, bE, bM = exact.brute_force(beta, h, 4, 2)
+    assert abs(lnz - bl) < 1e-12
+    assert abs(-net(QE, Q, Q, Q) / z - bE) < 1e-12
+    assert abs(net(QM, Q, Q, Q) / z - bM) < 1e-12
+
+
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_beta_zero_gives_ln2(d):
+    need_gpu()
+    announce("beta zero", d)
+    g = _gpu_run(0.0, 0.3, d, 4, 4, impure=("M",))
+    assert abs(g["f"] - math.log(2.0)) < 1e-14
+    assert abs(g["M"]) < 1e-14
+
+
+def test_field_reversal_symmetry():
+    need_gpu()
+    announce("field reversal")
+    a = _gpu_run(0.1497, 1e-3, 4, 4, 4)
+    b = _gpu_run(0.1497, -1e-3, 4, 4, 4)
+    assert abs(a["f"] - b["f"]) < 1e-13
+    assert abs(a["E"] - b["E"]) < 1e-12
+    assert abs(a["M"] + b["M"]) < 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-6), ("bf16x3", 1e-5)])
+def test_mixed_precision_error_against_fp64_path(precision, tol):
+    need_gpu()
+    announce("mixed", precision)
+    ref = _gpu_run(0.1497, 1e-5, 4, 4, 16)
+    got = _gpu_run(0.1497, 1e-5, 4, 4, 16, precision=precision)
+    ef = abs(got["f"] - ref["f"]) / abs(ref["f"])
+    eE = abs(got["E"] - ref["E"]) / abs(ref["E"])
+    eM = abs(got["M"] - ref["M"]) / abs(ref["M"])
+    print(f"[mixed {precision}] rel err f {ef:.3e} E {eE:.3e} M {eM:.3e}", flush=True)
+    assert ef < tol and eE < 10 * tol and eM < 10 * tol

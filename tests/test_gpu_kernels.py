@@ -1,0 +1,110 @@
+"""GPU kernels against plain references: the join GEMM in its three
+precisions and the Jacobi eigensolver."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import announce, need_gpu
+from trg_inputs import random_matrix, random_symmetric, gram_like
+
+pytestmark = pytest.mark.gpu
+
+
+def _pad(x, r, c):
+    out = np.zeros((r, c), dtype=x.dtype)
+    out[: x.shape[0], : x.shape[1]] = x
+    return out
+
+
+@pytest.mark.parametrize("M,N,K", [(128, 128, 16), (256, 384, 160), (1024, 512, 1040), (128, 1280, 4096)])
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_gemm_fp64(M, N, K, accumulate):
+    torch = need_gpu()
+    from paper_1911_12954_amd import trg_gemm
+    announce("gemm fp64", M, N, K, accumulate)
+    A = random_matrix(M, K, 1)
+    B = random_matrix(N, K, 2)
+    C0 = random_matrix(M, N, 3)
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    dC = torch.from_numpy(C0).cuda()
+    trg_gemm("fp64", dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), M, N, K, K, K, N, accumulate,
+             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    ref = A @ B.T + (C0 if accumulate else 0)
+    got = dC.cpu().numpy()
+    scale = np.abs(A) @ np.abs(B).T
+    assert np.max(np.abs(got - ref) / scale) < 1e-14 * K ** 0.5 + 1e-15
+
+
+@pytest.mark.parametrize("M,N,K", [(128, 128, 32), (384, 256, 1056), (256, 1024, 4096)])
+def test_gemm_fp32(M, N, K):
+    torch = need_gpu()
+    from paper_1911_12954_amd import trg_gemm
+    announce("gemm fp32", M, N, K)
+    A = random_matrix(M, K, 4).astype(np.float32)
+    B = random_matrix(N, K, 5).astype(np.float32)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    trg_gemm("fp32", dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), M, N, K, K, K, N, False,
+             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    ref = A.astype(np.float64) @ B.astype(np.float64).T
+    scale = np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64)).T
+    assert np.max(np.abs(dC.cpu().numpy() - ref) / scale) < 4 * 2.0 ** -24 * np.sqrt(K) + 1e-7
+
+
+@pytest.mark.parametrize("M,N,K", [(128, 128, 64), (256, 384, 1088), (512, 256, 4096)])
+def test_gemm_bf16x3(M, N, K):
+    torch = need_gpu()
+    from paper_1911_12954_amd import trg_gemm
+    announce("gemm bf16x3", M, N, K)
+    A = random_matrix(M, K, 6)
+    B = random_matrix(N, K, 7)
+
+    def split(X):
+        x32 = torch.from_numpy(X).float()
+        hi = x32.to(torch.bfloat16)
+        lo = (x32 - hi.float()).to(torch.bfloat16)
+        return hi, lo
+
+    ah, al = split(A)
+    bh, bl = split(B)
+    dA = torch.stack([ah, al]).cuda().contiguous()
+    dB = torch.stack([bh, bl]).cuda().contiguous()
+    dC = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    trg_gemm("bf16x3", dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), M, N, K, K, K, N, False,
+             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    f = lambda t: t.double().numpy()
+    ref = f(ah) @ f(bh).T + f(ah) @ f(bl).T + f(al) @ f(bh).T
+    scale = np.abs(A) @ np.abs(B).T
+    err = np.max(np.abs(dC.cpu().numpy() - ref) / scale)
+    assert err < 4 * 2.0 ** -24 * np.sqrt(K) + 1e-7
+    # and the split product is within ~2^-16 of the exact one
+    exact = A @ B.T
+    assert np.max(np.abs(dC.cpu().numpy() - exact) / scale) < 2.0 ** -14
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 7, 16, 33, 100, 144])
+def test_jacobi_eigh(n):
+    torch = need_gpu()
+    from paper_1911_12954_amd import trg_eigh
+    announce("eigh", n)
+    mats = [random_symmetric(n, 10 + n), gram_like(n, min(n, 12), 20 + n)]
+    A = np.stack(mats)
+    dA = torch.from_numpy(A.copy()).cuda()
+    dw = torch.empty((2, n), dtype=torch.float64, device="cuda")
+    dV = torch.empty((2, n, n), dtype=torch.float64, device="cuda")
+    ds = torch.empty(2, dtype=torch.int32, device="cuda")
+    trg_eigh(dA.data_ptr(), dw.data_ptr(), dV.data_ptr(), ds.data_ptr(), n, 2,
+             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    w, V, sw = dw.cpu().numpy(), dV.cpu().numpy(), ds.cpu().numpy()
+    for b in range(2):
+        assert sw[b] >= 0
+        ref = np.sort(np.linalg.eigvalsh(A[b]))[::-1]
+        nrm = np.linalg.norm(A[b])
+        assert np.max(np.abs(w[b] - ref)) < 1e-13 * nrm
+        assert np.all(np.diff(w[b]) <= 0)
+        assert np.allclose(V[b].T @ V[b], np.eye(n), atol=1e-13)
+        assert np.allclose(V[b] @ np.diag(w[b]) @ V[b].T, A[b], atol=1e-13 * nrm)
