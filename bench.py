@@ -1,0 +1,196 @@
+"""Benchmark: 4D Ising HOTRG RG-steps/s at Dcut = 10 on one MI355X.
+
+A step is one steady-state HOTRG coarse-graining step (Gram matrices, FP64
+eigendecomposition and isometries, block-spin contraction, post-join
+compression, FP64 normalisation) of the 4D Ising tensor at beta = 0.1497,
+h = 0, with every leg at Dcut = 10; inputs are resident in HBM.  The first
+three steps (leg dims 2 -> 4 -> 10) and `--warmup` steady steps are untimed;
+then `--steps` steps are timed between two stream synchronisations.
+
+The join GEMM (the D^15 contraction) is timed with HIP events on the
+library's stream; its algorithmic flops per step are 2 D^15 (3 x 2 D^15
+BF16 MFMA flops for the BF16x3 split).  The oracle (FP64 NumPy) is timed on
+a bounded sample of the same step on the host cores.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--dcut", type=int, default=10)
+    p.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    p.add_argument("--beta", type=float, default=0.1497)
+    p.add_argument("--compare", default="fp64,fp32",
+                   help="other join precisions timed for one step each (comma list, '' = none)")
+    p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    p.add_argument("--cpu-sample-blocks", type=int, default=1)
+    return p.parse_args()
+
+
+def progress(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def time_steps(precision, dcut, beta, warmup, steps):
+    import torch
+    from paper_1911_12954_amd import trg_init_ising
+    d = 4
+    ctx = trg_init_ising(beta, 0.0, d, dcut=dcut, precision=precision)
+    n = 0
+    # ramp: legs grow 2 -> 4 -> ... -> dcut
+    while min(ctx.dims()[0]) < dcut or n < d:
+        ctx.hotrg_step(n % d, dcut)
+        n += 1
+        if n > 3 * d:
+            break
+    ctx.sync()
+    progress(f"{precision}: ramp done after {n} steps, dims {ctx.dims()[0]}")
+    for _ in range(warmup):
+        tw = time.perf_counter()
+        ctx.hotrg_step(n % d, dcut)
+        n += 1
+        ctx.sync()
+        progress(f"{precision}: warmup step {n} took {time.perf_counter() - tw:.3f} s")
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    ctx.join_profile()  # reset counters
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.hotrg_step(n % d, dcut)
+        n += 1
+        if steps > 1 and dcut >= 10:
+            ctx.sync()  # keeps a progress line per step on long runs
+            progress(f"{precision}: timed step {n} done at {time.perf_counter() - t0:.3f} s")
+    ctx.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms, launches, _ = ctx.join_profile()
+    lnz = ctx.free_energy()
+    ctx.close()
+    torch.cuda.empty_cache()
+    return elapsed, ms, launches, lnz
+
+
+def cpu_baseline(dcut, blocks):
+    """Time the oracle on a bounded sample of one steady-state step: the six
+    isometries (all Gram matrices and eigendecompositions) plus `blocks`
+    blocks T'[x0, x2, Y, Y', :, :, :, :] of the block-spin contraction, each
+    1/D^4 of the join, then scale the join part to the whole step."""
+    import numpy as np
+    from oracle import hotrg
+    from trg_inputs import random_site_tensor
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    D = dcut
+    T = random_site_tensor((D,) * 4, seed=0, positive_bias=True)
+    T /= np.sqrt(np.sum(T * T))
+    mu = 0
+    t0 = time.perf_counter()
+    choices = [hotrg.isometry(T, mu, nu, D) for nu in (1, 2, 3)]
+    t_iso = time.perf_counter() - t0
+    U = {ch.nu: ch.U for ch in choices}
+    t0 = time.perf_counter()
+    for b in range(blocks):
+        # one (x0, x2) pair and one kept column Y of the first pre-join axis
+        Ub = dict(U)
+        Ub[1] = U[1][:, :, b % D: b % D + 1]
+        hotrg.coarse_grain(T, T, Ub, mu, x0s=[b % D], x2s=[(b + 1) % D])
+    t_blk = (time.perf_counter() - t0) / blocks
+    # whole step: D^2 (x0, x2) pairs x D^2 (Y, Y') pairs of such blocks
+    t_step = t_iso + t_blk * D ** 4
+    return {
+        "value": 1.0 / t_step,
+        "unit": "RG-steps/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"oracle FP64 NumPy, seeded random D={D} 4D tensor: the 6 HOSVD isometries of one step "
+                   f"({t_iso:.2f} s) plus {blocks} block(s) T'[x0,x2,Y,Y',:,:,:,:] of the block-spin "
+                   f"contraction ({t_blk:.2f} s each, 1/D^4 of the join), join scaled by D^4 = {D ** 4}"),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is design-only "
+                                   "(see DESIGN.md), --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    D = a.dcut
+    elapsed, join_ms, launches, lnz = time_steps(a.precision, D, a.beta, a.warmup, a.steps)
+    steps_per_s = a.steps / elapsed
+    alg_flops_step = 2.0 * D ** 15
+    mult = 3.0 if a.precision == "bf16x3" else 1.0
+    achieved = mult * alg_flops_step * a.steps / (join_ms * 1e-3) / 1e12 if join_ms > 0 else None
+    peak = PEAK_TFLOPS[a.precision]
+    out = {
+        "metric": "4D HOTRG RG-steps/s at Dcut=10 (steady-state step, 1 GPU)",
+        "value": steps_per_s,
+        "unit": "RG-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * elapsed / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16x3": "bf16x3 (bf16 MFMA, fp32 accumulate; fp64 Gram/eigh/norm)",
+                  "fp32": "fp32 (fp32 MFMA; fp64 Gram/eigh/norm)", "fp64": "fp64"}[a.precision],
+        "data": "synthetic (closed-form 4D Ising tensor, beta=%.4f, h=0)" % a.beta,
+        "config": {"workload": "4D Ising HOTRG, Dcut=%d, steady-state coarse-graining step, beta=%.4f, h=0, "
+                               "join precision %s" % (D, a.beta, a.precision),
+                   "dcut": D, "join_precision": a.precision, "lnZ_per_site_after_run": lnz},
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "gemm_nt_kernel (join, D^15 block-spin contraction)",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": (achieved / peak) if achieved else None,
+            "traffic": None,
+            "join_launches": launches,
+            "join_ms_per_step": join_ms / a.steps,
+            "join_share_of_step": (join_ms * 1e-3) / elapsed,
+            "fp32_equivalent_tflops": (alg_flops_step * a.steps / (join_ms * 1e-3) / 1e12) if join_ms > 0 else None,
+        },
+    }
+    others = {}
+    for prec in [x for x in a.compare.split(",") if x and x != a.precision]:
+        e, jm, nl, _ = time_steps(prec, D, a.beta, 0, 1)
+        m2 = 3.0 if prec == "bf16x3" else 1.0
+        ach = m2 * alg_flops_step / (jm * 1e-3) / 1e12
+        others[prec] = {"rg_steps_per_s": 1.0 / e, "join_tflops": ach, "frac_of_peak": ach / PEAK_TFLOPS[prec]}
+    if others:
+        out["other_precisions"] = others
+        if "fp64" in others:
+            out["speedup_vs_fp64_path"] = steps_per_s / others["fp64"]["rg_steps_per_s"]
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(D, a.cpu_sample_blocks)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
