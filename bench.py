@@ -42,7 +42,41 @@ def parse():
                    help="other join precisions timed for one step each (comma list, '' = none)")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     p.add_argument("--cpu-sample-blocks", type=int, default=1)
+    p.add_argument("--accuracy", default=None,
+                   help="instead of timing: run 'dcut,L,beta,h' in FP64, FP32 and BF16x3 with impure E and M "
+                        "and print the relative errors of f, E, M against the FP64 path")
     return p.parse_args()
+
+
+def accuracy(spec):
+    """Errors of the mixed-precision joins against the FP64 path on one
+    whole run (4D, impure-tensor E and M)."""
+    import torch
+    from paper_1911_12954_amd import trg_init_ising
+    dcut, L, beta, h = spec.split(",")
+    dcut, L, beta, h = int(dcut), int(L), float(beta), float(h)
+    res = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        t0 = time.perf_counter()
+        ctx = trg_init_ising(beta, h, 4, dcut=dcut, precision=prec, impure=("E", "M"))
+        m = L.bit_length() - 1
+        for n in range(1, 4 * m + 1):
+            ctx.hotrg_step((n - 1) % 4, dcut)
+            if n % 4 == 0:
+                ctx.sync()
+                progress(f"accuracy {prec}: step {n}/{4 * m} at {time.perf_counter() - t0:.1f} s")
+        res[prec] = {"f": ctx.free_energy(), "E": ctx.impure_energy(), "M": ctx.impure_magnetization(),
+                     "seconds": time.perf_counter() - t0,
+                     "degenerate_cuts": sum(sum(r.degenerate_cut) for r in ctx.step_log())}
+        ctx.close()
+        torch.cuda.empty_cache()
+        progress(f"accuracy {prec}: {res[prec]}")
+    ref = res["fp64"]
+    out = {"workload": f"4D Ising HOTRG Dcut={dcut} L={L} beta={beta} h={h}, impure E and M", "runs": res}
+    for prec in ("fp32", "bf16x3"):
+        out[f"rel_err_{prec}"] = {k: abs(res[prec][k] - ref[k]) / max(abs(ref[k]), 1e-300) for k in ("f", "E", "M")}
+        out[f"abs_err_{prec}"] = {k: abs(res[prec][k] - ref[k]) for k in ("f", "E", "M")}
+    return out
 
 
 def progress(*a):
@@ -139,6 +173,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.accuracy:
+        print(json.dumps(accuracy(a.accuracy)), flush=True)
+        return
     D = a.dcut
     elapsed, join_ms, launches, lnz = time_steps(a.precision, D, a.beta, a.warmup, a.steps)
     steps_per_s = a.steps / elapsed

@@ -184,15 +184,17 @@ def isometry(T: np.ndarray, mu: int, nu: int, dcut: int, force_side=None) -> Axi
 # Block-spin contraction C(A, B) (Fig. 1B red circle, Fig. 1C)
 # --------------------------------------------------------------------------
 
-def _coarse_grain_block(a, b, U, mu, d):
+def _coarse_grain_block(a, b, U, mu, d, Uf=None):
     """C(A, B) restricted to the x0 values present in ``a`` and the x2 values
     present in ``b``: ``a`` is A with its backward mu leg cut to those x0,
     ``b`` is B with its forward mu leg cut to those x2.
 
     Sums over the joined mu leg i (A's forward mu leg = B's backward mu leg)
     and over each transverse pair through U_nu[a_nu, b_nu, K_nu] (backward
-    legs) and U_nu[a'_nu, b'_nu, L_nu] (forward legs).  Legs of the result in
+    legs) and U_nu[a'_nu, b'_nu, L_nu] (forward legs; ``Uf`` when given
+    supplies these, e.g. column subsets for sampling).  Legs of the result in
     the canonical order: (x0, x2) on axis mu and (K_nu, L_nu) elsewhere."""
+    Uf = U if Uf is None else Uf
     others, pre, post = transverse_axes(d, mu)
     L = iter(_letters(3 + 6 * len(others)))
     i, x0, x2 = next(L), next(L), next(L)
@@ -212,7 +214,7 @@ def _coarse_grain_block(a, b, U, mu, d):
         new = [x for x in sa if x != la[nu]] + [lb[nu], lK[nu]]
         a, sa = ein(sa, la[nu] + lb[nu] + lK[nu], new, a, U[nu]), new
         new = [x for x in sb if x != lq[nu]] + [lp[nu], lL[nu]]
-        b, sb = ein(sb, lp[nu] + lq[nu] + lL[nu], new, b, U[nu]), new
+        b, sb = ein(sb, lp[nu] + lq[nu] + lL[nu], new, b, Uf[nu]), new
     # join: sum over i and the pre-axis legs shared by a and b
     shared = set(sa) & set(sb)
     se = [x for x in sa if x not in shared] + [x for x in sb if x not in shared]
@@ -222,7 +224,7 @@ def _coarse_grain_block(a, b, U, mu, d):
         new = [x for x in se if x not in (la[nu], lb[nu])] + [lK[nu]]
         e, se = ein(se, la[nu] + lb[nu] + lK[nu], new, e, U[nu]), new
         new = [x for x in se if x not in (lp[nu], lq[nu])] + [lL[nu]]
-        e, se = ein(se, lp[nu] + lq[nu] + lL[nu], new, e, U[nu]), new
+        e, se = ein(se, lp[nu] + lq[nu] + lL[nu], new, e, Uf[nu]), new
     target = []
     for ax in range(d):
         target += [x0, x2] if ax == mu else [lK[ax], lL[ax]]
@@ -232,14 +234,17 @@ def _coarse_grain_block(a, b, U, mu, d):
 SLICE_ELEMENTS = 1 << 24   # slice over (x0, x2) when an operand would exceed this
 
 
-def coarse_grain(A: np.ndarray, B: np.ndarray, U: dict, mu: int, x0s=None, x2s=None) -> np.ndarray:
+def coarse_grain(A: np.ndarray, B: np.ndarray, U: dict, mu: int, x0s=None, x2s=None,
+                 U_forward=None) -> np.ndarray:
     """C(A, B): the coarse-grained tensor of site 1 = A and site 2 = B along mu.
 
     ``U`` maps each transverse axis nu to U_nu[a, b, k].  Legs of the result are
     in the canonical order with dims d_mu on the mu legs and k_nu elsewhere.
     ``x0s``/``x2s`` restrict the output to some values of the new backward and
-    forward mu legs (used to sample large outputs); default all.  Large
-    problems are evaluated one (x0, x2) pair at a time to bound memory."""
+    forward mu legs (used to sample large outputs); default all.
+    ``U_forward`` (default ``U``) compresses the forward pairs; passing column
+    subsets of U and U_forward samples blocks of the output.  Large problems
+    are evaluated one (x0, x2) pair at a time to bound memory."""
     d = A.ndim // 2
     x0s = list(range(A.shape[2 * mu])) if x0s is None else list(x0s)
     x2s = list(range(B.shape[2 * mu + 1])) if x2s is None else list(x2s)
@@ -251,12 +256,13 @@ def coarse_grain(A: np.ndarray, B: np.ndarray, U: dict, mu: int, x0s=None, x2s=N
     for nu in pre:
         grow *= U[nu].shape[1] * U[nu].shape[2] // U[nu].shape[0]
     if a_all.size * grow <= SLICE_ELEMENTS:
-        return _coarse_grain_block(a_all, b_all, U, mu, d)
+        return _coarse_grain_block(a_all, b_all, U, mu, d, U_forward)
     shape = list(A.shape)
     shape[2 * mu], shape[2 * mu + 1] = len(x0s), len(x2s)
+    Uf = U if U_forward is None else U_forward
     for nu in range(d):
         if nu != mu:
-            shape[2 * nu] = shape[2 * nu + 1] = U[nu].shape[2]
+            shape[2 * nu], shape[2 * nu + 1] = U[nu].shape[2], Uf[nu].shape[2]
     out = np.zeros(shape)
     for p in range(len(x0s)):
         a = np.take(a_all, [p], axis=2 * mu)
@@ -264,7 +270,7 @@ def coarse_grain(A: np.ndarray, B: np.ndarray, U: dict, mu: int, x0s=None, x2s=N
             b = np.take(b_all, [q], axis=2 * mu + 1)
             idx = [slice(None)] * (2 * d)
             idx[2 * mu], idx[2 * mu + 1] = slice(p, p + 1), slice(q, q + 1)
-            out[tuple(idx)] = _coarse_grain_block(a, b, U, mu, d)
+            out[tuple(idx)] = _coarse_grain_block(a, b, U, mu, d, U_forward)
     return out
 
 

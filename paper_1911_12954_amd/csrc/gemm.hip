@@ -37,6 +37,17 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int ROW_BYTES = 128;               // K bytes per row per tile
 constexpr int LDS_STRIDE = ROW_BYTES + 16;   // padded row stride
 constexpr int NUM_XCD = 8;
+
+// LDS stages of the join kernels (compile-time tuning knobs)
+#ifndef TRG_F64_STAGES
+#define TRG_F64_STAGES 2
+#endif
+#ifndef TRG_F32_STAGES
+#define TRG_F32_STAGES 1
+#endif
+#ifndef TRG_BF16_STAGES
+#define TRG_BF16_STAGES 2
+#endif
 constexpr int GROUP_M = 8;
 
 template <int PREC> struct Prec;
@@ -83,7 +94,7 @@ __device__ inline void tile_coords(uint32_t wg, uint32_t tiles_m, uint32_t tiles
 }
 
 // BM x BN tile per workgroup, WM x WN waves, 256 threads for 4 waves.
-template <int PREC, int BM, int BN, int WM, int WN, bool ACCUM>
+template <int PREC, int BM, int BN, int WM, int WN, int STAGES, bool ACCUM>
 __global__ void __launch_bounds__(64 * WM * WN)
 gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
                const typename Prec<PREC>::in_t *__restrict__ Bt,
@@ -167,11 +178,20 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
     for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{};
 
   gload(0);
-  sstore(0);
-  __syncthreads();
+  if constexpr (STAGES == 2) {
+    sstore(0);
+    __syncthreads();
+  }
 
   for (uint32_t kt = 0; kt < ktiles; ++kt) {
-    const int cur = kt & 1;
+    // two stages: compute stage kt&1 while tile kt+1 is loaded, one barrier;
+    // one stage: store, barrier, load the next tile into registers, compute,
+    // barrier (two workgroups per CU then overlap each other's waits)
+    const int cur = STAGES == 2 ? (kt & 1) : 0;
+    if constexpr (STAGES == 1) {
+      sstore(0);
+      __syncthreads();
+    }
     if (kt + 1 < ktiles) gload(kt + 1);
 
     const unsigned char *base = smem + cur * STAGE;
@@ -216,18 +236,23 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
                                                               fb[0][j][s >> 2][s & 3], acc[i][j], 0, 0, 0);
     } else {
 #pragma unroll
+      // the three products of a block are spread over all accumulators so
+      // that consecutive MFMAs never depend on each other
       for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int term = 0; term < 3; ++term)
 #pragma unroll
-          for (int j = 0; j < FN; ++j) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i][s], fb[0][j][s], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i][s], fb[1][j][s], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i][s], fb[0][j][s], acc[i][j], 0, 0, 0);
-          }
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+              const int pa = term == 0 ? 1 : 0, pb = term == 1 ? 1 : 0;  // lo*hi, hi*lo, hi*hi
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[pa][i][s], fb[pb][j][s], acc[i][j], 0, 0, 0);
+            }
     }
 
-    if (kt + 1 < ktiles) sstore(cur ^ 1);
+    if constexpr (STAGES == 2) {
+      if (kt + 1 < ktiles) sstore(cur ^ 1);
+    }
     __syncthreads();
   }
 
@@ -251,7 +276,7 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
       }
 }
 
-template <int PREC, int BM, int BN, int WM, int WN>
+template <int PREC, int BM, int BN, int WM, int WN, int STAGES = 2>
 void launch_gemm(const void *A, const void *Bt, void *C, uint64_t M, uint64_t N, uint64_t K,
                  uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st,
                  uint32_t splits = 1, uint64_t c_split_stride = 0) {
@@ -263,7 +288,7 @@ void launch_gemm(const void *A, const void *Bt, void *C, uint64_t M, uint64_t N,
   if (M == 0 || N == 0) return;
   const uint64_t tiles_m = M / BM, tiles_n = N / BN, tiles = tiles_m * tiles_n;
   TRG_REQUIRE(tiles < (1ull << 31) && K / BK < (1ull << 31), "gemm: problem too large for one launch");
-  constexpr size_t lds = 2 * size_t(BM + BN) * LDS_STRIDE * P::planes;
+  constexpr size_t lds = STAGES * size_t(BM + BN) * LDS_STRIDE * P::planes;
   using in_t = typename P::in_t;
   using out_t = typename P::out_t;
   auto *a = static_cast<const in_t *>(A);
@@ -281,17 +306,17 @@ void launch_gemm(const void *A, const void *Bt, void *C, uint64_t M, uint64_t N,
   // dynamic LDS above 64 KB must be allowed per kernel (once per instantiation)
   static bool attr_set = false;
   if (!attr_set) {
-    TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nt_kernel<PREC, BM, BN, WM, WN, true>),
+    TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, true>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-    TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nt_kernel<PREC, BM, BN, WM, WN, false>),
+    TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, false>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     attr_set = true;
   }
   if (accum)
-    hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, true>), grid, block, lds, st, a, b, c,
+    hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, true>), grid, block, lds, st, a, b, c,
                        uint32_t(tiles_m), uint32_t(tiles_n), kt, lda, ldb, ldc, plA, plB, c_split_stride);
   else
-    hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, false>), grid, block, lds, st, a, b, c,
+    hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, false>), grid, block, lds, st, a, b, c,
                        uint32_t(tiles_m), uint32_t(tiles_n), kt, lda, ldb, ldc, plA, plB, c_split_stride);
   TRG_HIP_CHECK(hipGetLastError());
 }
@@ -310,9 +335,9 @@ GemmTile gemm_tile(int prec) {
 void gemm_nt(int prec, const void *A, const void *Bt, void *C, uint64_t M, uint64_t N, uint64_t K,
              uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st) {
   switch (prec) {
-    case 0: launch_gemm<0, 128, 128, 2, 2>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
-    case 1: launch_gemm<1, 128, 128, 2, 2>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
-    case 2: launch_gemm<2, 128, 128, 2, 2>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
+    case 0: launch_gemm<0, 128, 128, 2, 2, TRG_F64_STAGES>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
+    case 1: launch_gemm<1, 128, 128, 2, 2, TRG_F32_STAGES>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
+    case 2: launch_gemm<2, 128, 128, 2, 2, TRG_BF16_STAGES>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
   }
   throw Error(-1, "gemm: unknown precision");
 }

@@ -237,3 +237,17 @@ def test_gauge_invariance(d, L, dcut, beta, h):
         assert abs(v.ln_z_per_site - ref.ln_z_per_site) < 1e-12
         assert abs(v.energy - ref.energy) < 1e-10
         assert abs(v.magnetization - ref.magnetization) < 1e-10
+
+
+def test_sampled_blocks_equal_the_full_contraction():
+    """Column subsets of the backward and forward isometries select exactly
+    the corresponding block of C(A, B)."""
+    A = random_site_tensor((2, 3, 2, 3), seed=21)
+    rng = np.random.default_rng(4)
+    U = {nu: rng.standard_normal((dn, dn, 4)) for nu, dn in ((1, 3), (2, 2), (3, 3))}
+    full = hotrg.coarse_grain(A, A, U, 0)
+    Ub = dict(U); Uf = dict(U)
+    Ub[1] = U[1][:, :, [2]]; Uf[1] = U[1][:, :, [1]]
+    Ub[2] = U[2][:, :, [3]]; Uf[2] = U[2][:, :, [0]]
+    blk = hotrg.coarse_grain(A, A, Ub, 0, x0s=[1], x2s=[0], U_forward=Uf)
+    assert np.allclose(blk[0, 0, 0, 0, 0, 0], full[1, 0, 2, 1, 3, 0], atol=1e-13)
