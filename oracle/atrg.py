@@ -1,0 +1,391 @@
+"""ATRG coarse-graining of a d-dimensional tensor network (oracle, test infrastructure).
+
+Method: Sec. 2 and Fig. 2 of the paper.  ATRG keeps every site tensor as a
+product of two pieces and makes two approximations: a singular value
+decomposition of each local tensor, and a HOSVD of the two adjacent
+decomposed tensors.  The partial SVD that swaps tensor indices (the dark-blue
+tensors of Fig. 2B) and the contraction completing the block-spin
+transformation (the red dotted circle of Fig. 2B) are the two D^{2d+1} parts;
+the memory is D^{d+1}.  The partial SVD is a randomized SVD (RSVD) with a
+trial matrix drawn from N(0,1), oversampling p and q iterations of the
+orthogonal-matrix update (Sec. 3.2: p = 4 Dcut, q = 2 Dcut).
+
+Readings (the algorithm is given in Adachi et al., which the paper cites;
+each choice below is listed in the design doc):
+
+* A tensor T[b, f] (b = backward legs, f = forward legs, each in axis order)
+  is held as T = U diag(s) V with U[b, k], V[k, f].  The first local SVD of
+  the Ising tensor is exact (it has rank 2 in that bipartition); after a step
+  the new tensor is already a product over one index of dim <= Dcut, so the
+  "local SVD" is a canonicalisation (QR of both pieces, SVD of the small core)
+  and the approximations are the swap and the HOSVD.
+* Step along mu with site A below and site B above: with
+  Ut = U sqrt(s) and Vt = sqrt(s) V,
+  M[(k_A, b^B_perp), (f^A_perp, k_B)] = sum_j Vt[k_A, f^A_perp, f_mu = j] Ut[b_mu = j, b^B_perp, k_B]
+  is truncated to rank Dcut by RSVD: M ~ X diag(sigma) Y.  This swaps the
+  transverse legs between the pieces.
+* G[b^A, b^B_perp, l] = sum_kA Ut[b^A, k_A] X[k_A, b^B_perp, l] sqrt(sigma_l) holds all
+  backward legs, H[l, f^A_perp, f^B] = sqrt(sigma_l) sum_kB Y[l, f^A_perp, k_B] Vt[k_B, f^B]
+  all forward legs; the two-site tensor is sum_l G H.
+* HOSVD: for each transverse nu, the Gram matrix of the two-site tensor over
+  the backward pair (b^A_nu, b^B_nu) and over the forward pair (f^A_nu,
+  f^B_nu); the same selection rule as HOTRG (smaller discarded weight,
+  forward on a tie, canonical basis of degenerate eigenspaces) gives P_nu,
+  applied to both pairs.
+* New pieces G'[b_mu, B_perp, l] and H'[l, F_perp, f_mu]; normalisation
+  c = ||G' H'||_F = sqrt(Tr[(G'^T G')(H' H'^T)]), both pieces scaled by
+  c^{-1/2}, acc += 2^{-n} ln c.  Tr T = sum_l sum_b G'[b, l] H'[l, b].
+* RSVD (Halko et al. as in Erichson et al.): Q = orth(M Omega); q times
+  Z = orth(M^T Q), Q = orth(M Z); then the SVD of Q^T M.  Omega has
+  Dcut + p columns; entry (i, c) of step n comes from Philox4x32-10 with key
+  (seed low, seed high) and counter (i * ncols + c, n, 0, 0): the first two
+  output words give uniforms u = (w + 0.5) / 2^32 and one Box-Muller normal
+  sqrt(-2 ln u1) cos(2 pi u2).
+"""
+from __future__ import annotations
+
+import math
+import string
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import hotrg
+from .ising import bond_split
+
+# ------------------------------------------------------------------ Philox ---
+PHILOX_M0, PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+PHILOX_W0, PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+MASK32 = 0xFFFFFFFF
+
+
+def philox4x32_10(counter, key):
+    """Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11) on four
+    32-bit counter words and two 32-bit key words; returns four words."""
+    c = [int(x) & MASK32 for x in counter]
+    k0, k1 = int(key[0]) & MASK32, int(key[1]) & MASK32
+    for r in range(10):
+        if r:
+            k0 = (k0 + PHILOX_W0) & MASK32
+            k1 = (k1 + PHILOX_W1) & MASK32
+        p0 = PHILOX_M0 * c[0]
+        p1 = PHILOX_M1 * c[2]
+        hi0, lo0 = p0 >> 32, p0 & MASK32
+        hi1, lo1 = p1 >> 32, p1 & MASK32
+        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+    return c
+
+
+def philox4x32_10_vec(ctr0, ctr1, key):
+    """Vectorised Philox4x32-10 over arrays of the first two counter words
+    (the last two are zero); returns the first two output words."""
+    c0 = np.asarray(ctr0, dtype=np.uint64) & MASK32
+    c1 = np.asarray(ctr1, dtype=np.uint64) & MASK32
+    c2 = np.zeros_like(c0)
+    c3 = np.zeros_like(c0)
+    k0, k1 = np.uint64(key[0] & MASK32), np.uint64(key[1] & MASK32)
+    m0, m1 = np.uint64(PHILOX_M0), np.uint64(PHILOX_M1)
+    for r in range(10):
+        if r:
+            k0 = np.uint64((int(k0) + PHILOX_W0) & MASK32)
+            k1 = np.uint64((int(k1) + PHILOX_W1) & MASK32)
+        p0 = m0 * c0
+        p1 = m1 * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & np.uint64(MASK32)
+        hi1, lo1 = p1 >> np.uint64(32), p1 & np.uint64(MASK32)
+        c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+    return c0, c1
+
+
+def trial_matrix(rows: int, cols: int, step: int, seed: int) -> np.ndarray:
+    """Gaussian trial matrix Omega[rows, cols] of ATRG step `step`."""
+    e = np.arange(rows * cols, dtype=np.uint64)
+    w0, w1 = philox4x32_10_vec(e, np.full_like(e, step), (seed & MASK32, (seed >> 32) & MASK32))
+    u1 = (w0.astype(np.float64) + 0.5) / 4294967296.0
+    u2 = (w1.astype(np.float64) + 0.5) / 4294967296.0
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    return z.reshape(rows, cols)
+
+
+# ------------------------------------------------------------ factored state ---
+@dataclass
+class Factors:
+    """T[b, f] = sum_k U[b..., k] s[k] V[k, f...] (b, f: d legs each)."""
+    U: np.ndarray
+    s: np.ndarray
+    V: np.ndarray
+
+    @property
+    def d(self):
+        return self.U.ndim - 1
+
+    def dims(self):
+        return self.U.shape[:-1]
+
+    def dense(self):
+        d = self.d
+        Um = self.U.reshape(-1, self.U.shape[-1])
+        Vm = self.V.reshape(self.V.shape[0], -1)
+        return ((Um * self.s) @ Vm).reshape(self.U.shape[:-1] + self.V.shape[1:])
+
+
+def ising_factors(beta: float, h: float, d: int) -> Factors:
+    """Exact rank-2 factorisation of the Ising site tensor in the
+    (backward | forward) bipartition: T0[b, f] = sum_sigma u_sigma[b] v_sigma[f]
+    with u_sigma[b] = e^{beta h sigma/2} prod W[sigma, b_nu] (v the same)."""
+    W = bond_split(beta)
+    U = np.zeros((2,) * d + (2,))
+    for row, spin in enumerate((1.0, -1.0)):
+        u = np.array(math.exp(0.5 * beta * h * spin))
+        for _ in range(d):
+            u = np.multiply.outer(u, W[row])
+        U[..., row] = u
+    V = np.moveaxis(U, -1, 0).copy()
+    return Factors(U, np.ones(2), V)
+
+
+def canonical(G: np.ndarray, H: np.ndarray, dcut: int) -> Factors:
+    """Local SVD of T = G H (G[b..., l], H[l, f...]): QR of both pieces and an
+    SVD of the small core; keeps at most dcut singular values."""
+    r = G.shape[-1]
+    Gm = G.reshape(-1, r)
+    Hm = H.reshape(r, -1)
+    Qg, Rg = np.linalg.qr(Gm)
+    Qh, Rh = np.linalg.qr(Hm.T)
+    W, s, Zt = np.linalg.svd(Rg @ Rh.T)
+    k = min(dcut, int(np.count_nonzero(s > 0)) or 1, len(s))
+    U = (Qg @ W[:, :k]).reshape(G.shape[:-1] + (k,))
+    V = (Zt[:k] @ Qh.T).reshape((k,) + H.shape[1:])
+    return Factors(U, s[:k], V)
+
+
+# ------------------------------------------------------------------- swap ---
+def _swap_operands(F: Factors, mu: int):
+    """Ut = U sqrt(s), Vt = sqrt(s) V with the mu legs moved next to the core:
+    Vt -> [k_A, f_perp..., j], Ut -> [j, b_perp..., k_B]."""
+    d = F.d
+    rs = np.sqrt(F.s)
+    Ut = F.U * rs
+    Vt = F.V * rs.reshape((-1,) + (1,) * d)
+    Ut = np.moveaxis(Ut, mu, 0)            # [j, b_perp..., k]
+    Vt = np.moveaxis(Vt, 1 + mu, -1)       # [k, f_perp..., j]
+    return Ut, Vt
+
+
+def swap_matrix(F: Factors, mu: int) -> np.ndarray:
+    """The regrouped matrix M[(k_A, b^B_perp), (f^A_perp, k_B)] (dense; small
+    problems only)."""
+    Ut, Vt = _swap_operands(F, mu)
+    k = F.s.shape[0]
+    nperp = int(np.prod(Ut.shape[1:-1]))
+    # [k_A, f_perp, j] x [j, b_perp, k_B] -> [k_A, f_perp, b_perp, k_B]
+    M = np.tensordot(Vt, Ut, axes=([Vt.ndim - 1], [0]))
+    M = M.reshape(k, nperp, nperp, k)
+    M = M.transpose(0, 2, 1, 3).reshape(k * nperp, nperp * k)
+    return M
+
+
+def _apply(Ut, Vt, Z, transpose: bool):
+    """M @ Z (or M^T @ Z) without forming M: Z has rows (f_perp, k_B) (or
+    (k_A, b_perp)) and c columns."""
+    k = Vt.shape[0]
+    nperp = int(np.prod(Vt.shape[1:-1]))
+    Um = Ut.reshape(Ut.shape[0], nperp, k)       # [j, b, kB]
+    Vm = Vt.reshape(k, nperp, Vt.shape[-1])      # [kA, f, j]
+    c = Z.shape[1]
+    if not transpose:
+        Zr = Z.reshape(nperp, k, c)              # [f, kB, c]
+        t = np.einsum("afj,fbc->ajbc", Vm, Zr, optimize=True)      # [kA, j, kB, c]
+        out = np.einsum("ajbc,jpb->apc", t, Um, optimize=True)     # [kA, b_perp, c]
+        return out.reshape(k * nperp, c)
+    Zr = Z.reshape(k, nperp, c)                  # [kA, b, c]
+    t = np.einsum("jpb,apc->jbac", Um, Zr, optimize=True)          # [j, kB, kA, c]
+    out = np.einsum("afj,jbac->fbc", Vm, t, optimize=True)         # [f_perp, kB, c]
+    return out.reshape(nperp * k, c)
+
+
+def rsvd_swap(F: Factors, mu: int, dcut: int, p: int, q: int, step: int, seed: int, dense: bool = False):
+    """Truncated partial SVD of the swap matrix: X[(k_A, b_perp), l], sigma[l],
+    Y[l, (f_perp, k_B)] with l < dcut.  ``dense`` uses a full SVD instead of
+    the randomized one (a pin for small problems)."""
+    Ut, Vt = _swap_operands(F, mu)
+    k = F.s.shape[0]
+    nperp = int(np.prod(Ut.shape[1:-1]))
+    n = k * nperp
+    if dense:
+        M = swap_matrix(F, mu)
+        X, sig, Y = np.linalg.svd(M, full_matrices=False)
+        r = min(dcut, len(sig))
+        return X[:, :r], sig[:r], Y[:r]
+    r = min(dcut + p, n)
+    Om = trial_matrix(n, r, step, seed)
+    Q, _ = np.linalg.qr(_apply(Ut, Vt, Om, False))
+    for _ in range(q):
+        Z, _ = np.linalg.qr(_apply(Ut, Vt, Q, True))
+        Q, _ = np.linalg.qr(_apply(Ut, Vt, Z, False))
+    Bt = _apply(Ut, Vt, Q, True)                 # M^T Q = (Q^T M)^T, n x r
+    Wb, sig, Zt = np.linalg.svd(Bt.T, full_matrices=False)
+    keep = min(dcut, len(sig))
+    return Q @ Wb[:, :keep], sig[:keep], Zt[:keep]
+
+
+# ------------------------------------------------------------------ HOSVD ---
+def _pieces(F: Factors, X, sig, Y, mu: int):
+    """G[b^A (d legs), b^B_perp (d-1 legs), l] and H[l, f^A_perp, f^B (d legs)]."""
+    d = F.d
+    k = F.s.shape[0]
+    rs = np.sqrt(F.s)
+    dims = F.dims()
+    perp = [dims[a] for a in range(d) if a != mu]
+    r = sig.shape[0]
+    Xs = (X * np.sqrt(sig)).reshape((k,) + tuple(perp) + (r,))
+    Ys = (np.sqrt(sig)[:, None] * Y).reshape((r,) + tuple(perp) + (k,))
+    Ut = F.U * rs
+    Vt = F.V * rs.reshape((-1,) + (1,) * d)
+    G = np.tensordot(Ut, Xs, axes=([d], [0]))          # [b^A..., b^B_perp..., l]
+    H = np.tensordot(Ys, Vt, axes=([Ys.ndim - 1], [0]))  # [l, f^A_perp..., f^B...]
+    return G, H
+
+
+def isometries(G: np.ndarray, H: np.ndarray, mu: int, d: int, dcut: int):
+    """HOSVD isometries P_nu from the Gram matrices of sum_l G H over the
+    backward pair (b^A_nu, b^B_nu) (legs of G) and the forward pair (f^A_nu,
+    f^B_nu) (legs of H); same selection rule as HOTRG."""
+    perp = [a for a in range(d) if a != mu]
+    # leg positions: G = [bA_0..bA_{d-1}, bB_perp..., l]; H = [l, fA_perp..., fB_0..fB_{d-1}]
+    Wf = np.tensordot(H, H, axes=(list(range(1, H.ndim)), list(range(1, H.ndim))))   # [l, l']
+    Wb = np.tensordot(G, G, axes=(list(range(G.ndim - 1)), list(range(G.ndim - 1))))  # [l, l']
+    out = []
+    L = string.ascii_letters
+    for j, nu in enumerate(perp):
+        dn = G.shape[nu]
+        grams = []
+        # backward pair: G legs nu (site A) and d + j (site B)
+        sub1 = list(L[: G.ndim])
+        sub2 = list(sub1)
+        sub2[nu], sub2[d + j], sub2[-1] = "W", "X", "Y"
+        gb = np.einsum("".join(sub1) + "," + "".join(sub2) + "," + sub1[-1] + "Y" + "->" +
+                       sub1[nu] + sub1[d + j] + "WX", G, G, Wf, optimize=True)
+        grams.append(gb.reshape(dn * dn, dn * dn))
+        # forward pair: H legs 1 + j (site A) and 1 + (d - 1) + nu (site B)
+        a_pos, b_pos = 1 + j, d + nu
+        sub1 = list(L[: H.ndim])
+        sub2 = list(sub1)
+        sub2[a_pos], sub2[b_pos], sub2[0] = "W", "X", "Y"
+        gf = np.einsum(sub1[0] + "Y" + "," + "".join(sub1) + "," + "".join(sub2) + "->" +
+                       sub1[a_pos] + sub1[b_pos] + "WX", Wb, H, H, optimize=True)
+        grams.append(gf.reshape(dn * dn, dn * dn))
+        n = dn * dn
+        k = min(n, dcut)
+        res = []
+        for g in grams:
+            w, v = hotrg._eig_desc(g)
+            res.append((w, v, float(np.sum(np.maximum(w[k:], 0.0)))))
+        eps_b, eps_f = res[0][2], res[1][2]
+        side = hotrg.SIDE_BACKWARD if eps_b < (1.0 - hotrg.TIE_REL) * eps_f else hotrg.SIDE_FORWARD
+        w, v, _ = res[side]
+        P = hotrg._kept_vectors(w, v, k).reshape(dn, dn, k)
+        out.append(hotrg.AxisChoice(nu, side, k, (eps_b, eps_f), w, False, P))
+    return out
+
+
+def contract(G: np.ndarray, H: np.ndarray, P: dict, mu: int, d: int):
+    """G'[b_mu, B_perp..., l] and H'[l, F_perp..., f_mu] in the canonical leg
+    order (axis order within the backward and the forward group)."""
+    perp = [a for a in range(d) if a != mu]
+    # G legs: bA_0..bA_{d-1}, bB_perp..., l; compress (bA_nu, bB_nu) -> B_nu
+    L = string.ascii_letters
+    gA = list(L[:d])
+    gB = {nu: L[d + j] for j, nu in enumerate(perp)}
+    gl = L[2 * d]
+    outB = {nu: L[2 * d + 1 + j] for j, nu in enumerate(perp)}
+    sub_G = "".join(gA) + "".join(gB[nu] for nu in perp) + gl
+    ops = [G]
+    subs = [sub_G]
+    for nu in perp:
+        ops.append(P[nu])
+        subs.append(gA[nu] + gB[nu] + outB[nu])
+    target = "".join(gA[a] if a == mu else outB[a] for a in range(d)) + gl
+    Gn = np.einsum(",".join(subs) + "->" + target, *ops, optimize=True)
+    # H legs: l, fA_perp..., fB_0..fB_{d-1}
+    hl = L[0]
+    hA = {nu: L[1 + j] for j, nu in enumerate(perp)}
+    hB = list(L[d: 2 * d])
+    outF = {nu: L[2 * d + j] for j, nu in enumerate(perp)}
+    sub_H = hl + "".join(hA[nu] for nu in perp) + "".join(hB)
+    ops = [H]
+    subs = [sub_H]
+    for nu in perp:
+        ops.append(P[nu])
+        subs.append(hA[nu] + hB[nu] + outF[nu])
+    target = hl + "".join(hB[a] if a == mu else outF[a] for a in range(d))
+    Hn = np.einsum(",".join(subs) + "->" + target, *ops, optimize=True)
+    return Gn, Hn
+
+
+# ------------------------------------------------------------- step / run ---
+@dataclass
+class AtrgStep:
+    n: int
+    mu: int
+    ln_c: float
+    swap_sigma: np.ndarray
+    local_s: np.ndarray
+    axes: list = field(default_factory=list)
+
+
+def atrg_step(F: Factors, mu: int, dcut: int, p: int, q: int, step: int, seed: int, dense_swap=False):
+    """One ATRG step along mu on canonical factors F.  Returns the new pieces
+    (G', H') normalised, c, and the step record."""
+    d = F.d
+    X, sig, Y = rsvd_swap(F, mu, dcut, p, q, step, seed, dense=dense_swap)
+    G, H = _pieces(F, X, sig, Y, mu)
+    choices = isometries(G, H, mu, d, dcut)
+    P = {ch.nu: ch.U for ch in choices}
+    Gn, Hn = contract(G, H, P, mu, d)
+    r = Gn.shape[-1]
+    GtG = Gn.reshape(-1, r).T @ Gn.reshape(-1, r)
+    HHt = Hn.reshape(r, -1) @ Hn.reshape(r, -1).T
+    c = math.sqrt(float(np.sum(GtG * HHt)))
+    Gn = Gn / math.sqrt(c)
+    Hn = Hn / math.sqrt(c)
+    return Gn, Hn, c, AtrgStep(step, mu, math.log(c), sig, F.s, choices)
+
+
+def periodic_trace(G: np.ndarray, H: np.ndarray) -> float:
+    """Tr T for T = sum_l G[b..., l] H[l, f...] with each f_nu joined to b_nu."""
+    r = G.shape[-1]
+    return float(np.sum(G.reshape(-1, r) * H.reshape(r, -1).T))
+
+
+@dataclass
+class AtrgResult:
+    ln_z_per_site: float
+    acc: float
+    trace: float
+    steps: list
+
+
+def run(beta: float, h: float, d: int, dcut: int, L: int, p=None, q=None, seed: int = 0,
+        dense_swap: bool = False) -> AtrgResult:
+    """ATRG on the periodic L^d lattice: d*m steps along (n-1) mod d."""
+    m = int(round(math.log2(L)))
+    if 2 ** m != L or m < 1:
+        raise ValueError("L must be a power of two >= 2")
+    p = 4 * dcut if p is None else p
+    q = 2 * dcut if q is None else q
+    F0 = ising_factors(beta, h, d)
+    G, H = F0.U * 1.0, F0.V * 1.0
+    r = G.shape[-1]
+    c0 = math.sqrt(float(np.sum((G.reshape(-1, r).T @ G.reshape(-1, r)) * (H.reshape(r, -1) @ H.reshape(r, -1).T))))
+    G, H = G / math.sqrt(c0), H / math.sqrt(c0)
+    acc = math.log(c0)
+    steps = []
+    for n in range(1, d * m + 1):
+        mu = (n - 1) % d
+        F = canonical(G, H, dcut)
+        G, H, c, rec = atrg_step(F, mu, dcut, p, q, n, seed, dense_swap)
+        acc += 2.0 ** (-n) * math.log(c)
+        steps.append(rec)
+    tr = periodic_trace(G, H)
+    return AtrgResult(acc + 2.0 ** (-(d * m)) * math.log(tr), acc, tr, steps)

@@ -1,0 +1,107 @@
+"""Pins of the ATRG oracle: the counter-based generator against its published
+known answers, exactness against brute-force spin sums when nothing is
+truncated, RSVD against a dense SVD, the p,q-independence the paper reports,
+and Onsager's solution on a large 2D lattice."""
+import math
+import warnings
+
+import numpy as np
+import pytest
+
+from oracle import atrg, exact
+
+warnings.filterwarnings("ignore", message=".*roundoff error.*")
+
+
+@pytest.mark.parametrize("ctr,key,expect", [
+    ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+    ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+    ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+     (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+])
+def test_philox_known_answers(ctr, key, expect):
+    """Known-answer vectors of Philox4x32-10 published with the generator."""
+    assert tuple(atrg.philox4x32_10(ctr, key)) == expect
+
+
+def test_philox_vectorised_equals_scalar():
+    c0 = np.array([0, 5, 123456789, 0xFFFFFFFF])
+    c1 = np.array([0, 7, 3, 1])
+    w0, w1 = atrg.philox4x32_10_vec(c0, c1, (0xDEADBEEF, 42))
+    for i in range(4):
+        s = atrg.philox4x32_10((int(c0[i]), int(c1[i]), 0, 0), (0xDEADBEEF, 42))
+        assert (int(w0[i]), int(w1[i])) == (s[0], s[1])
+
+
+def test_trial_matrix_is_standard_normal():
+    Om = atrg.trial_matrix(400, 250, 3, 99)
+    assert abs(Om.mean()) < 0.01 and abs(Om.std() - 1.0) < 0.01
+    assert np.array_equal(Om, atrg.trial_matrix(400, 250, 3, 99))
+    assert not np.array_equal(Om, atrg.trial_matrix(400, 250, 4, 99))
+
+
+def test_ising_factors_are_exact():
+    from oracle import ising
+    for d in (2, 4):
+        F = atrg.ising_factors(0.3, 0.1, d)
+        T0 = ising.site_tensors(0.3, 0.1, d)[0]
+        # factor legs (b..., f...) -> canonical interleaved (b0, f0, b1, f1, ...)
+        dense = F.dense()
+        order = [x for a in range(d) for x in (a, d + a)]
+        assert np.allclose(np.transpose(dense, order), T0, atol=1e-14)
+
+
+@pytest.mark.parametrize("beta,h", [(0.4407, 0.0), (0.3, 0.1)])
+@pytest.mark.parametrize("dense", [True, False])
+def test_2d_L4_untruncated_equals_brute_force(beta, h, dense):
+    r = atrg.run(beta, h, 2, 128, 4, p=8, q=2, dense_swap=dense)
+    assert abs(r.ln_z_per_site - exact.brute_force(beta, h, 2, 4)[0]) < 1e-12
+
+
+def test_3d_L2_untruncated_equals_brute_force():
+    r = atrg.run(0.25, 0.05, 3, 1024, 2, dense_swap=True)
+    assert abs(r.ln_z_per_site - exact.brute_force(0.25, 0.05, 3, 2)[0]) < 1e-12
+
+
+def test_4d_two_steps_then_exact_equals_brute_force():
+    """Two untruncated ATRG steps on the 2^4 lattice, then the coarse-grained
+    legs closed and the periodic 2x2 network of the other two axes contracted
+    exactly (as for HOTRG)."""
+    beta, h = 0.2, 0.1
+    F0 = atrg.ising_factors(beta, h, 4)
+    G, H = F0.U, F0.V
+    r = G.shape[-1]
+    c0 = math.sqrt(float(np.sum((G.reshape(-1, r).T @ G.reshape(-1, r)) * (H.reshape(r, -1) @ H.reshape(r, -1).T))))
+    G, H = G / math.sqrt(c0), H / math.sqrt(c0)
+    lnz = math.log(c0)
+    for n, mu in ((1, 0), (2, 1)):
+        F = atrg.canonical(G, H, 4096)
+        G, H, c, _ = atrg.atrg_step(F, mu, 4096, 0, 0, n, 0, dense_swap=True)
+        lnz += 2.0 ** -n * math.log(c)
+    T = np.tensordot(G, H, axes=([4], [0]))  # [b0..b3, f0..f3]
+    Q = np.einsum("abcdabef->cdef", T)       # close x, y: Q[z, t, z', t']
+    Q = Q.transpose(0, 2, 1, 3)              # -> [z, z', t, t']
+    net = lambda A, B, C, D: np.einsum("abcd,baef,ghdc,hgfe->", A, B, C, D, optimize=True)
+    lnz += math.log(net(Q, Q, Q, Q)) / 16
+    assert abs(lnz - exact.brute_force(beta, h, 4, 2)[0]) < 1e-12
+
+
+@pytest.mark.parametrize("dcut", [4, 6])
+def test_rsvd_equals_dense_svd_and_pq_independence(dcut):
+    a = atrg.run(0.1497, 0.0, 4, dcut, 4)                         # p = 4 Dcut, q = 2 Dcut
+    b = atrg.run(0.1497, 0.0, 4, dcut, 4, dense_swap=True)
+    c = atrg.run(0.1497, 0.0, 4, dcut, 4, p=2 * dcut, q=dcut)      # p = 2 Dcut, q = Dcut
+    assert abs(a.ln_z_per_site - b.ln_z_per_site) < 1e-12
+    assert abs(c.ln_z_per_site - a.ln_z_per_site) < 1e-6
+
+
+def test_beta_zero_and_field_symmetry():
+    assert abs(atrg.run(0.0, 0.2, 4, 4, 4).ln_z_per_site - math.log(2.0)) < 1e-14
+    a = atrg.run(0.1497, 1e-3, 4, 4, 4)
+    b = atrg.run(0.1497, -1e-3, 4, 4, 4)
+    assert abs(a.ln_z_per_site - b.ln_z_per_site) < 1e-12
+
+
+def test_2d_large_lattice_approaches_onsager():
+    r = atrg.run(0.2, 0.0, 2, 16, 2 ** 20)
+    assert abs(r.ln_z_per_site - exact.onsager_lnz(0.2)) < 1e-7
