@@ -42,6 +42,8 @@ def parse():
                    help="other join precisions timed for one step each (comma list, '' = none)")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     p.add_argument("--cpu-sample-blocks", type=int, default=1)
+    p.add_argument("--method", default="hotrg", choices=["hotrg", "atrg"],
+                   help="atrg: time steady-state ATRG steps (default Dcut 24 there) instead of HOTRG")
     p.add_argument("--accuracy", default=None,
                    help="instead of timing: run 'dcut,L,beta,h' in FP64, FP32 and BF16x3 with impure E and M "
                         "and print the relative errors of f, E, M against the FP64 path")
@@ -124,6 +126,43 @@ def time_steps(precision, dcut, beta, warmup, steps):
     return elapsed, ms, launches, lnz
 
 
+def time_atrg(precision, dcut, beta, warmup, steps):
+    """Steady-state ATRG steps of the 4D Ising model (every leg at dcut,
+    p = 4 dcut, q = 2 dcut).  Returns elapsed, contraction-GEMM ms, launches,
+    algorithmic flops of those GEMMs."""
+    import torch
+    from paper_1911_12954_amd import trg_init_ising
+    d = 4
+    ctx = trg_init_ising(beta, 0.0, d, dcut=dcut, precision=precision, method="atrg")
+    n = 0
+    while min(ctx.dims()[0]) < dcut or n < d:
+        t0 = time.perf_counter()
+        ctx.atrg_step(n % d, dcut)
+        n += 1
+        ctx.sync()
+        progress(f"atrg {precision}: ramp step {n} dims {ctx.dims()[0]} {time.perf_counter() - t0:.2f} s")
+        if n > 4 * d:
+            break
+    for _ in range(warmup):
+        ctx.atrg_step(n % d, dcut)
+        n += 1
+        ctx.sync()
+    ctx.set_profiling(True)
+    ctx.join_profile()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.atrg_step(n % d, dcut)
+        n += 1
+        ctx.sync()
+        progress(f"atrg {precision}: timed step {n} at {time.perf_counter() - t0:.2f} s")
+    elapsed = time.perf_counter() - t0
+    ms, launches, flops = ctx.join_profile()
+    lnz = ctx.free_energy()
+    ctx.close()
+    torch.cuda.empty_cache()
+    return elapsed, ms, launches, flops, lnz
+
+
 def cpu_baseline(dcut, blocks):
     """Time the oracle on a bounded sample of one steady-state step: the six
     isometries (all Gram matrices and eigendecompositions) plus `blocks`
@@ -175,6 +214,24 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.accuracy:
         print(json.dumps(accuracy(a.accuracy)), flush=True)
+        return
+    if a.method == "atrg":
+        D = a.dcut if a.dcut != 10 else 24
+        prec = a.precision if a.precision != "bf16x3" else "fp64"
+        el, ms, nl, fl, lnz = time_atrg(prec, D, a.beta, a.warmup, a.steps)
+        ach = fl / (ms * 1e-3) / 1e12 if ms > 0 else None
+        print(json.dumps({
+            "metric": "4D ATRG RG-steps/s at Dcut=%d (steady-state step, 1 GPU)" % D,
+            "value": a.steps / el, "unit": "RG-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": 1e3 * el / a.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": prec, "data": "synthetic (closed-form 4D Ising tensor, beta=%.4f, h=0)" % a.beta,
+            "config": {"workload": "4D Ising ATRG, Dcut=%d, p=4Dcut, q=2Dcut, contraction %s" % (D, prec),
+                       "lnZ_per_site_after_run": lnz},
+            "roofline": {"bound": "mfma", "kernel": "gemm_nt_kernel (ATRG contraction, M=D^4 K=D^2 N=D^3)",
+                         "achieved": ach, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                         "frac": (ach / PEAK_TFLOPS[prec]) if ach else None, "traffic": None,
+                         "launches": nl, "gemm_ms_per_step": ms / a.steps,
+                         "gemm_share_of_step": ms * 1e-3 / el}}), flush=True)
         return
     D = a.dcut
     elapsed, join_ms, launches, lnz = time_steps(a.precision, D, a.beta, a.warmup, a.steps)

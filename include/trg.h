@@ -63,8 +63,8 @@ typedef struct trg_config {
   int method;             /* TRG_HOTRG (default) or TRG_ATRG */
   int dcut;               /* bond dimension used by trg_run; > 0 */
   unsigned impure;        /* TRG_IMPURE_E | TRG_IMPURE_M, or 0 */
-  int rsvd_p;             /* ATRG randomized SVD oversampling; 0 = 4*dcut */
-  int rsvd_q;             /* ATRG power iterations; < 0 = 2*dcut */
+  int rsvd_p;             /* ATRG randomized SVD oversampling; 0 = 4*dcut, < 0 = none */
+  int rsvd_q;             /* ATRG power iterations; 0 = 2*dcut, < 0 = none */
   uint64_t seed;          /* ATRG trial-matrix seed */
   void *stream;           /* hipStream_t; NULL = default stream */
   /* Device allocator.  NULL alloc = hipMalloc/hipFree.  alloc returns NULL on
@@ -122,8 +122,27 @@ int trg_hotrg_step(trg_ctx *ctx, int axis, int dcut);
  * (batched launches).  Results are identical to n separate calls. */
 int trg_hotrg_step_batch(trg_ctx *const *ctxs, int n, int axis, int dcut);
 
-/* ATRG step along `axis` (Sec. 2, Fig. 2).  Requires method == TRG_ATRG. */
+/* ATRG step along `axis` (Sec. 2, Fig. 2) with bond dimension `dcut`
+ * (1..256): canonical form of the factored tensor, the index-swapping partial
+ * SVD by randomized SVD (trial matrix N(0,1) from Philox4x32-10 keyed by
+ * (cfg->seed, step); cfg->rsvd_p oversampling, cfg->rsvd_q iterations;
+ * defaults p = 4 dcut, q = 2 dcut as in Sec. 3.2), the HOSVD isometries of
+ * the two adjacent decomposed tensors and the contraction completing the
+ * block-spin transformation; FP64 throughout, or the contraction GEMMs in
+ * FP32 when cfg->precision == TRG_FP32.  The context must have been created
+ * with method TRG_ATRG (trg_init_ising or trg_init_factors).  Asynchronous.
+ * Errors: TRG_EINVAL, TRG_ESTATE, TRG_ENOMEM, TRG_EHIP. */
 int trg_atrg_step(trg_ctx *ctx, int axis, int dcut);
+
+/* Create an ATRG context from host pieces T[b, f] = sum_l G[b, l] H[l, f]:
+ * G row-major (prod dims) x r with the d backward legs in axis order, H
+ * row-major r x (prod dims) with the forward legs.  No normalisation is
+ * applied.  For tests and checkpoint restore.  cfg->method must be ATRG. */
+int trg_init_factors(trg_ctx **out, int d, const int *dims, int r, const double *host_G,
+                     const double *host_H, const trg_config *cfg);
+
+/* Singular values (descending, *n of them) of the latest ATRG swap. */
+int trg_atrg_spectrum(trg_ctx *ctx, double *out, int cap, int *n);
 
 /* Coarse-grain the periodic lattice L^d (L = 2^m, m >= 1): d*m steps along
  * axis (n-1) mod d with cfg->dcut, using the context's method.  Synchronises

@@ -18,7 +18,10 @@ each choice below is listed in the design doc):
   the Ising tensor is exact (it has rank 2 in that bipartition); after a step
   the new tensor is already a product over one index of dim <= Dcut, so the
   "local SVD" is a canonicalisation (QR of both pieces, SVD of the small core)
-  and the approximations are the swap and the HOSVD.
+  and the approximations are the swap and the HOSVD.  The sign of each
+  singular-vector pair is fixed (largest entry of the left vector positive),
+  so that the randomized SVD, which is not converged for every input, sees
+  the same swap matrix in every implementation.
 * Step along mu with site A below and site B above: with
   Ut = U sqrt(s) and Vt = sqrt(s) V,
   M[(k_A, b^B_perp), (f^A_perp, k_B)] = sum_j Vt[k_A, f^A_perp, f_mu = j] Ut[b_mu = j, b^B_perp, k_B]
@@ -154,8 +157,18 @@ def canonical(G: np.ndarray, H: np.ndarray, dcut: int) -> Factors:
     Qh, Rh = np.linalg.qr(Hm.T)
     W, s, Zt = np.linalg.svd(Rg @ Rh.T)
     k = min(dcut, int(np.count_nonzero(s > 0)) or 1, len(s))
-    U = (Qg @ W[:, :k]).reshape(G.shape[:-1] + (k,))
-    V = (Zt[:k] @ Qh.T).reshape((k,) + H.shape[1:])
+    Um = Qg @ W[:, :k]
+    Vm = Zt[:k] @ Qh.T
+    # sign gauge: the first largest-modulus entry of each left singular
+    # vector (within a relative 1e-9) is positive; the right vector follows
+    for j in range(k):
+        col = np.abs(Um[:, j])
+        i = int(np.nonzero(col >= (1.0 - 1e-9) * col.max())[0][0])
+        if Um[i, j] < 0:
+            Um[:, j] = -Um[:, j]
+            Vm[j] = -Vm[j]
+    U = Um.reshape(G.shape[:-1] + (k,))
+    V = Vm.reshape((k,) + H.shape[1:])
     return Factors(U, s[:k], V)
 
 

@@ -57,6 +57,9 @@ SIGNATURES = {
     "trg_hotrg_step": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "trg_hotrg_step_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int]),
     "trg_atrg_step": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "trg_init_factors": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int), C.c_int,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(TrgConfig)]),
+    "trg_atrg_spectrum": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int)]),
     "trg_run": (C.c_int, [C.c_void_p, C.c_longlong]),
     "trg_free_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "trg_impure_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),

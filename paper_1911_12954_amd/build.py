@@ -11,7 +11,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["gemm.hip", "tensor.hip", "eigh.hip", "engine.hip"]
+SOURCES = ["gemm.hip", "tensor.hip", "eigh.hip", "engine.hip", "atrg.hip"]
 LIB = os.path.join(HERE, "libtrg.so")
 
 FLAGS = [

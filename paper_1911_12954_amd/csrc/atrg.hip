@@ -1,0 +1,971 @@
+// ATRG coarse-graining step (Sec. 2 and Fig. 2 of the paper) on the GPU.
+//
+// A site tensor is kept as two pieces T[b, f] = sum_l G[b, l] H[l, f]
+// (b: the d backward legs, f: the d forward legs; D^{d+1} elements each).
+// One step along mu:
+//   1. canonical form T = U diag(s) V: QR of G and of H^T (shifted
+//      CholeskyQR3) and the SVD of the small core, obtained from the
+//      eigendecomposition of [[0, C], [C^T, 0]] (no squared condition number);
+//      each singular-vector pair signed so that the first largest entry of
+//      the left vector is positive;
+//   2. the swap (dark-blue tensors of Fig. 2B): the matrix
+//      M[(kA, b_perp), (f_perp, kB)] = sum_j Vt[kA, f_perp, j] Ut[j, b_perp, kB]
+//      (Ut = U sqrt(s), Vt = sqrt(s) V) is truncated to rank Dcut by a
+//      randomized SVD whose products M Z and M^T Z are applied in factored
+//      form (two GEMMs each, 2 D^{d+2} r flops), with a Philox4x32-10 +
+//      Box-Muller Gaussian trial matrix and q re-orthonormalised iterations;
+//   3. HOSVD of the two-site product sum_l G H: Gram matrices of each
+//      transverse leg pair in factored form (D^{d+3}), eigendecomposition and
+//      the isometry selection shared with HOTRG;
+//   4. the contraction that completes the block-spin transformation (red
+//      dotted circle of Fig. 2B): the isometries applied to both pieces, the
+//      dominant GEMM has M = D^4, K = D^2, N = D^3 in 4D;
+//   5. normalisation c = sqrt(Tr[(G'^T G')(H' H'^T)]), pieces scaled by
+//      c^{-1/2}, acc += 2^{-n} ln c.
+// Contractions of named legs go through einsum2: both operands are packed
+// (K-contiguous, zero-padded) by the strided map kernel and multiplied by the
+// MFMA GEMM of the HOTRG join.
+#include <cmath>
+#include <cstdlib>
+
+#include "context.h"
+
+namespace trg {
+namespace {
+
+// ------------------------------------------------------------------ kernels ---
+// U0[b, sigma] = e^{beta h sigma/2} prod_nu W[sigma, b_nu]; H0[sigma, b] the same
+__global__ void atrg_ising_kernel(double *G, double *H, int d, double beta, double h) {
+  const int n = 1 << d;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * n) return;
+  const int sig = idx & 1, b = idx >> 1;
+  const double spin = sig == 0 ? 1.0 : -1.0;
+  const double c = sqrt(cosh(beta)), s = sqrt(sinh(beta));
+  double v = exp(0.5 * beta * h * spin);
+  for (int a = 0; a < d; ++a) v *= ((b >> (d - 1 - a)) & 1) ? spin * s : c;
+  G[b * 2 + sig] = v;
+  H[sig * n + b] = v;
+}
+
+// Philox4x32 with 10 rounds (Salmon et al., SC'11)
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = uint64_t(0xD2511F53u) * c[0];
+    const uint64_t p1 = uint64_t(0xCD9E8D57u) * c[2];
+    const uint32_t hi0 = uint32_t(p0 >> 32), lo0 = uint32_t(p0);
+    const uint32_t hi1 = uint32_t(p1 >> 32), lo1 = uint32_t(p1);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// Omega[e] for e < count: counter (e, step, 0, 0), key (k0, k1); Box-Muller
+// sqrt(-2 ln u1) cos(2 pi u2) with u = (w + 0.5) / 2^32
+__global__ void trial_kernel(double *out, uint32_t count, uint32_t step, uint32_t k0, uint32_t k1) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  uint32_t c[4] = {e, step, 0u, 0u};
+  philox4x32_10(c, k0, k1);
+  const double u1 = (double(c[0]) + 0.5) / 4294967296.0;
+  const double u2 = (double(c[1]) + 0.5) / 4294967296.0;
+  out[e] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+// Upper Cholesky factor R of C + shift I (shift = shift_coef * trace C) and
+// the matrix Rinv that maps Y to Q = Y Rinv; one workgroup, n <= 1024.  A
+// pivot at or below 1e-26 of the largest diagonal entry marks its column as
+// numerically dependent on the previous ones (rank-deficient Y): that column
+// of Q is set to zero (column of Rinv zero) and its row of R is zero, so
+// Y = Q R still holds and no division by a vanishing pivot occurs.
+__global__ void __launch_bounds__(256)
+chol_inv_kernel(const double *C, int n, double shift_coef, double *R, double *Rinv, int *err) {
+  __shared__ double sh[256];
+  __shared__ double shm[256];
+  __shared__ int dead[1024];
+  const int t = threadIdx.x;
+  double tr = 0.0, mx = 0.0;
+  for (int i = t; i < n; i += 256) {
+    tr += C[i * n + i];
+    mx = fmax(mx, C[i * n + i]);
+  }
+  sh[t] = tr;
+  shm[t] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      sh[t] += sh[t + s];
+      shm[t] = fmax(shm[t], shm[t + s]);
+    }
+    __syncthreads();
+  }
+  const double shift = shift_coef * sh[0];
+  const double tol = 1e-26 * (shm[0] + shift);
+  __syncthreads();
+  for (int i = t; i < n * n; i += 256) {
+    const int r = i / n, c = i % n;
+    R[i] = r <= c ? C[i] + (r == c ? shift : 0.0) : 0.0;
+    Rinv[i] = 0.0;
+  }
+  for (int i = t; i < n; i += 256) dead[i] = 0;
+  __syncthreads();
+  // row j of R from the rows above it
+  for (int j = 0; j < n; ++j) {
+    if (t == 0) {
+      double dj = R[j * n + j];
+      for (int k = 0; k < j; ++k) dj -= R[k * n + j] * R[k * n + j];
+      if (!(dj > tol)) {
+        if (!(dj > -1e3 * tol) && !isfinite(dj)) *err |= 4;
+        dead[j] = 1;
+        dj = 1.0;
+      }
+      R[j * n + j] = sqrt(dj);
+    }
+    __syncthreads();
+    const double rjj = R[j * n + j];
+    const bool dj_dead = dead[j] != 0;
+    for (int i = j + 1 + t; i < n; i += 256) {
+      double v = R[j * n + i];
+      for (int k = 0; k < j; ++k) v -= R[k * n + j] * R[k * n + i];
+      R[j * n + i] = dj_dead ? 0.0 : v / rjj;
+    }
+    __syncthreads();
+  }
+  // inverse of the upper triangular R (dead rows are unit rows of R), one
+  // column per thread; then dead columns of Rinv and dead rows of R vanish
+  for (int j = t; j < n; j += 256) {
+    for (int i = j; i >= 0; --i) {
+      double v = (i == j) ? 1.0 : 0.0;
+      for (int k = i + 1; k <= j; ++k) v -= R[i * n + k] * Rinv[k * n + j];
+      Rinv[i * n + j] = v / R[i * n + i];
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n * n; i += 256) {
+    const int r = i / n, c = i % n;
+    if (dead[c]) Rinv[i] = 0.0;
+    if (dead[r]) R[i] = 0.0;
+  }
+}
+
+// C = A B for n x n matrices (one workgroup)
+__global__ void small_matmul_kernel(const double *A, const double *B, double *C, int n) {
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+    const int r = i / n, c = i % n;
+    double v = 0.0;
+    for (int k = 0; k < n; ++k) v += A[r * n + k] * B[k * n + c];
+    C[i] = v;
+  }
+}
+
+// J = [[0, C], [C^T, 0]] (2n x 2n) for C (n x n)
+__global__ void jw_build_kernel(const double *C, int n, double *J) {
+  const int m = 2 * n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m * m; i += gridDim.x * blockDim.x) {
+    const int r = i / m, c = i % m;
+    double v = 0.0;
+    if (r < n && c >= n) v = C[r * n + (c - n)];
+    if (r >= n && c < n) v = C[c * n + (r - n)];
+    J[i] = v;
+  }
+}
+
+// From the sorted eigensystem of J: s[i] = max(w[i], 0), sqrt_s[i],
+// W[:, i] = sqrt(2) V[0:n, i], Z[:, i] = sqrt(2) V[n:2n, i] for i < k
+__global__ void jw_extract_kernel(const double *w, const double *V, int n, int k, double *s, double *sqs,
+                                  double *W, double *Z) {
+  const int m = 2 * n;
+  const double r2 = 1.4142135623730951;
+  for (int i = threadIdx.x; i < n * k; i += blockDim.x) {
+    const int row = i / k, col = i % k;
+    W[row * k + col] = r2 * V[row * m + col];
+    Z[row * k + col] = r2 * V[(n + row) * m + col];
+  }
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const double v = w[i] > 0.0 ? w[i] : 0.0;
+    s[i] = v;
+    sqs[i] = sqrt(v);
+  }
+}
+
+// Sign gauge of the canonical form: for column j of U (n x k), the first
+// entry whose modulus is within a relative 1e-9 of the column maximum is made
+// positive: out[j] = sign * sqs[j] (one block per column).
+__global__ void __launch_bounds__(256)
+sign_gauge_kernel(const double *U, int64_t n, int k, const double *sqs, double *out) {
+  __shared__ double sh[256];
+  __shared__ long long si[256];
+  const int j = blockIdx.x, t = threadIdx.x;
+  double mx = 0.0;
+  for (int64_t i = t; i < n; i += 256) mx = fmax(mx, fabs(U[i * k + j]));
+  sh[t] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  const double thr = (1.0 - 1e-9) * sh[0];
+  __syncthreads();
+  long long first = n;
+  for (int64_t i = t; i < n; i += 256)
+    if (fabs(U[i * k + j]) >= thr && i < first) first = i;
+  si[t] = first;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) si[t] = si[t] < si[t + s] ? si[t] : si[t + s];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const long long r = si[0] < n ? si[0] : 0;
+    out[j] = (U[r * k + j] < 0.0 ? -1.0 : 1.0) * sqs[j];
+  }
+}
+
+// c^2 = sum_ij GtG[i,j] HHt[i,j]; scal[0] = c, scal[1] = c^{-1/2}, scal[2] = ln c
+__global__ void atrg_norm_kernel(const double *GtG, const double *HHt, int r, double *scal, double *acc,
+                                 double weight, int *err) {
+  __shared__ double sh[256];
+  const int t = threadIdx.x;
+  double v = 0.0;
+  for (int i = t; i < r * r; i += 256) v += GtG[i] * HHt[i];
+  sh[t] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double c = sqrt(sh[0]);
+    const bool ok = c > 0.0 && isfinite(c);
+    scal[0] = c;
+    scal[1] = ok ? 1.0 / sqrt(c) : 0.0;
+    scal[2] = ok ? log(c) : 0.0;
+    if (ok) acc[0] += weight * log(c);
+    else *err |= 1;
+  }
+}
+
+// out = sum_{b, l} G[b * r + l] H[l * n + b] (deterministic: fixed block sums, then one block)
+__global__ void __launch_bounds__(256) gh_trace_partial(const double *G, const double *H, int64_t n, int r,
+                                                        double *partial) {
+  __shared__ double sh[256];
+  const int64_t total = n * r;
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = int64_t(blockIdx.x) * per;
+  const int64_t e = b0 + per < total ? b0 + per : total;
+  double v = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < e; i += 256) {
+    const int64_t b = i / r, l = i % r;
+    v += G[i] * H[l * n + b];
+  }
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) sum_partials(const double *partial, int nb, double *out) {
+  __shared__ double sh[256];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) v += partial[i];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// ------------------------------------------------------------- host helpers ---
+void dbg(trg_ctx &c, const char *name, const double *p, int64_t count) {
+  static const bool on = std::getenv("TRG_DEBUG") != nullptr;
+  if (!on) return;
+  TRG_HIP_CHECK(hipStreamSynchronize(c.st));
+  std::vector<double> h(static_cast<size_t>(count));
+  TRG_HIP_CHECK(hipMemcpy(h.data(), p, size_t(count) * 8, hipMemcpyDeviceToHost));
+  double mx = 0, s2 = 0;
+  int64_t bad = 0;
+  for (double v : h) {
+    if (!std::isfinite(v)) ++bad;
+    else {
+      mx = std::max(mx, std::fabs(v));
+      s2 += v * v;
+    }
+  }
+  int e = 0;
+  TRG_HIP_CHECK(hipMemcpy(&e, c.errp(), 4, hipMemcpyDeviceToHost));
+  std::fprintf(stderr, "[trg debug] %-10s n=%lld nonfinite=%lld max=%.3e norm=%.6e err=%d first=%.6e\n", name,
+               (long long)count, (long long)bad, mx, std::sqrt(s2), e, h.empty() ? 0.0 : h[0]);
+}
+
+std::vector<std::pair<std::string, int64_t>> legs_of(const View &v) {
+  std::vector<std::pair<std::string, int64_t>> out;
+  for (const auto &l : v) out.push_back({l.name, l.size});
+  return out;
+}
+
+View pick(const View &v, const std::vector<std::string> &names) {
+  View out;
+  for (const auto &n : names) out.push_back(find_leg(v, n));
+  return out;
+}
+
+// Orthonormalise the columns of the m x k row-major matrix Y (m >= k) by
+// shifted CholeskyQR3 (Fukaya et al.): three passes of Y <- Y R^{-1} with
+// R^T R = Y^T Y (+ a shift of 11 (mk + k(k+1)) u tr(Y^T Y) on the first pass
+// so that the Cholesky factorisation exists for ill-conditioned Y).  Q must
+// not alias Y; Rout (optional) receives R = R3 R2 R1 with Y = Q R.
+void cholqr3(trg_ctx &c, const double *Y, int64_t m, int k, double *Q, double *Rout, const std::string &tag) {
+  TRG_REQUIRE(m >= k && k >= 1 && k <= 1024, "cholqr: bad shape");
+  TRG_REQUIRE(Q != Y, "cholqr: output aliases input");
+  double *Cg = c.wsp<double>("qrC" + tag, size_t(k) * k * 8);
+  double *R = c.wsp<double>("qrR" + tag, size_t(k) * k * 8);
+  double *Ri = c.wsp<double>("qrRi" + tag, size_t(k) * k * 8);
+  double *Racc = c.wsp<double>("qrRa" + tag, size_t(k) * k * 8);
+  double *Rtmp = c.wsp<double>("qrRt" + tag, size_t(k) * k * 8);
+  double *bufA = c.wsp<double>("qrA" + tag, size_t(m) * k * 8);
+  double *bufB = c.wsp<double>("qrB" + tag, size_t(m) * k * 8);
+  const View vy = contiguous({{"i", m}, {"c", k}});
+  const View vk = contiguous({{"i", m}, {"k", k}});
+  const double u = std::ldexp(1.0, -53);
+  const double *src = Y;
+  for (int pass = 0; pass < 3; ++pass) {
+    einsum2(c, src, vy, src, rename(vy, {{"c", "c2"}}), Cg, {"c", "c2"}, TRG_FP64, "qr" + tag);
+    const double shift = pass == 0 ? 11.0 * (double(m) * k + double(k) * (k + 1)) * u : 0.0;
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, c.st, Cg, k, shift, R, Ri, c.errp());
+    TRG_HIP_CHECK(hipGetLastError());
+    double *dst = pass == 2 ? Q : (pass == 0 ? bufA : bufB);
+    apply_map(src, IN_F64, vk, Ri, {{"k", int64_t(k)}, {"c", 1}}, {"k"}, dst, OUT_F64, 0, vy, c.st);
+    if (Rout) {
+      if (pass == 0) {
+        TRG_HIP_CHECK(hipMemcpyAsync(Racc, R, size_t(k) * k * 8, hipMemcpyDeviceToDevice, c.st));
+      } else {
+        hipLaunchKernelGGL(small_matmul_kernel, dim3(1), dim3(256), 0, c.st, R, Racc, Rtmp, k);
+        TRG_HIP_CHECK(hipGetLastError());
+        TRG_HIP_CHECK(hipMemcpyAsync(Racc, Rtmp, size_t(k) * k * 8, hipMemcpyDeviceToDevice, c.st));
+      }
+    }
+    src = dst;
+  }
+  if (Rout) TRG_HIP_CHECK(hipMemcpyAsync(Rout, Racc, size_t(k) * k * 8, hipMemcpyDeviceToDevice, c.st));
+}
+
+// SVD of the k x k matrix Cm = W diag(s) Z^T through the eigendecomposition
+// of [[0, Cm], [Cm^T, 0]]; keeps the first kk columns.
+void small_svd(trg_ctx &c, const double *Cm, int k, int kk, double *s, double *sqs, double *W, double *Z,
+               const std::string &tag) {
+  const int m = 2 * k;
+  double *J = c.wsp<double>("svdJ" + tag, size_t(m) * m * 8);
+  double *w = c.wsp<double>("svdw" + tag, size_t(m) * 8);
+  double *V = c.wsp<double>("svdV" + tag, size_t(m) * m * 8);
+  int *sw = c.wsp<int>("svdsw" + tag, 16);
+  hipLaunchKernelGGL(jw_build_kernel, dim3(64), dim3(256), 0, c.st, Cm, k, J);
+  TRG_HIP_CHECK(hipGetLastError());
+  eigh_batched(J, w, V, sw, m, 1, c.st);
+  hipLaunchKernelGGL(jw_extract_kernel, dim3(1), dim3(256), 0, c.st, w, V, k, kk, s, sqs, W, Z);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ einsum2 ---
+void einsum2(trg_ctx &c, const double *A, const View &va, const double *B, const View &vb, double *C,
+             const std::vector<std::string> &out_names, int prec, const std::string &tag) {
+  std::vector<std::string> con, fa, fb;
+  for (const auto &l : va)
+    if (has_leg(vb, l.name)) con.push_back(l.name);
+  for (const auto &n : out_names) {
+    if (has_leg(va, n) && !has_leg(vb, n)) fa.push_back(n);
+    else if (has_leg(vb, n) && !has_leg(va, n)) fb.push_back(n);
+    else throw Error(-1, "einsum2: output leg " + n + " must belong to exactly one operand");
+  }
+  TRG_REQUIRE(!con.empty(), "einsum2: no contracted leg");
+  TRG_REQUIRE(fa.size() + fb.size() + con.size() * 2 == va.size() + vb.size(), "einsum2: stray leg");
+  int64_t M = 1, N = 1, K = 1;
+  std::vector<std::pair<std::string, int64_t>> ra, rb, kc;
+  for (const auto &n : fa) {
+    ra.push_back({n, find_leg(va, n).size});
+    M *= ra.back().second;
+  }
+  for (const auto &n : fb) {
+    rb.push_back({n, find_leg(vb, n).size});
+    N *= rb.back().second;
+  }
+  for (const auto &n : con) {
+    const int64_t s = find_leg(va, n).size;
+    TRG_REQUIRE(s == find_leg(vb, n).size, "einsum2: contracted leg sizes differ");
+    kc.push_back({n, s});
+    K *= s;
+  }
+  const GemmTile t = gemm_tile(prec);
+  const int64_t Mp = int64_t(round_up(M, t.m)), Np = int64_t(round_up(N, t.n)), Kp = int64_t(round_up(K, t.k));
+  const int esz = prec == TRG_FP64 ? 8 : 4;
+  const int okind = prec == TRG_FP64 ? OUT_F64 : OUT_F32;
+  void *Ap = c.wsp<char>("e2A" + tag, size_t(Mp) * Kp * esz);
+  void *Bp = c.wsp<char>("e2B" + tag, size_t(Np) * Kp * esz);
+  View pa = contiguous(ra, Kp), pb = contiguous(rb, Kp), pk = contiguous(kc);
+  pa.insert(pa.end(), pk.begin(), pk.end());
+  pb.insert(pb.end(), pk.begin(), pk.end());
+  apply_map(A, IN_F64, va, nullptr, {}, {}, Ap, okind, 0, pa, c.st);
+  zero_pad(Ap, M, Mp, K, Kp, esz, 1, 0, c.st);
+  apply_map(B, IN_F64, vb, nullptr, {}, {}, Bp, okind, 0, pb, c.st);
+  zero_pad(Bp, N, Np, K, Kp, esz, 1, 0, c.st);
+  // the GEMM writes C directly when the output is [fa, fb] unpadded in FP64
+  std::vector<std::string> natural = fa;
+  natural.insert(natural.end(), fb.begin(), fb.end());
+  const bool direct = prec == TRG_FP64 && Mp == M && Np == N && natural == out_names;
+  void *Cp = direct ? static_cast<void *>(C) : c.wsp<char>("e2C" + tag, size_t(Mp) * Np * esz);
+  // the ATRG contraction GEMMs ("k2") are the timed kernel of an ATRG step
+  const bool timed = c.profiling && tag == "k2";
+  hipEvent_t e0{}, e1{};
+  if (timed) {
+    TRG_HIP_CHECK(hipEventCreate(&e0));
+    TRG_HIP_CHECK(hipEventCreate(&e1));
+    TRG_HIP_CHECK(hipEventRecord(e0, c.st));
+  }
+  gemm_nt(prec, Ap, Bp, Cp, uint64_t(Mp), uint64_t(Np), uint64_t(Kp), uint64_t(Kp), uint64_t(Kp), uint64_t(Np),
+          false, c.st);
+  if (timed) {
+    TRG_HIP_CHECK(hipEventRecord(e1, c.st));
+    c.join_events.push_back({e0, e1});
+    c.join_launches += 1;
+    c.join_flops_pending += 2.0 * double(M) * double(N) * double(K);
+  }
+  if (direct) return;
+  View cv = contiguous(ra, Np), cb = contiguous(rb);
+  cv.insert(cv.end(), cb.begin(), cb.end());
+  std::vector<std::pair<std::string, int64_t>> ol;
+  for (const auto &n : out_names) ol.push_back({n, has_leg(va, n) ? find_leg(va, n).size : find_leg(vb, n).size});
+  apply_map(Cp, prec == TRG_FP64 ? IN_F64 : IN_F32, cv, nullptr, {}, {}, C, OUT_F64, 0, contiguous(ol), c.st);
+}
+
+// --------------------------------------------------------------- init / step ---
+void atrg_init_ising(trg_ctx &c, double beta, double h) {
+  const int d = c.d;
+  const int64_t n = int64_t(1) << d;
+  c.r = 2;
+  c.ensure(c.G, size_t(n) * 2 * 8);
+  c.ensure(c.H, size_t(n) * 2 * 8);
+  double *G = static_cast<double *>(c.G.ptr), *H = static_cast<double *>(c.H.ptr);
+  hipLaunchKernelGGL(atrg_ising_kernel, dim3(1), dim3(64), 0, c.st, G, H, d, beta, h);
+  TRG_HIP_CHECK(hipGetLastError());
+  // c_0 = ||G H||_F, both pieces scaled by c_0^{-1/2}
+  double *GtG = c.wsp<double>("nGtG", 4 * 8), *HHt = c.wsp<double>("nHHt", 4 * 8);
+  View vg = contiguous({{"b", n}, {"l", 2}}), vh = contiguous({{"l", 2}, {"f", n}});
+  einsum2(c, G, vg, G, rename(vg, {{"l", "l2"}}), GtG, {"l", "l2"}, TRG_FP64, "nrm");
+  einsum2(c, H, vh, H, rename(vh, {{"l", "l2"}}), HHt, {"l", "l2"}, TRG_FP64, "nrm");
+  hipLaunchKernelGGL(atrg_norm_kernel, dim3(1), dim3(256), 0, c.st, GtG, HHt, 2, c.scal(), c.scal() + 3, 1.0,
+                     c.errp());
+  TRG_HIP_CHECK(hipGetLastError());
+  dbg(c, "init G", G, n * 2);
+  dbg(c, "init GtG", GtG, 4);
+  dbg(c, "init HHt", HHt, 4);
+  scale_by_inverse(G, n * 2, c.scal(), 1.0, c.st);
+  scale_by_inverse(H, n * 2, c.scal(), 1.0, c.st);
+  dbg(c, "init scal", c.scal(), 4);
+  TRG_HIP_CHECK(hipMemcpyAsync(rec_d(c, 0), c.scal() + 2, 8, hipMemcpyDeviceToDevice, c.st));
+}
+
+double atrg_trace(trg_ctx &c) {
+  int64_t n = 1;
+  for (int a = 0; a < c.d; ++a) n *= c.dims[a];
+  const int nb = 256;
+  double *partial = c.wsp<double>("trpart", nb * 8);
+  hipLaunchKernelGGL(gh_trace_partial, dim3(nb), dim3(256), 0, c.st, static_cast<const double *>(c.G.ptr),
+                     static_cast<const double *>(c.H.ptr), n, c.r, partial);
+  TRG_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, c.st, partial, nb, c.scal() + 4);
+  TRG_HIP_CHECK(hipGetLastError());
+  sync_check(c);
+  double v = 0.0;
+  TRG_HIP_CHECK(hipMemcpy(&v, c.scal() + 4, 8, hipMemcpyDeviceToHost));
+  return v;
+}
+
+void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
+  const int d = c.d;
+  const int r = c.r;
+  const hipStream_t st = c.st;
+  int dims[4] = {0, 0, 0, 0};
+  int64_t n = 1;
+  for (int a = 0; a < d; ++a) {
+    dims[a] = c.dims[a];
+    n *= dims[a];
+  }
+  std::vector<int> perp;
+  for (int a = 0; a < d; ++a)
+    if (a != mu) perp.push_back(a);
+  int64_t nperp = 1;
+  for (int a : perp) nperp *= dims[a];
+  // 0 selects the paper's values (p = 4 Dcut, q = 2 Dcut); negative means none
+  const int p = c.cfg.rsvd_p > 0 ? c.cfg.rsvd_p : (c.cfg.rsvd_p == 0 ? 4 * dcut : 0);
+  const int q = c.cfg.rsvd_q > 0 ? c.cfg.rsvd_q : (c.cfg.rsvd_q == 0 ? 2 * dcut : 0);
+  const int cprec = c.cfg.precision == TRG_FP32 ? TRG_FP32 : TRG_FP64;
+  const int n_step = c.nsteps + 1;
+  ensure_records(c, n_step + 1);
+  double *rd = rec_d(c, n_step);
+  int *ri = rec_i(c, n_step);
+  const double *Gp = static_cast<const double *>(c.G.ptr);
+  const double *Hp = static_cast<const double *>(c.H.ptr);
+
+  // names of the canonical legs
+  std::vector<std::string> bn, fn;
+  for (int a = 0; a < d; ++a) {
+    bn.push_back(nm("b", a));
+    fn.push_back(nm("f", a));
+  }
+
+  // ---- 1. canonical form T = U diag(s) V
+  TRG_REQUIRE(n >= r, "atrg: piece has fewer rows than its rank");
+  const int k = r < dcut ? r : dcut;
+  double *Qg = c.wsp<double>("cQg", size_t(n) * r * 8);
+  double *Qh = c.wsp<double>("cQh", size_t(n) * r * 8);
+  double *HT = c.wsp<double>("cHT", size_t(n) * r * 8);
+  double *Rg = c.wsp<double>("cRg", size_t(r) * r * 8);
+  double *Rh = c.wsp<double>("cRh", size_t(r) * r * 8);
+  double *Cm = c.wsp<double>("cCm", size_t(r) * r * 8);
+  dbg(c, "G", Gp, n * r);
+  dbg(c, "H", Hp, n * r);
+  cholqr3(c, Gp, n, r, Qg, Rg, "g");
+  dbg(c, "Qg", Qg, n * r);
+  dbg(c, "Rg", Rg, int64_t(r) * r);
+  apply_map(Hp, IN_F64, contiguous({{"l", r}, {"f", n}}), nullptr, {}, {}, HT, OUT_F64, 0,
+            contiguous({{"f", n}, {"l", r}}), st);
+  cholqr3(c, HT, n, r, Qh, Rh, "h");
+  // core = Rg Rh^T
+  einsum2(c, Rg, contiguous({{"i", r}, {"j", r}}), Rh, contiguous({{"m", r}, {"j", r}}), Cm, {"i", "m"},
+          TRG_FP64, "core");
+  double *s = c.wsp<double>("cs", size_t(k) * 8), *sqs = c.wsp<double>("csq", size_t(k) * 8);
+  double *W = c.wsp<double>("cW", size_t(r) * k * 8), *Z = c.wsp<double>("cZ", size_t(r) * k * 8);
+  dbg(c, "Cm", Cm, int64_t(r) * r);
+  small_svd(c, Cm, r, k, s, sqs, W, Z, "core");
+  dbg(c, "s", s, k);
+  dbg(c, "W", W, int64_t(r) * k);
+  // Ut[b..., k] = Qg W sqrt(s); Vt[k, f...] = sqrt(s) (Qh Z)^T
+  double *Ut = c.wsp<double>("Ut", size_t(n) * k * 8);
+  double *Vt = c.wsp<double>("Vt", size_t(n) * k * 8);
+  {
+    double *tmp = c.wsp<double>("cUtmp", size_t(n) * k * 8);
+    double *ssq = c.wsp<double>("cssq", size_t(k) * 8);  // sign * sqrt(s)
+    einsum2(c, Qg, contiguous({{"i", n}, {"j", r}}), W, contiguous({{"j", r}, {"k", k}}), tmp, {"i", "k"},
+            TRG_FP64, "cu");
+    hipLaunchKernelGGL(sign_gauge_kernel, dim3(k), dim3(256), 0, st, tmp, n, k, sqs, ssq);
+    TRG_HIP_CHECK(hipGetLastError());
+    apply_map(tmp, IN_F64, contiguous({{"i", n}, {"k", k}}), ssq, {{"k", 1}}, {}, Ut, OUT_F64, 0,
+              contiguous({{"i", n}, {"k", k}}), st);
+    einsum2(c, Qh, contiguous({{"i", n}, {"j", r}}), Z, contiguous({{"j", r}, {"k", k}}), tmp, {"i", "k"},
+            TRG_FP64, "cu");
+    apply_map(tmp, IN_F64, contiguous({{"i", n}, {"k", k}}), ssq, {{"k", 1}}, {}, Vt, OUT_F64, 0,
+              contiguous({{"k", k}, {"i", n}}), st);
+  }
+  // views: Ut[b0..b_{d-1}, kk], Vt[kk, f0..f_{d-1}]
+  std::vector<std::pair<std::string, int64_t>> lb, lf;
+  for (int a = 0; a < d; ++a) lb.push_back({bn[a], dims[a]});
+  lb.push_back({"kk", k});
+  lf.push_back({"kk", k});
+  for (int a = 0; a < d; ++a) lf.push_back({fn[a], dims[a]});
+  const View vUt = contiguous(lb), vVt = contiguous(lf);
+
+  // ---- 2. swap by randomized SVD of M[(kA, b_perp), (f_perp, kB)]
+  // M Z: t[kA, j, kB, c] = sum_f Vt[kA, f_perp, j] Z[f_perp, kB, c];
+  //      out[kA, b_perp, c] = sum_{j, kB} t Ut[j, b_perp, kB]
+  const View vVA = rename(vVt, {{"kk", "kA"}, {fn[mu], "j"}});
+  const View vUB = rename(vUt, {{"kk", "kB"}, {bn[mu], "j"}});
+  const int64_t nsw = int64_t(k) * nperp;
+  int r2 = dcut + p;
+  if (r2 > nsw) r2 = int(nsw);
+  std::vector<std::string> fperp, bperp;
+  for (int a : perp) {
+    fperp.push_back(fn[a]);
+    bperp.push_back(bn[a]);
+  }
+  auto zview = [&](int64_t cols) {  // rows (f_perp, kB)
+    std::vector<std::pair<std::string, int64_t>> l;
+    for (int a : perp) l.push_back({fn[a], dims[a]});
+    l.push_back({"kB", k});
+    l.push_back({"c", cols});
+    return contiguous(l);
+  };
+  auto qview = [&](int64_t cols) {  // rows (kA, b_perp)
+    std::vector<std::pair<std::string, int64_t>> l;
+    l.push_back({"kA", k});
+    for (int a : perp) l.push_back({bn[a], dims[a]});
+    l.push_back({"c", cols});
+    return contiguous(l);
+  };
+  double *tbuf = c.wsp<double>("swT", size_t(k) * dims[mu] * k * r2 * 8);
+  auto apply_M = [&](const double *Zin, double *out) {
+    einsum2(c, Vt, vVA, Zin, zview(r2), tbuf, {"kA", "j", "kB", "c"}, TRG_FP64, "sw1");
+    const View vt = contiguous({{"kA", k}, {"j", dims[mu]}, {"kB", k}, {"c", r2}});
+    std::vector<std::string> o{"kA"};
+    o.insert(o.end(), bperp.begin(), bperp.end());
+    o.push_back("c");
+    einsum2(c, tbuf, vt, Ut, vUB, out, o, TRG_FP64, "sw2");
+  };
+  auto apply_MT = [&](const double *Qin, double *out) {
+    einsum2(c, Ut, vUB, Qin, qview(r2), tbuf, {"j", "kB", "kA", "c"}, TRG_FP64, "sw3");
+    const View vt = contiguous({{"j", dims[mu]}, {"kB", k}, {"kA", k}, {"c", r2}});
+    std::vector<std::string> o = fperp;
+    o.push_back("kB");
+    o.push_back("c");
+    einsum2(c, Vt, vVA, tbuf, vt, out, o, TRG_FP64, "sw4");
+  };
+  double *Om = c.wsp<double>("swOm", size_t(nsw) * r2 * 8);
+  double *Yb = c.wsp<double>("swY", size_t(nsw) * r2 * 8);
+  double *Qb = c.wsp<double>("swQ", size_t(nsw) * r2 * 8);
+  double *Zb = c.wsp<double>("swZ", size_t(nsw) * r2 * 8);
+  {
+    const uint64_t cnt = uint64_t(nsw) * r2;
+    TRG_REQUIRE(cnt < (1ull << 32), "atrg: trial matrix too large");
+    const uint64_t seed = c.cfg.seed;
+    hipLaunchKernelGGL(trial_kernel, dim3(uint32_t((cnt + 255) / 256)), dim3(256), 0, st, Om, uint32_t(cnt),
+                       uint32_t(n_step), uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32));
+    TRG_HIP_CHECK(hipGetLastError());
+  }
+  dbg(c, "Ut", Ut, n * k);
+  dbg(c, "Vt", Vt, n * k);
+  dbg(c, "Om", Om, nsw * r2);
+  apply_M(Om, Yb);
+  dbg(c, "MOm", Yb, nsw * r2);
+  cholqr3(c, Yb, nsw, r2, Qb, nullptr, "sw");
+  dbg(c, "Q0", Qb, nsw * r2);
+  for (int it = 0; it < q; ++it) {
+    apply_MT(Qb, Yb);
+    cholqr3(c, Yb, nsw, r2, Zb, nullptr, "sw");
+    apply_M(Zb, Yb);
+    cholqr3(c, Yb, nsw, r2, Qb, nullptr, "sw");
+  }
+  // Bt = M^T Q = Qbt Rb; Q^T M = Rb^T Qbt^T; SVD of Rb^T
+  double *Rb = c.wsp<double>("swRb", size_t(r2) * r2 * 8);
+  double *RbT = c.wsp<double>("swRbT", size_t(r2) * r2 * 8);
+  apply_MT(Qb, Yb);
+  cholqr3(c, Yb, nsw, r2, Zb, Rb, "sw");
+  apply_map(Rb, IN_F64, contiguous({{"i", r2}, {"j", r2}}), nullptr, {}, {}, RbT, OUT_F64, 0,
+            contiguous({{"j", r2}, {"i", r2}}), st);
+  const int dc = r2 < dcut ? r2 : dcut;
+  double *sig = c.wsp<double>("swsig", size_t(dc) * 8), *sqsig = c.wsp<double>("swsq", size_t(dc) * 8);
+  double *Wb = c.wsp<double>("swW", size_t(r2) * dc * 8), *Zs = c.wsp<double>("swZs", size_t(r2) * dc * 8);
+  dbg(c, "Rb", Rb, int64_t(r2) * r2);
+  small_svd(c, RbT, r2, dc, sig, sqsig, Wb, Zs, "sw");
+  dbg(c, "sigma", sig, dc);
+  // Xs[kA, b_perp, l] = Q W sqrt(sigma); Ys[l, f_perp, kB] = sqrt(sigma) (Qbt Z)^T
+  double *Xs = c.wsp<double>("Xs", size_t(nsw) * dc * 8);
+  double *Ys = c.wsp<double>("Ys", size_t(nsw) * dc * 8);
+  {
+    double *tmp = c.wsp<double>("swtmp", size_t(nsw) * dc * 8);
+    einsum2(c, Qb, contiguous({{"i", nsw}, {"j", r2}}), Wb, contiguous({{"j", r2}, {"l", dc}}), tmp, {"i", "l"},
+            TRG_FP64, "sx");
+    apply_map(tmp, IN_F64, contiguous({{"i", nsw}, {"l", dc}}), sqsig, {{"l", 1}}, {}, Xs, OUT_F64, 0,
+              contiguous({{"i", nsw}, {"l", dc}}), st);
+    einsum2(c, Zb, contiguous({{"i", nsw}, {"j", r2}}), Zs, contiguous({{"j", r2}, {"l", dc}}), tmp, {"i", "l"},
+            TRG_FP64, "sx");
+    apply_map(tmp, IN_F64, contiguous({{"i", nsw}, {"l", dc}}), sqsig, {{"l", 1}}, {}, Ys, OUT_F64, 0,
+              contiguous({{"l", dc}, {"i", nsw}}), st);
+  }
+  c.ensure(c.atrg_sigma, size_t(dc) * 8);
+  TRG_HIP_CHECK(hipMemcpyAsync(c.atrg_sigma.ptr, sig, size_t(dc) * 8, hipMemcpyDeviceToDevice, st));
+  c.atrg_nsig = dc;
+  // views of the pieces' factors
+  View vXs, vYs;
+  {
+    std::vector<std::pair<std::string, int64_t>> l{{"kA", k}};
+    for (int a : perp) l.push_back({nm("bB", a), dims[a]});
+    l.push_back({"l", dc});
+    vXs = contiguous(l);
+    std::vector<std::pair<std::string, int64_t>> m{{"l", dc}};
+    for (int a : perp) m.push_back({nm("fA", a), dims[a]});
+    m.push_back({"kB", k});
+    vYs = contiguous(m);
+  }
+  View vUA = vUt, vVB = vVt;  // site A backward legs (Ut), site B forward legs (Vt)
+  for (int a = 0; a < d; ++a) {
+    vUA = rename(vUA, {{bn[a], nm("bA", a)}});
+    vVB = rename(vVB, {{fn[a], nm("fB", a)}});
+  }
+  vUA = rename(vUA, {{"kk", "kA"}});
+  vVB = rename(vVB, {{"kk", "kB"}});
+
+  // ---- 3. HOSVD isometries from factored Gram matrices
+  double *UtU = c.wsp<double>("gUtU", size_t(k) * k * 8), *VVt = c.wsp<double>("gVVt", size_t(k) * k * 8);
+  {
+    std::map<std::string, std::string> ren{{"kA", "kA2"}};
+    einsum2(c, Ut, vUA, Ut, rename(vUA, ren), UtU, {"kA", "kA2"}, TRG_FP64, "g0");
+    einsum2(c, Vt, vVB, Vt, rename(vVB, {{"kB", "kB2"}}), VVt, {"kB", "kB2"}, TRG_FP64, "g0");
+  }
+  double *Wf = c.wsp<double>("gWf", size_t(dc) * dc * 8), *Wbk = c.wsp<double>("gWb", size_t(dc) * dc * 8);
+  {
+    // Wf[l, l2] = sum Ys[l, fA_perp, kB] VVt[kB, kB2] Ys[l2, fA_perp, kB2]
+    double *YV = c.wsp<double>("gYV", size_t(nsw) * dc * 8);
+    std::vector<std::string> o{"l"};
+    for (int a : perp) o.push_back(nm("fA", a));
+    o.push_back("kB2");
+    einsum2(c, Ys, vYs, VVt, contiguous({{"kB", k}, {"kB2", k}}), YV, o, TRG_FP64, "g1");
+    std::vector<std::pair<std::string, int64_t>> yl{{"l", dc}};
+    for (int a : perp) yl.push_back({nm("fA", a), dims[a]});
+    yl.push_back({"kB2", k});
+    einsum2(c, YV, contiguous(yl), Ys, rename(vYs, {{"l", "l2"}, {"kB", "kB2"}}), Wf, {"l", "l2"}, TRG_FP64,
+            "g2");
+    // Wb[l, l2] = sum Xs[kA, bB_perp, l] UtU[kA, kA2] Xs[kA2, bB_perp, l2]
+    std::vector<std::string> o2{"kA2"};
+    for (int a : perp) o2.push_back(nm("bB", a));
+    o2.push_back("l");
+    einsum2(c, UtU, contiguous({{"kA", k}, {"kA2", k}}), Xs, vXs, YV, o2, TRG_FP64, "g1");
+    std::vector<std::pair<std::string, int64_t>> xl{{"kA2", k}};
+    for (int a : perp) xl.push_back({nm("bB", a), dims[a]});
+    xl.push_back({"l", dc});
+    einsum2(c, YV, contiguous(xl), Xs, rename(vXs, {{"l", "l2"}, {"kA", "kA2"}}), Wbk, {"l", "l2"}, TRG_FP64,
+            "g2");
+  }
+  int nd[4] = {0, 0, 0, 0};
+  for (int a = 0; a < d; ++a) {
+    const int64_t sq = int64_t(dims[a]) * dims[a];
+    nd[a] = a == mu ? dims[a] : int(sq < dcut ? sq : dcut);
+  }
+  for (int nu : perp) {
+    const int dn = dims[nu], nn = dn * dn, kn = nd[nu];
+    double *G2 = c.wsp<double>("gG", size_t(2) * nn * nn * 8);
+    double *Wv = c.wsp<double>("gW", size_t(2) * nn * 8);
+    double *Vv = c.wsp<double>("gV", size_t(2) * nn * nn * 8);
+    int *sw = c.wsp<int>("gsw", 16);
+    double *PA = c.wsp<double>("gPA", size_t(nn) * k * k * 8);
+    double *Xw = c.wsp<double>("gXw", size_t(nsw) * dc * 8);
+    double *QX = c.wsp<double>("gQX", size_t(nn) * k * k * 8);
+    // backward pair: PA[a, kA, a2, kA2] = sum_{bA other} Ut Ut
+    {
+      View v1 = rename(vUA, {{nm("bA", nu), "a"}});
+      View v2 = rename(vUA, {{nm("bA", nu), "a2"}, {"kA", "kA2"}});
+      einsum2(c, Ut, v1, Ut, v2, PA, {"a", "kA", "a2", "kA2"}, TRG_FP64, "h1");
+      // Xw[kA2, bb2, others, l] = sum_l2 Xs[kA2, bb2, others, l2] Wf[l, l2]
+      View vx = rename(vXs, {{"kA", "kA2"}, {nm("bB", nu), "bb2"}, {"l", "l2"}});
+      std::vector<std::string> o{"kA2", "bb2"};
+      std::vector<std::pair<std::string, int64_t>> xl{{"kA2", k}, {"bb2", dn}};
+      for (int a : perp)
+        if (a != nu) {
+          o.push_back(nm("bB", a));
+          xl.push_back({nm("bB", a), dims[a]});
+        }
+      o.push_back("l");
+      xl.push_back({"l", dc});
+      einsum2(c, Xs, vx, Wf, contiguous({{"l", dc}, {"l2", dc}}), Xw, o, TRG_FP64, "h2");
+      // QX[kA, bb, kA2, bb2] = sum_{others, l} Xs Xw
+      einsum2(c, Xs, rename(vXs, {{nm("bB", nu), "bb"}}), Xw, contiguous(xl), QX, {"kA", "bb", "kA2", "bb2"},
+              TRG_FP64, "h3");
+      // Gram[a, bb, a2, bb2] = sum_{kA, kA2} PA QX
+      einsum2(c, PA, contiguous({{"a", dn}, {"kA", k}, {"a2", dn}, {"kA2", k}}), QX,
+              contiguous({{"kA", k}, {"bb", dn}, {"kA2", k}, {"bb2", dn}}), G2, {"a", "bb", "a2", "bb2"}, TRG_FP64,
+              "h4");
+    }
+    // forward pair: QY[fa, kB, fa2, kB2] from Ys and Wb, PV[kB, fb, kB2, fb2] from Vt
+    {
+      View v1 = rename(vVB, {{nm("fB", nu), "fb"}});
+      View v2 = rename(vVB, {{nm("fB", nu), "fb2"}, {"kB", "kB2"}});
+      einsum2(c, Vt, v1, Vt, v2, PA, {"kB", "fb", "kB2", "fb2"}, TRG_FP64, "h1");
+      View vy = rename(vYs, {{"l", "l2"}, {nm("fA", nu), "fa2"}, {"kB", "kB2"}});
+      std::vector<std::string> o{"l", "fa2"};
+      std::vector<std::pair<std::string, int64_t>> yl{{"l", dc}, {"fa2", dn}};
+      for (int a : perp)
+        if (a != nu) {
+          o.push_back(nm("fA", a));
+          yl.push_back({nm("fA", a), dims[a]});
+        }
+      o.push_back("kB2");
+      yl.push_back({"kB2", k});
+      einsum2(c, Wbk, contiguous({{"l", dc}, {"l2", dc}}), Ys, vy, Xw, o, TRG_FP64, "h2");
+      einsum2(c, Ys, rename(vYs, {{nm("fA", nu), "fa"}}), Xw, contiguous(yl), QX, {"fa", "kB", "fa2", "kB2"},
+              TRG_FP64, "h3");
+      einsum2(c, QX, contiguous({{"fa", dn}, {"kB", k}, {"fa2", dn}, {"kB2", k}}), PA,
+              contiguous({{"kB", k}, {"fb", dn}, {"kB2", k}, {"fb2", dn}}), G2 + size_t(nn) * nn,
+              {"fa", "fb", "fa2", "fb2"}, TRG_FP64, "h4");
+    }
+    eigh_batched(G2, Wv, Vv, sw, nn, 2, st);
+    c.ensure(c.U[nu], size_t(nn) * kn * 8);
+    c.ensure(c.spec[nu], size_t(nn) * 8);
+    c.Un[nu] = nn;
+    c.Uk[nu] = kn;
+    SelectOut so{static_cast<double *>(c.U[nu].ptr), rd + 1 + 2 * nu, ri + 4 * nu,
+                 static_cast<double *>(c.spec[nu].ptr)};
+    select_isometry(Wv, Vv, sw, nn, kn, c.force_side, so, st);
+  }
+
+  dbg(c, "Wf", Wf, int64_t(dc) * dc);
+  dbg(c, "Wb", Wbk, int64_t(dc) * dc);
+  for (int nu : perp) dbg(c, "P", static_cast<const double *>(c.U[nu].ptr), int64_t(dims[nu]) * dims[nu] * nd[nu]);
+  // ---- 4. contraction with the isometries
+  int64_t nnew = 1;
+  for (int a = 0; a < d; ++a) nnew *= nd[a];
+  double *Gn = c.wsp<double>("newG", size_t(nnew) * dc * 8);
+  double *Hn = c.wsp<double>("newH", size_t(nnew) * dc * 8);
+  const int nu1 = perp[0];
+  auto P = [&](int nu) { return static_cast<const double *>(c.U[nu].ptr); };
+  {
+    // G: UP = Ut[bA..., kA] P1[bA_nu1, bB_nu1, B_nu1]
+    const View vP1 = contiguous({{nm("bA", nu1), dims[nu1]}, {nm("bB", nu1), dims[nu1]}, {nm("B", nu1), nd[nu1]}});
+    std::vector<std::string> o;
+    std::vector<std::pair<std::string, int64_t>> ol;
+    for (int a = 0; a < d; ++a)
+      if (a != nu1) {
+        o.push_back(nm("bA", a));
+        ol.push_back({nm("bA", a), dims[a]});
+      }
+    o.insert(o.end(), {"kA", nm("bB", nu1), nm("B", nu1)});
+    ol.insert(ol.end(), {{"kA", k}, {nm("bB", nu1), dims[nu1]}, {nm("B", nu1), nd[nu1]}});
+    double *UP = c.wsp<double>("kUP", size_t(view_count(contiguous(ol))) * 8);
+    einsum2(c, Ut, vUA, P(nu1), vP1, UP, o, TRG_FP64, "k1");
+    // G1 = sum_{kA, bB_nu1} UP Xs  -> [bA (not nu1)..., B_nu1, bB (perp not nu1)..., l]
+    std::vector<std::string> o2;
+    std::vector<std::pair<std::string, int64_t>> ol2;
+    for (int a = 0; a < d; ++a)
+      if (a != nu1) {
+        o2.push_back(nm("bA", a));
+        ol2.push_back({nm("bA", a), dims[a]});
+      }
+    o2.push_back(nm("B", nu1));
+    ol2.push_back({nm("B", nu1), nd[nu1]});
+    for (int a : perp)
+      if (a != nu1) {
+        o2.push_back(nm("bB", a));
+        ol2.push_back({nm("bB", a), dims[a]});
+      }
+    o2.push_back("l");
+    ol2.push_back({"l", dc});
+    double *G1 = c.wsp<double>("kG1", size_t(view_count(contiguous(ol2))) * 8);
+    einsum2(c, UP, contiguous(ol), Xs, vXs, G1, o2, cprec, "k2");
+    // remaining pairs: (bA_nu, bB_nu) -> B_nu, the last one writes the canonical order
+    View cur = contiguous(ol2);
+    const double *src = G1;
+    for (size_t j = 1; j < perp.size(); ++j) {
+      const int nu = perp[j];
+      std::vector<std::pair<std::string, int64_t>> tl;
+      const bool last = j + 1 == perp.size();
+      if (last) {
+        for (int a = 0; a < d; ++a) tl.push_back(a == mu ? std::make_pair(nm("bA", a), int64_t(dims[a]))
+                                                         : std::make_pair(nm("B", a), int64_t(nd[a])));
+        tl.push_back({"l", dc});
+      } else {
+        for (const auto &l : cur)
+          if (l.name != nm("bA", nu) && l.name != nm("bB", nu)) tl.push_back({l.name, l.size});
+        tl.push_back({nm("B", nu), nd[nu]});
+      }
+      const View tv = contiguous(tl);
+      double *dst = last ? Gn : c.wsp<double>("kG2" + std::to_string(j), size_t(view_count(tv)) * 8);
+      apply_map(src, IN_F64, cur, P(nu),
+                {{nm("bA", nu), int64_t(dims[nu]) * nd[nu]}, {nm("bB", nu), nd[nu]}, {nm("B", nu), 1}},
+                {nm("bA", nu), nm("bB", nu)}, dst, OUT_F64, 0, tv, st);
+      src = dst;
+      cur = tv;
+    }
+    if (perp.size() == 1) {
+      std::vector<std::pair<std::string, int64_t>> tl;
+      for (int a = 0; a < d; ++a) tl.push_back(a == mu ? std::make_pair(nm("bA", a), int64_t(dims[a]))
+                                                       : std::make_pair(nm("B", a), int64_t(nd[a])));
+      tl.push_back({"l", dc});
+      apply_map(G1, IN_F64, cur, nullptr, {}, {}, Gn, OUT_F64, 0, contiguous(tl), st);
+    }
+  }
+  {
+    // H: VP = Vt[kB, fB...] P1[fA_nu1, fB_nu1, F_nu1]
+    const View vP1 = contiguous({{nm("fA", nu1), dims[nu1]}, {nm("fB", nu1), dims[nu1]}, {nm("F", nu1), nd[nu1]}});
+    std::vector<std::string> o{"kB"};
+    std::vector<std::pair<std::string, int64_t>> ol{{"kB", k}};
+    for (int a = 0; a < d; ++a)
+      if (a != nu1) {
+        o.push_back(nm("fB", a));
+        ol.push_back({nm("fB", a), dims[a]});
+      }
+    o.insert(o.end(), {nm("fA", nu1), nm("F", nu1)});
+    ol.insert(ol.end(), {{nm("fA", nu1), dims[nu1]}, {nm("F", nu1), nd[nu1]}});
+    double *VP = c.wsp<double>("kUP", size_t(view_count(contiguous(ol))) * 8);
+    einsum2(c, Vt, vVB, P(nu1), vP1, VP, o, TRG_FP64, "k1");
+    // H1 = sum_{kB, fA_nu1} Ys VP -> [l, fA (perp not nu1)..., fB (not nu1)..., F_nu1]
+    std::vector<std::string> o2{"l"};
+    std::vector<std::pair<std::string, int64_t>> ol2{{"l", dc}};
+    for (int a : perp)
+      if (a != nu1) {
+        o2.push_back(nm("fA", a));
+        ol2.push_back({nm("fA", a), dims[a]});
+      }
+    for (int a = 0; a < d; ++a)
+      if (a != nu1) {
+        o2.push_back(nm("fB", a));
+        ol2.push_back({nm("fB", a), dims[a]});
+      }
+    o2.push_back(nm("F", nu1));
+    ol2.push_back({nm("F", nu1), nd[nu1]});
+    double *H1 = c.wsp<double>("kG1", size_t(view_count(contiguous(ol2))) * 8);
+    einsum2(c, Ys, vYs, VP, contiguous(ol), H1, o2, cprec, "k2");
+    View cur = contiguous(ol2);
+    const double *src = H1;
+    for (size_t j = 1; j < perp.size(); ++j) {
+      const int nu = perp[j];
+      std::vector<std::pair<std::string, int64_t>> tl;
+      const bool last = j + 1 == perp.size();
+      if (last) {
+        tl.push_back({"l", dc});
+        for (int a = 0; a < d; ++a) tl.push_back(a == mu ? std::make_pair(nm("fB", a), int64_t(dims[a]))
+                                                         : std::make_pair(nm("F", a), int64_t(nd[a])));
+      } else {
+        for (const auto &l : cur)
+          if (l.name != nm("fA", nu) && l.name != nm("fB", nu)) tl.push_back({l.name, l.size});
+        tl.push_back({nm("F", nu), nd[nu]});
+      }
+      const View tv = contiguous(tl);
+      double *dst = last ? Hn : c.wsp<double>("kG2" + std::to_string(j), size_t(view_count(tv)) * 8);
+      apply_map(src, IN_F64, cur, P(nu),
+                {{nm("fA", nu), int64_t(dims[nu]) * nd[nu]}, {nm("fB", nu), nd[nu]}, {nm("F", nu), 1}},
+                {nm("fA", nu), nm("fB", nu)}, dst, OUT_F64, 0, tv, st);
+      src = dst;
+      cur = tv;
+    }
+    if (perp.size() == 1) {
+      std::vector<std::pair<std::string, int64_t>> tl{{"l", dc}};
+      for (int a = 0; a < d; ++a) tl.push_back(a == mu ? std::make_pair(nm("fB", a), int64_t(dims[a]))
+                                                       : std::make_pair(nm("F", a), int64_t(nd[a])));
+      apply_map(H1, IN_F64, cur, nullptr, {}, {}, Hn, OUT_F64, 0, contiguous(tl), st);
+    }
+  }
+
+  dbg(c, "Gn", Gn, nnew * dc);
+  dbg(c, "Hn", Hn, nnew * dc);
+  // ---- 5. normalisation
+  double *GtG = c.wsp<double>("nGtG", size_t(dc) * dc * 8), *HHt = c.wsp<double>("nHHt", size_t(dc) * dc * 8);
+  {
+    const View vg = contiguous({{"b", nnew}, {"l", dc}}), vh = contiguous({{"l", dc}, {"f", nnew}});
+    einsum2(c, Gn, vg, Gn, rename(vg, {{"l", "l2"}}), GtG, {"l", "l2"}, TRG_FP64, "nrm");
+    einsum2(c, Hn, vh, Hn, rename(vh, {{"l", "l2"}}), HHt, {"l", "l2"}, TRG_FP64, "nrm");
+  }
+  hipLaunchKernelGGL(atrg_norm_kernel, dim3(1), dim3(256), 0, st, GtG, HHt, dc, c.scal(), c.scal() + 3,
+                     std::ldexp(1.0, -n_step), c.errp());
+  TRG_HIP_CHECK(hipGetLastError());
+  scale_by_inverse(Gn, nnew * dc, c.scal(), 1.0, st);
+  scale_by_inverse(Hn, nnew * dc, c.scal(), 1.0, st);
+  TRG_HIP_CHECK(hipMemcpyAsync(rd, c.scal() + 2, 8, hipMemcpyDeviceToDevice, st));
+  c.ensure(c.G, size_t(nnew) * dc * 8);
+  c.ensure(c.H, size_t(nnew) * dc * 8);
+  TRG_HIP_CHECK(hipMemcpyAsync(c.G.ptr, Gn, size_t(nnew) * dc * 8, hipMemcpyDeviceToDevice, st));
+  TRG_HIP_CHECK(hipMemcpyAsync(c.H.ptr, Hn, size_t(nnew) * dc * 8, hipMemcpyDeviceToDevice, st));
+
+  trg_step_rec hr{};
+  hr.n = n_step;
+  hr.axis = mu;
+  for (int a = 0; a < 4; ++a) {
+    hr.dims[a] = a < d ? nd[a] : 0;
+    hr.side[a] = -1;
+  }
+  c.host_rec.push_back(hr);
+  for (int a = 0; a < d; ++a) c.dims[a] = nd[a];
+  c.r = dc;
+  c.nsteps = n_step;
+}
+
+}  // namespace trg

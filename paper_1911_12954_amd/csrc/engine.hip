@@ -23,8 +23,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/trg.h"
-#include "internal.h"
+#include "context.h"
 
 using namespace trg;
 
@@ -32,42 +31,10 @@ namespace {
 
 thread_local std::string g_thread_error;
 
-struct Leg {
-  std::string name;
-  int64_t size, stride;
-};
-using View = std::vector<Leg>;
+}  // namespace
 
-const Leg &find_leg(const View &v, const std::string &n) {
-  for (const auto &l : v)
-    if (l.name == n) return l;
-  throw Error(-1, "internal: leg " + n + " not found");
-}
-bool has_leg(const View &v, const std::string &n) {
-  for (const auto &l : v)
-    if (l.name == n) return true;
-  return false;
-}
+namespace trg {
 
-// row-major contiguous layout of the named legs (first = outermost)
-View contiguous(const std::vector<std::pair<std::string, int64_t>> &legs, int64_t scale = 1) {
-  View v;
-  int64_t s = scale;
-  for (int i = int(legs.size()) - 1; i >= 0; --i) {
-    v.insert(v.begin(), Leg{legs[i].first, legs[i].second, s});
-    s *= legs[i].second;
-  }
-  return v;
-}
-
-int64_t view_count(const View &v) {
-  int64_t n = 1;
-  for (const auto &l : v) n *= l.size;
-  return n;
-}
-
-// out(legs of outv) = sum over `sums` of in(legs of inv) * U(u legs)
-// u_strides gives the U stride of every U-side leg name (outputs and sums).
 void apply_map(const void *in, int in_kind, const View &inv, const double *U,
                const std::map<std::string, int64_t> &u_strides, const std::vector<std::string> &sums,
                void *out, int out_kind, int64_t lo_plane, const View &outv, hipStream_t st) {
@@ -92,99 +59,9 @@ void apply_map(const void *in, int in_kind, const View &inv, const double *U,
              int(ss.size()), st);
 }
 
-std::string nm(const char *p, int ax) { return std::string(p) + std::to_string(ax); }
+}  // namespace trg
 
-struct Buffer {
-  void *ptr = nullptr;
-  size_t cap = 0;
-};
-
-}  // namespace
-
-struct trg_ctx {
-  int d = 0;
-  int dims[4] = {0, 0, 0, 0};
-  int nsteps = 0;
-  trg_config cfg{};
-  hipStream_t st = nullptr;
-  bool poisoned = false;
-  std::string err;
-  int nimp = 0;        // number of impure tensors
-  int imp_kind[2] = {-1, -1};  // 0 = E, 1 = M
-  bool has_e = false, has_m = false;
-
-  Buffer T, Tn, S[2], Sn[2];
-  Buffer dev_scalars;  // doubles: [0] c [1] 1/c [2] ln c [3] acc [4..6] traces [7] c0
-  Buffer dev_err;      // int
-  Buffer dev_rec;      // per-step device records
-  int rec_cap = 0;
-  std::vector<trg_step_rec> host_rec;  // host-known parts
-  Buffer U[4], spec[4];
-  int Un[4] = {0, 0, 0, 0}, Uk[4] = {0, 0, 0, 0};
-  std::map<std::string, Buffer> ws;
-  int force_side = -1;
-
-  bool profiling = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> join_events;
-  double join_ms = 0.0, join_flops_done = 0.0, join_flops_pending = 0.0;
-  long long join_launches = 0;
-
-  void *alloc(size_t bytes) {
-    if (bytes == 0) bytes = 256;
-    void *p = nullptr;
-    if (cfg.alloc) {
-      p = cfg.alloc(bytes, cfg.alloc_user);
-      if (!p) throw Error(TRG_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-    } else {
-      hipError_t e = hipMalloc(&p, bytes);
-      if (e != hipSuccess || !p) {
-        (void)hipGetLastError();
-        throw Error(TRG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-      }
-    }
-    return p;
-  }
-  void release(void *p) {
-    if (!p) return;
-    if (cfg.alloc) {
-      if (cfg.free) cfg.free(p, cfg.alloc_user);
-    } else {
-      (void)hipFree(p);
-    }
-  }
-  void ensure(Buffer &b, size_t bytes) {
-    if (b.cap >= bytes && b.ptr) return;
-    if (b.ptr) {
-      // the stream may still read the old buffer
-      TRG_HIP_CHECK(hipStreamSynchronize(st));
-      release(b.ptr);
-      b.ptr = nullptr;
-      b.cap = 0;
-    }
-    b.ptr = alloc(bytes);
-    b.cap = bytes;
-  }
-  template <typename Tp>
-  Tp *wsp(const std::string &name, size_t bytes) {
-    Buffer &b = ws[name];
-    ensure(b, bytes);
-    return static_cast<Tp *>(b.ptr);
-  }
-  size_t ws_held() const {
-    size_t s = 0;
-    for (const auto &kv : ws) s += kv.second.cap;
-    return s;
-  }
-  double *scal() { return static_cast<double *>(dev_scalars.ptr); }
-  int *errp() { return static_cast<int *>(dev_err.ptr); }
-  int64_t total() const {
-    int64_t n = 1;
-    for (int a = 0; a < d; ++a) n *= int64_t(dims[a]) * dims[a];
-    return n;
-  }
-};
-
-namespace {
+namespace trg {
 
 // device step record layout (doubles first, then ints)
 constexpr int REC_D = 1 + 8;        // ln c, eps[4][2]
@@ -667,7 +544,7 @@ void normalise_initial(trg_ctx &c) {
   TRG_HIP_CHECK(hipMemcpyAsync(rec_d(c, 0), c.scal() + 2, 8, hipMemcpyDeviceToDevice, c.st));
 }
 
-}  // namespace
+}  // namespace trg
 
 // =================================================================== C-ABI ==
 extern "C" {
@@ -682,9 +559,16 @@ int trg_init_ising(trg_ctx **out, double beta, double h, int d, const trg_config
     TRG_REQUIRE(std::isfinite(h), "h must be finite");
     const unsigned imp = cfg ? cfg->impure : 0u;
     TRG_REQUIRE(!(imp & TRG_IMPURE_E) || beta > 0.0, "the energy impurity needs beta > 0");
-    TRG_REQUIRE(!cfg || cfg->method == TRG_HOTRG, "ATRG contexts are not available in this build");
+    const bool atrg = cfg && cfg->method == TRG_ATRG;
+    TRG_REQUIRE(!atrg || imp == 0, "ATRG contexts carry no impure tensors");
+    TRG_REQUIRE(!atrg || cfg->precision != TRG_BF16X3, "ATRG supports FP64 and FP32 contractions");
     c = new_ctx(d, cfg);
     for (int a = 0; a < d; ++a) c->dims[a] = 2;
+    if (atrg) {
+      init_common(*c);
+      atrg_init_ising(*c, beta, h);
+      return TRG_OK;
+    }
     c->has_e = imp & TRG_IMPURE_E;
     c->has_m = imp & TRG_IMPURE_M;
     if (c->has_e) c->imp_kind[c->nimp++] = 0;
@@ -763,9 +647,62 @@ int trg_hotrg_step_batch(trg_ctx *const *ctxs, int n, int axis, int dcut) {
 }
 
 int trg_atrg_step(trg_ctx *ctx, int axis, int dcut) {
-  (void)axis;
-  (void)dcut;
-  return fail(ctx, TRG_ESTATE, "ATRG is not available in this build");
+  if (!ctx) return fail(nullptr, TRG_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&]() -> int {
+    TRG_REQUIRE(axis >= 0 && axis < ctx->d, "axis out of range");
+    TRG_REQUIRE(dcut >= 1 && dcut <= 256, "dcut out of range for ATRG");
+    if (ctx->cfg.method != TRG_ATRG) return fail(ctx, TRG_ESTATE, "context method is not ATRG");
+    atrg_step_impl(*ctx, axis, dcut);
+    return TRG_OK;
+  });
+}
+
+int trg_init_factors(trg_ctx **out, int d, const int *dims, int r, const double *host_G, const double *host_H,
+                     const trg_config *cfg) {
+  if (!out || !dims || !host_G || !host_H) return fail(nullptr, TRG_EINVAL, "NULL argument");
+  *out = nullptr;
+  trg_ctx *c = nullptr;
+  int rc = guarded(nullptr, [&]() -> int {
+    validate_cfg(cfg, d);
+    TRG_REQUIRE(cfg && cfg->method == TRG_ATRG, "factors need method TRG_ATRG");
+    TRG_REQUIRE(cfg->impure == 0 && cfg->precision != TRG_BF16X3, "unsupported ATRG configuration");
+    TRG_REQUIRE(r >= 1 && r <= 512, "rank out of range");
+    int64_t n = 1;
+    for (int a = 0; a < d; ++a) {
+      TRG_REQUIRE(dims[a] >= 1 && dims[a] <= 1024, "bad leg dim");
+      n *= dims[a];
+    }
+    TRG_REQUIRE(n >= r, "pieces need at least r rows");
+    c = new_ctx(d, cfg);
+    for (int a = 0; a < d; ++a) c->dims[a] = dims[a];
+    init_common(*c);
+    c->r = r;
+    c->ensure(c->G, size_t(n) * r * 8);
+    c->ensure(c->H, size_t(n) * r * 8);
+    TRG_HIP_CHECK(hipMemcpyAsync(c->G.ptr, host_G, size_t(n) * r * 8, hipMemcpyHostToDevice, c->st));
+    TRG_HIP_CHECK(hipMemcpyAsync(c->H.ptr, host_H, size_t(n) * r * 8, hipMemcpyHostToDevice, c->st));
+    sync_check(*c);
+    return TRG_OK;
+  });
+  if (rc != TRG_OK) {
+    if (c) trg_free(c);
+    return rc;
+  }
+  *out = c;
+  return TRG_OK;
+}
+
+int trg_atrg_spectrum(trg_ctx *ctx, double *out, int cap, int *n) {
+  if (!ctx || !n) return fail(ctx, TRG_EINVAL, "NULL argument");
+  return guarded(ctx, [&]() -> int {
+    sync_check(*ctx);
+    *n = ctx->atrg_nsig;
+    if (out && ctx->atrg_nsig > 0) {
+      TRG_REQUIRE(cap >= ctx->atrg_nsig, "capacity too small");
+      TRG_HIP_CHECK(hipMemcpy(out, ctx->atrg_sigma.ptr, size_t(ctx->atrg_nsig) * 8, hipMemcpyDeviceToHost));
+    }
+    return TRG_OK;
+  });
 }
 
 int trg_run(trg_ctx *ctx, long long L) {
@@ -774,7 +711,12 @@ int trg_run(trg_ctx *ctx, long long L) {
     TRG_REQUIRE(L >= 2 && (L & (L - 1)) == 0, "L must be a power of two >= 2");
     int m = 0;
     while ((1LL << m) < L) ++m;
-    for (int n = 1; n <= ctx->d * m; ++n) hotrg_step_impl(*ctx, (n - 1) % ctx->d, ctx->cfg.dcut);
+    for (int n = 1; n <= ctx->d * m; ++n) {
+      if (ctx->cfg.method == TRG_ATRG)
+        atrg_step_impl(*ctx, (n - 1) % ctx->d, ctx->cfg.dcut);
+      else
+        hotrg_step_impl(*ctx, (n - 1) % ctx->d, ctx->cfg.dcut);
+    }
     sync_check(*ctx);
     return TRG_OK;
   });
@@ -799,7 +741,12 @@ int trg_free_energy(trg_ctx *ctx, double *lnz) {
   if (!ctx || !lnz) return fail(ctx, TRG_EINVAL, "NULL argument");
   return guarded(ctx, [&]() -> int {
     double t[4];
-    traces(ctx, t);
+    if (ctx->cfg.method == TRG_ATRG) {
+      t[1] = atrg_trace(*ctx);
+      TRG_HIP_CHECK(hipMemcpy(&t[0], ctx->scal() + 3, 8, hipMemcpyDeviceToHost));
+    } else {
+      traces(ctx, t);
+    }
     if (!(t[1] > 0.0) || !std::isfinite(t[1])) throw Error(TRG_ENUMERIC, "non-positive trace of the tensor");
     *lnz = t[0] + std::ldexp(1.0, -ctx->nsteps) * std::log(t[1]);
     return TRG_OK;
@@ -848,6 +795,7 @@ int trg_get_dims(const trg_ctx *ctx, int *dims, int *steps) {
 int trg_get_tensor(trg_ctx *ctx, int which, double *host_out, size_t cap) {
   if (!ctx || !host_out) return fail(ctx, TRG_EINVAL, "NULL argument");
   return guarded(ctx, [&]() -> int {
+    if (ctx->cfg.method != TRG_HOTRG) return fail(ctx, TRG_ESTATE, "ATRG contexts hold factored tensors");
     const size_t n = size_t(ctx->total());
     TRG_REQUIRE(cap >= n, "output capacity too small");
     const void *src = nullptr;
@@ -910,8 +858,16 @@ int trg_step_log(trg_ctx *ctx, trg_step_rec *out, int cap, int *n) {
 }
 
 size_t trg_footprint_bytes(int d, int dcut, int precision, int method, unsigned impure) {
-  (void)method;
   if (d < 2 || d > 4 || dcut < 1) return 0;
+  if (method == TRG_ATRG) {
+    // pieces (2 D^{d+1}) resident; workspace dominated by the D^{2d-1}
+    // intermediate of the contraction (GEMM output and its unpacked copy)
+    const double D = dcut;
+    const double pieces = 2.0 * std::pow(D, d + 1) * 8.0;
+    const double inter = 2.0 * std::pow(D, 2 * d - 1) * 8.0;
+    const double rs = 8.0 * std::pow(D, d) * 5.0 * D * 8.0;  // RSVD blocks (r = 5 Dcut)
+    return size_t(pieces + inter + rs);
+  }
   // resident tensors: T and its next-step buffer, per impurity the same
   double D = dcut;
   double t = std::pow(D, 2 * d);
@@ -951,6 +907,9 @@ void trg_free(trg_ctx *ctx) {
     rel(ctx->S[j]);
     rel(ctx->Sn[j]);
   }
+  rel(ctx->G);
+  rel(ctx->H);
+  rel(ctx->atrg_sigma);
   rel(ctx->dev_scalars);
   rel(ctx->dev_err);
   rel(ctx->dev_rec);

@@ -53,7 +53,7 @@ def _torch_allocator(stream_ptr):
 
 
 def make_config(precision="fp64", method="hotrg", dcut=8, impure=(), stream=None,
-                use_torch_allocator=True, workspace_bytes=0, rsvd_p=0, rsvd_q=-1, seed=0):
+                use_torch_allocator=True, workspace_bytes=0, rsvd_p=0, rsvd_q=0, seed=0):
     """Build a trg_config.  ``stream``: a torch.cuda.Stream, an int handle or
     None (torch's current stream when torch has a GPU, else the default)."""
     cfg = L.TrgConfig()
@@ -175,6 +175,17 @@ class Context:
                                   tuple(tuple(r.eps[a]) for a in range(self.d))))
         return out
 
+    def atrg_step(self, axis: int, dcut: int):
+        _err(_lib().trg_atrg_step(self.handle, axis, dcut), self.handle)
+
+    def atrg_spectrum(self):
+        n = C.c_int()
+        _err(_lib().trg_atrg_spectrum(self.handle, None, 0, C.byref(n)), self.handle)
+        out = np.empty(max(n.value, 1))
+        _err(_lib().trg_atrg_spectrum(self.handle, out.ctypes.data_as(C.POINTER(C.c_double)), out.size,
+                                      C.byref(n)), self.handle)
+        return out[: n.value]
+
     def set_profiling(self, on=True):
         _err(_lib().trg_set_profiling(self.handle, 1 if on else 0), self.handle)
 
@@ -224,6 +235,23 @@ def trg_init_tensor(T: np.ndarray, **cfg) -> Context:
     return ctx
 
 
+def trg_init_factors(G: np.ndarray, H: np.ndarray, **cfg) -> Context:
+    """ATRG context from pieces G[b0..b_{d-1}, l] and H[l, f0..f_{d-1}]."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    d = G.ndim - 1
+    r = G.shape[-1]
+    dims = (C.c_int * d)(*G.shape[:-1])
+    cfg.setdefault("method", "atrg")
+    conf, keep = make_config(**cfg)
+    h_ = C.c_void_p()
+    _err(_lib().trg_init_factors(C.byref(h_), d, dims, r, G.ctypes.data_as(C.POINTER(C.c_double)),
+                                 H.ctypes.data_as(C.POINTER(C.c_double)), C.byref(conf)))
+    ctx = Context(h_, keep + [conf], d)
+    ctx._initial_dims = tuple(G.shape[:-1])
+    return ctx
+
+
 def trg_hotrg_step(ctx: Context, axis: int, dcut: int):
     ctx.hotrg_step(axis, dcut)
 
@@ -235,7 +263,7 @@ def trg_hotrg_step_batch(ctxs, axis: int, dcut: int):
 
 
 def trg_atrg_step(ctx: Context, axis: int, dcut: int):
-    _err(_lib().trg_atrg_step(ctx.handle, axis, dcut), ctx.handle)
+    ctx.atrg_step(axis, dcut)
 
 
 def trg_run(ctx: Context, L_: int):

@@ -1,7 +1,11 @@
 """One steady-state HOTRG step at the benchmark's size (4D, every leg at
 Dcut = 10, the same chunking of the join) against the oracle, on sampled
 output blocks T'[x0, x2, Y, Y', Z, Z', :, :] that the oracle computes one by
-one, plus properties that hold at any size."""
+one, plus properties that hold at any size.  The input has geometrically
+decaying HOSVD spectra (as the Ising tensor has), so that the kept
+eigenvectors are well conditioned and an element-by-element comparison is
+meaningful (a flat spectrum with relative gaps ~1e-7 would determine them
+only to ~2e-9)."""
 import math
 
 import numpy as np
@@ -9,7 +13,7 @@ import pytest
 
 from oracle import hotrg
 from tests.gpu_util import announce, need_gpu
-from trg_inputs import random_site_tensor
+from trg_inputs import decaying_site_tensor
 
 pytestmark = pytest.mark.gpu
 
@@ -20,7 +24,7 @@ BLOCKS = [(0, 0, 0, 0, 0, 0), (9, 9, 9, 9, 9, 9), (9, 2, 3, 7, 1, 8), (4, 6, 5, 
 
 @pytest.fixture(scope="module")
 def problem():
-    T = random_site_tensor((D,) * 4, seed=101, positive_bias=True)
+    T = decaying_site_tensor((D,) * 4, seed=101)
     Tn = T / np.sqrt(np.sum(T * T))
     choices = [hotrg.isometry(Tn, 0, nu, D) for nu in (1, 2, 3)]
     U = {ch.nu: ch.U for ch in choices}
@@ -34,7 +38,7 @@ def problem():
     return T, choices, blocks
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-5), ("bf16x3", 2e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 2e-4)])
 def test_dcut10_step_on_sampled_blocks(problem, precision, tol):
     need_gpu()
     from paper_1911_12954_amd import trg_init_tensor

@@ -47,3 +47,18 @@ def gram_like(n: int, rank: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((n, rank)) * (0.5 ** np.arange(rank))[None, :]
     return X @ X.T
+
+
+def decaying_site_tensor(dims, seed: int, rank: int = 20, ratio: float = 0.8, noise: float = 1e-3) -> np.ndarray:
+    """A site tensor whose HOSVD spectra decay geometrically, as those of the
+    Ising tensor do: sum_r ratio^r prod_legs v_{r,leg} with N(0,1) vectors,
+    plus `noise` times N(0,1) entries.  One dim per axis, legs (x, x', y, y', ...)."""
+    shape = tuple(int(x) for x in dims for _ in range(2))
+    rng = np.random.default_rng(seed)
+    T = noise * rng.standard_normal(shape)
+    for r in range(rank):
+        term = np.array(ratio ** r)
+        for n in shape:
+            term = np.multiply.outer(term, rng.standard_normal(n))
+        T += term
+    return T
