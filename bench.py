@@ -44,6 +44,15 @@ def parse():
     p.add_argument("--cpu-sample-blocks", type=int, default=1)
     p.add_argument("--method", default="hotrg", choices=["hotrg", "atrg"],
                    help="atrg: time steady-state ATRG steps (default Dcut 24 there) instead of HOTRG")
+    p.add_argument("--serve", action="store_true",
+                   help="serving benchmark: Poisson stream of HOTRG solves, time-boxed window")
+    p.add_argument("--serve-n", type=int, default=200)
+    p.add_argument("--serve-rate", type=float, default=1.0, help="arrivals per second")
+    p.add_argument("--serve-window", type=float, default=60.0)
+    p.add_argument("--serve-dcuts", default="6,8,10")
+    p.add_argument("--serve-k", default="4,10", help="L = 2^k, k uniform in [kmin, kmax]")
+    p.add_argument("--serve-precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    p.add_argument("--serve-budget-gb", type=float, default=200.0)
     p.add_argument("--accuracy", default=None,
                    help="instead of timing: run 'dcut,L,beta,h' in FP64, FP32 and BF16x3 with impure E and M "
                         "and print the relative errors of f, E, M against the FP64 path")
@@ -214,6 +223,30 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.accuracy:
         print(json.dumps(accuracy(a.accuracy)), flush=True)
+        return
+    if a.serve:
+        from paper_1911_12954_amd.serve import Server, TrgBackend
+        from trg_inputs import serving_requests
+        dcuts = tuple(int(x) for x in a.serve_dcuts.split(","))
+        kmin, kmax = (int(x) for x in a.serve_k.split(","))
+        reqs = serving_requests(a.serve_n, a.serve_rate, seed=0, dcuts=dcuts, kmin=kmin, kmax=kmax)
+        srv = Server(TrgBackend(a.serve_precision), int(a.serve_budget_gb * 2 ** 30))
+        progress(f"serving {len(reqs)} requests, window {a.serve_window} s")
+        summ = srv.serve(reqs, window=a.serve_window)
+        srv.close()
+        by_dcut = {}
+        for r in srv.results:
+            by_dcut.setdefault(r["dcut"], []).append(r["latency"])
+        print(json.dumps({
+            "metric": "served HOTRG solves/s and latency (continuous batching, 1 GPU)",
+            "value": summ["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
+            "dtype": a.serve_precision, "data": "synthetic Poisson stream",
+            "config": {"workload": "Poisson stream: beta~U[0.1490,0.1505], h in {0,1e-6,1e-5}, Dcut in %s, "
+                                   "L=2^k, k~U{%d..%d}, rate %.2f/s, window %.0f s" %
+                                   (list(dcuts), kmin, kmax, a.serve_rate, a.serve_window)},
+            "summary": summ,
+            "completed_by_dcut": {str(k): len(v) for k, v in sorted(by_dcut.items())}}), flush=True)
         return
     if a.method == "atrg":
         D = a.dcut if a.dcut != 10 else 24

@@ -346,7 +346,7 @@ void cholqr3(trg_ctx &c, const double *Y, int64_t m, int k, double *Q, double *R
     hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, c.st, Cg, k, shift, R, Ri, c.errp());
     TRG_HIP_CHECK(hipGetLastError());
     double *dst = pass == 2 ? Q : (pass == 0 ? bufA : bufB);
-    apply_map(src, IN_F64, vk, Ri, {{"k", int64_t(k)}, {"c", 1}}, {"k"}, dst, OUT_F64, 0, vy, c.st);
+    einsum2(c, src, vk, Ri, contiguous({{"k", k}, {"c", k}}), dst, {"i", "c"}, TRG_FP64, "qm" + tag);
     if (Rout) {
       if (pass == 0) {
         TRG_HIP_CHECK(hipMemcpyAsync(Racc, R, size_t(k) * k * 8, hipMemcpyDeviceToDevice, c.st));
@@ -408,8 +408,23 @@ void einsum2(trg_ctx &c, const double *A, const View &va, const double *B, const
     kc.push_back({n, s});
     K *= s;
   }
-  const GemmTile t = gemm_tile(prec);
-  const int64_t Mp = int64_t(round_up(M, t.m)), Np = int64_t(round_up(N, t.n)), Kp = int64_t(round_up(K, t.k));
+  // few output tiles and a long K (tall-skinny Gram products of the RSVD):
+  // split K over many workgroups with the 64 x 64 FP64 kernel, then reduce
+  const GemmTile t0 = gemm_tile(prec);
+  const int64_t tiles128 = int64_t(round_up(M, t0.m) / t0.m) * int64_t(round_up(N, t0.n) / t0.n);
+  const bool splitk = prec == TRG_FP64 && tiles128 < 128 && K >= 4096;
+  int64_t splits = 1, kper = 0;
+  GemmTile t = t0;
+  if (splitk) {
+    t = GemmTile{64, 64, 16};
+    const int64_t tiles64 = int64_t(round_up(M, 64) / 64) * int64_t(round_up(N, 64) / 64);
+    splits = (1024 + tiles64 - 1) / tiles64;
+    const int64_t kt = (K + 15) / 16;
+    if (splits > kt) splits = kt;
+    kper = int64_t(round_up((K + splits - 1) / splits, 16));
+  }
+  const int64_t Mp = int64_t(round_up(M, t.m)), Np = int64_t(round_up(N, t.n));
+  const int64_t Kp = splitk ? kper * splits : int64_t(round_up(K, t.k));
   const int esz = prec == TRG_FP64 ? 8 : 4;
   const int okind = prec == TRG_FP64 ? OUT_F64 : OUT_F32;
   void *Ap = c.wsp<char>("e2A" + tag, size_t(Mp) * Kp * esz);
@@ -424,8 +439,14 @@ void einsum2(trg_ctx &c, const double *A, const View &va, const double *B, const
   // the GEMM writes C directly when the output is [fa, fb] unpadded in FP64
   std::vector<std::string> natural = fa;
   natural.insert(natural.end(), fb.begin(), fb.end());
-  const bool direct = prec == TRG_FP64 && Mp == M && Np == N && natural == out_names;
+  const bool direct = !splitk && prec == TRG_FP64 && Mp == M && Np == N && natural == out_names;
   void *Cp = direct ? static_cast<void *>(C) : c.wsp<char>("e2C" + tag, size_t(Mp) * Np * esz);
+  if (splitk) {
+    double *part = c.wsp<double>("e2P" + tag, size_t(splits) * Mp * Np * 8);
+    gemm_nt_splitk_f64(static_cast<const double *>(Ap), static_cast<const double *>(Bp), part, uint64_t(Mp),
+                       uint64_t(Np), uint64_t(Kp), uint64_t(Kp), uint64_t(Kp), uint32_t(splits), uint64_t(kper), c.st);
+    reduce_splits(part, int(splits), M, N, Np, Mp * Np, static_cast<double *>(Cp), Np, c.st);
+  } else {
   // the ATRG contraction GEMMs ("k2") are the timed kernel of an ATRG step
   const bool timed = c.profiling && tag == "k2";
   hipEvent_t e0{}, e1{};
@@ -441,6 +462,7 @@ void einsum2(trg_ctx &c, const double *A, const View &va, const double *B, const
     c.join_events.push_back({e0, e1});
     c.join_launches += 1;
     c.join_flops_pending += 2.0 * double(M) * double(N) * double(K);
+  }
   }
   if (direct) return;
   View cv = contiguous(ra, Np), cb = contiguous(rb);

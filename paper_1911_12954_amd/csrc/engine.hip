@@ -308,9 +308,17 @@ void join(trg_ctx &c, int prec, const void *A, const void *Bt, void *E, int64_t 
   c.join_flops_pending += 2.0 * double(Mpad) * double(Npad) * double(Kpad);
 }
 
-void hotrg_step_impl(trg_ctx &c, int mu, int dcut) {
-  const int d = c.d;
+struct StepPrep {
   StepShape sh;
+  int n_step;
+  double *rd;
+  int *ri;
+};
+
+StepPrep prepare_step(trg_ctx &c, int mu, int dcut) {
+  const int d = c.d;
+  StepPrep p;
+  StepShape &sh = p.sh;
   sh.mu = mu;
   sh.prec = c.cfg.precision;
   for (int ax = 0; ax < d; ++ax)
@@ -321,39 +329,59 @@ void hotrg_step_impl(trg_ctx &c, int mu, int dcut) {
     const int64_t sq = int64_t(c.dims[ax]) * c.dims[ax];
     sh.nd[ax] = ax == mu ? c.dims[ax] : int(sq < dcut ? sq : dcut);
   }
-  const int n_step = c.nsteps + 1;
-  ensure_records(c, n_step + 1);
-  double *rd = rec_d(c, n_step);
-  int *ri = rec_i(c, n_step);
+  p.n_step = c.nsteps + 1;
+  ensure_records(c, p.n_step + 1);
+  p.rd = rec_d(c, p.n_step);
+  p.ri = rec_i(c, p.n_step);
+  return p;
+}
 
-  // ---- 1-2: Gram matrices, eigendecomposition, isometries
-  for (int ax : sh.others) {
-    const int dn = c.dims[ax];
+// Gram matrices of every context into one buffer, one batched Jacobi launch
+// for all of them, then each context's isometry selection.  Every matrix is
+// processed by its own workgroup, so a batch gives the same bits as single
+// contexts.
+void isometries_batch(std::vector<trg_ctx *> &cs, std::vector<StepPrep> &ps, int mu) {
+  trg_ctx &c0 = *cs[0];
+  const int nc = int(cs.size());
+  for (int ax : ps[0].sh.others) {
+    const int dn = c0.dims[ax];
     const int n = dn * dn;
-    const int dmu = c.dims[mu];
+    const int dmu = c0.dims[mu];
     const int64_t R = int64_t(dmu) * dn;
-    double *PQ = c.wsp<double>("gram_PQ", size_t(2) * R * R * 8);
-    double *G = c.wsp<double>("gram_G", size_t(2) * n * n * 8);
-    double *W = c.wsp<double>("gram_W", size_t(2) * n * 8);
-    double *V = c.wsp<double>("gram_V", size_t(2) * n * n * 8);
-    int *sw = c.wsp<int>("gram_sweeps", 2 * 4);
-    const double *T = static_cast<const double *>(c.T.ptr);
-    for (int side = 0; side < 2; ++side) {
-      environment(c, T, 2 * mu + 1, 2 * ax + side, PQ, "");
-      environment(c, T, 2 * mu, 2 * ax + side, PQ + R * R, "");
-      gram_combine(PQ, PQ + R * R, dmu, dn, G + size_t(side) * n * n, c.st);
+    double *G = c0.wsp<double>("gram_G", size_t(nc) * 2 * n * n * 8);
+    double *W = c0.wsp<double>("gram_W", size_t(nc) * 2 * n * 8);
+    double *V = c0.wsp<double>("gram_V", size_t(nc) * 2 * n * n * 8);
+    int *sw = c0.wsp<int>("gram_sweeps", size_t(nc) * 2 * 4);
+    for (int i = 0; i < nc; ++i) {
+      trg_ctx &c = *cs[i];
+      double *PQ = c.wsp<double>("gram_PQ", size_t(2) * R * R * 8);
+      const double *T = static_cast<const double *>(c.T.ptr);
+      for (int side = 0; side < 2; ++side) {
+        environment(c, T, 2 * mu + 1, 2 * ax + side, PQ, "");
+        environment(c, T, 2 * mu, 2 * ax + side, PQ + R * R, "");
+        gram_combine(PQ, PQ + R * R, dmu, dn, G + (size_t(i) * 2 + side) * n * n, c.st);
+      }
     }
-    eigh_batched(G, W, V, sw, n, 2, c.st);
-    const int k = sh.nd[ax];
-    c.ensure(c.U[ax], size_t(n) * k * 8);
-    c.ensure(c.spec[ax], size_t(n) * 8);
-    c.Un[ax] = n;
-    c.Uk[ax] = k;
-    SelectOut so{static_cast<double *>(c.U[ax].ptr), rd + 1 + 2 * ax, ri + 4 * ax,
-                 static_cast<double *>(c.spec[ax].ptr)};
-    select_isometry(W, V, sw, n, k, c.force_side, so, c.st);
+    eigh_batched(G, W, V, sw, n, 2 * nc, c0.st);
+    for (int i = 0; i < nc; ++i) {
+      trg_ctx &c = *cs[i];
+      const int k = ps[i].sh.nd[ax];
+      c.ensure(c.U[ax], size_t(n) * k * 8);
+      c.ensure(c.spec[ax], size_t(n) * 8);
+      c.Un[ax] = n;
+      c.Uk[ax] = k;
+      SelectOut so{static_cast<double *>(c.U[ax].ptr), ps[i].rd + 1 + 2 * ax, ps[i].ri + 4 * ax,
+                   static_cast<double *>(c.spec[ax].ptr)};
+      select_isometry(W + size_t(i) * 2 * n, V + size_t(i) * 2 * n * n, sw + 2 * i, n, k, c.force_side, so, c.st);
+    }
   }
+}
 
+void contract_step(trg_ctx &c, StepPrep &prep, int mu) {
+  const int d = c.d;
+  StepShape &sh = prep.sh;
+  const int n_step = prep.n_step;
+  double *rd = prep.rd;
   // ---- 3: block-spin contraction, sliced over x0 (A) and x2 (Bt)
   const GemmTile tile = gemm_tile(sh.prec);
   sh.Mr = 1;
@@ -458,6 +486,15 @@ void hotrg_step_impl(trg_ctx &c, int mu, int dcut) {
   for (int ax = 0; ax < d; ++ax) c.dims[ax] = sh.nd[ax];
   c.nsteps = n_step;
 }
+
+void hotrg_step_batch_impl(std::vector<trg_ctx *> cs, int mu, int dcut) {
+  std::vector<StepPrep> ps;
+  for (auto *c : cs) ps.push_back(prepare_step(*c, mu, dcut));
+  isometries_batch(cs, ps, mu);
+  for (size_t i = 0; i < cs.size(); ++i) contract_step(*cs[i], ps[i], mu);
+}
+
+void hotrg_step_impl(trg_ctx &c, int mu, int dcut) { hotrg_step_batch_impl({&c}, mu, dcut); }
 
 // ------------------------------------------------------------- helpers ---
 int fail(trg_ctx *c, int code, const std::string &msg) {
@@ -639,11 +676,16 @@ int trg_hotrg_step_batch(trg_ctx *const *ctxs, int n, int axis, int dcut) {
     for (int a = 0; a < ctxs[0]->d; ++a)
       if (ctxs[i]->dims[a] != ctxs[0]->dims[a]) return fail(nullptr, TRG_EINVAL, "batch contexts differ in dims");
   }
-  for (int i = 0; i < n; ++i) {
-    const int rc = trg_hotrg_step(ctxs[i], axis, dcut);
-    if (rc != TRG_OK) return rc;
-  }
-  return TRG_OK;
+  for (int i = 0; i < n; ++i)
+    if (ctxs[i]->poisoned) return fail(ctxs[i], TRG_ESTATE, "context is poisoned by an earlier device error");
+  if (axis < 0 || axis >= ctxs[0]->d || dcut < 1 || dcut > 1024) return fail(nullptr, TRG_EINVAL, "bad axis or dcut");
+  for (int i = 0; i < n; ++i)
+    if (ctxs[i]->cfg.method != TRG_HOTRG) return fail(nullptr, TRG_EINVAL, "batch contexts must be HOTRG");
+  return guarded(nullptr, [&]() -> int {
+    std::vector<trg_ctx *> cs(ctxs, ctxs + n);
+    hotrg_step_batch_impl(cs, axis, dcut);
+    return TRG_OK;
+  });
 }
 
 int trg_atrg_step(trg_ctx *ctx, int axis, int dcut) {

@@ -1,0 +1,210 @@
+"""Continuous-batching solve server for HOTRG runs (beta/h scans around T_c).
+
+Requests (beta, h, Dcut, L, method) arrive over time.  The server
+
+* admits a request while the summed device footprint of the admitted runs
+  (trg_footprint_bytes: resident tensors plus join workspace) stays within
+  the HBM budget; waiting requests are admitted as soon as finished runs
+  free their memory;
+* keeps each run's tensors resident until it finishes;
+* runs one lane (HIP stream) per bond dimension, so lanes of different Dcut
+  overlap on the device; inside a lane, runs whose leg dims and next axis
+  agree are stepped together by one batched library call
+  (trg_hotrg_step_batch), otherwise one call per run;
+* advances a lane as soon as its previous step has completed (event query,
+  no global barrier), and records arrival, admission and completion times.
+
+Every result is computed by the same kernels in the same order as a run
+alone, so it does not depend on what else is in the mix.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+
+@dataclass
+class Run:
+    req: dict
+    handle: object
+    total: int
+    done: int = 0
+    t_admit: float = 0.0
+
+
+@dataclass
+class Lane:
+    dcut: int
+    stream: object
+    runs: list = field(default_factory=list)
+    event: object = None
+
+
+class TrgBackend:
+    """The HIP library through its Python binding."""
+
+    def __init__(self, precision="fp32", d=4):
+        import torch
+        self.torch = torch
+        self.precision = precision
+        self.d = d
+
+    def footprint(self, req) -> int:
+        from .trg import trg_footprint_bytes
+        return trg_footprint_bytes(self.d, req["dcut"], self.precision, "hotrg")
+
+    def new_lane(self, dcut):
+        return self.torch.cuda.Stream()
+
+    def create(self, req, stream):
+        from .trg import trg_init_ising
+        return trg_init_ising(req["beta"], req["h"], self.d, dcut=req["dcut"], precision=self.precision,
+                              stream=stream)
+
+    def dims(self, h):
+        return h.dims()[0]
+
+    def step(self, handles, axis, dcut):
+        from .trg import trg_hotrg_step_batch
+        if len(handles) == 1:
+            handles[0].hotrg_step(axis, dcut)
+        else:
+            trg_hotrg_step_batch(handles, axis, dcut)
+
+    def mark(self, stream):
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        return ev
+
+    def ready(self, ev) -> bool:
+        return ev is None or ev.query()
+
+    def result(self, h) -> float:
+        return h.free_energy()
+
+    def close(self, h):
+        h.close()
+
+
+class Server:
+    def __init__(self, backend, hbm_budget: int, d: int = 4, max_batch: int = 64):
+        self.be = backend
+        self.budget = int(hbm_budget)
+        self.d = d
+        self.max_batch = max_batch
+        self.lanes = {}
+        self.used = 0
+        self.peak_used = 0
+        self.results = []
+        self.batch_calls = 0
+        self.batched_runs = 0
+
+    def _lane(self, dcut):
+        if dcut not in self.lanes:
+            self.lanes[dcut] = Lane(dcut, self.be.new_lane(dcut))
+        return self.lanes[dcut]
+
+    def _admit(self, req, now):
+        fp = self.be.footprint(req)
+        if fp > self.budget:
+            raise ValueError(f"request {req['id']} needs {fp} bytes, more than the whole budget")
+        if self.used + fp > self.budget:
+            return False
+        lane = self._lane(req["dcut"])
+        h = self.be.create(req, lane.stream)
+        m = req["L"].bit_length() - 1
+        lane.runs.append(Run(req, h, self.d * m, 0, now))
+        self.used += fp
+        self.peak_used = max(self.peak_used, self.used)
+        return True
+
+    def _advance(self, lane, now, t0):
+        """Finish completed runs of a lane whose last step is done, then issue
+        the next step of every remaining run (batched by leg dims)."""
+        if not self.be.ready(lane.event):
+            return False
+        lane.event = None
+        still = []
+        for run in lane.runs:
+            if run.done >= run.total:
+                lnz = self.be.result(run.handle)
+                self.be.close(run.handle)
+                self.used -= self.be.footprint(run.req)
+                t_done = time.perf_counter() - t0
+                self.results.append({"id": run.req["id"], "lnz": lnz, "arrival": run.req["arrival"],
+                                     "admitted": run.t_admit, "done": t_done,
+                                     "latency": t_done - run.req["arrival"], "dcut": run.req["dcut"],
+                                     "L": run.req["L"], "beta": run.req["beta"], "h": run.req["h"]})
+            else:
+                still.append(run)
+        lane.runs = still
+        if not still:
+            return True
+        groups = {}
+        for run in still:
+            axis = run.done % self.d
+            key = (tuple(self.be.dims(run.handle)), axis)
+            groups.setdefault(key, []).append(run)
+        for (dims, axis), runs in groups.items():
+            for i in range(0, len(runs), self.max_batch):
+                chunk = runs[i:i + self.max_batch]
+                self.be.step([r.handle for r in chunk], axis, lane.dcut)
+                self.batch_calls += 1
+                self.batched_runs += len(chunk)
+                for r in chunk:
+                    r.done += 1
+        lane.event = self.be.mark(lane.stream)
+        return True
+
+    def serve(self, requests, window: float = None, idle_sleep: float = 5e-4):
+        """Process `requests` (dicts with an 'arrival' time in seconds) in
+        real time until all are done or `window` seconds have passed.
+        Returns a summary with completed solves/s and latency percentiles."""
+        pending = sorted(requests, key=lambda r: r["arrival"])
+        waiting = []
+        t0 = time.perf_counter()
+        i = 0
+        while True:
+            now = time.perf_counter() - t0
+            if window is not None and now >= window:
+                break
+            while i < len(pending) and pending[i]["arrival"] <= now:
+                waiting.append(pending[i])
+                i += 1
+            # first come, first served while memory allows
+            while waiting and self._admit(waiting[0], now):
+                waiting.pop(0)
+            progressed = False
+            for lane in list(self.lanes.values()):
+                progressed |= self._advance(lane, now, t0)
+            active = sum(len(l.runs) for l in self.lanes.values())
+            if i >= len(pending) and not waiting and active == 0:
+                break
+            if not progressed:
+                time.sleep(idle_sleep)
+        elapsed = time.perf_counter() - t0
+        return self.summary(elapsed, len(requests))
+
+    def summary(self, elapsed, submitted):
+        import numpy as np
+        lat = np.array([r["latency"] for r in self.results]) if self.results else np.zeros(0)
+        active = sum(len(l.runs) for l in self.lanes.values())
+        return {
+            "submitted": submitted,
+            "completed": len(self.results),
+            "censored_active": active,
+            "elapsed_s": elapsed,
+            "solves_per_s": len(self.results) / elapsed if elapsed > 0 else 0.0,
+            "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
+            "peak_footprint_bytes": self.peak_used,
+            "budget_bytes": self.budget,
+            "step_calls": self.batch_calls,
+            "mean_runs_per_call": self.batched_runs / self.batch_calls if self.batch_calls else 0.0,
+        }
+
+    def close(self):
+        for lane in self.lanes.values():
+            for run in lane.runs:
+                self.be.close(run.handle)
+            lane.runs = []

@@ -1,0 +1,36 @@
+"""The solve server on the GPU: results in a mix of concurrent, batched runs
+are bit-for-bit those of the same runs alone, and one of them matches the
+oracle."""
+import pytest
+
+from oracle import hotrg
+from tests.gpu_util import announce, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+MIX = [
+    {"id": 0, "arrival": 0.00, "beta": 0.1490, "h": 0.0, "dcut": 4, "L": 16, "method": "hotrg"},
+    {"id": 1, "arrival": 0.00, "beta": 0.1497, "h": 1e-5, "dcut": 4, "L": 16, "method": "hotrg"},
+    {"id": 2, "arrival": 0.00, "beta": 0.1505, "h": 1e-6, "dcut": 4, "L": 16, "method": "hotrg"},
+    {"id": 3, "arrival": 0.02, "beta": 0.1500, "h": 0.0, "dcut": 5, "L": 4, "method": "hotrg"},
+    {"id": 4, "arrival": 0.05, "beta": 0.1495, "h": 1e-5, "dcut": 4, "L": 8, "method": "hotrg"},
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_results_in_the_mix_equal_results_alone(precision):
+    need_gpu()
+    from paper_1911_12954_amd.serve import Server, TrgBackend
+    announce("serve mix", precision)
+    srv = Server(TrgBackend(precision), 64 * 2 ** 30)
+    out = srv.serve(MIX)
+    assert out["completed"] == len(MIX)
+    assert out["mean_runs_per_call"] > 1.0       # same-shape steps were batched
+    mix = {r["id"]: r["lnz"] for r in srv.results}
+    for req in MIX:
+        alone = Server(TrgBackend(precision), 64 * 2 ** 30)
+        alone.serve([dict(req, arrival=0.0)])
+        assert alone.results[0]["lnz"] == mix[req["id"]], req
+    if precision == "fp64":
+        r = hotrg.run(0.1497, 1e-5, 4, 4, 16, impure=False)
+        assert abs(mix[1] - r.ln_z_per_site) <= 1e-10 * abs(r.ln_z_per_site)

@@ -1,0 +1,126 @@
+"""Scheduling logic of the solve server on the CPU, with a stand-in backend
+that follows the same leg-dim schedule as HOTRG and completes steps after a
+fixed number of polls (no GPU, no kernels)."""
+import pytest
+
+from paper_1911_12954_amd.serve import Server
+from trg_inputs import serving_requests
+
+
+class FakeHandle:
+    def __init__(self, req):
+        self.req = req
+        self.dims = [2, 2, 2, 2]
+        self.steps = 0
+
+
+class FakeBackend:
+    """Footprint grows like D^8; a lane's step completes after `lag` polls."""
+
+    def __init__(self, lag=2):
+        self.lag = lag
+        self.live = 0
+        self.max_live = 0
+        self.calls = []
+
+    def footprint(self, req):
+        return 10 * req["dcut"] ** 8
+
+    def new_lane(self, dcut):
+        return {"dcut": dcut}
+
+    def create(self, req, stream):
+        self.live += 1
+        self.max_live = max(self.max_live, self.live)
+        return FakeHandle(req)
+
+    def dims(self, h):
+        return tuple(h.dims)
+
+    def step(self, handles, axis, dcut):
+        self.calls.append((len(handles), axis, dcut))
+        for h in handles:
+            for a in range(4):
+                if a != axis:
+                    h.dims[a] = min(h.dims[a] ** 2, dcut)
+            h.steps += 1
+
+    def mark(self, stream):
+        return {"polls": self.lag}
+
+    def ready(self, ev):
+        if ev is None:
+            return True
+        ev["polls"] -= 1
+        return ev["polls"] <= 0
+
+    def result(self, h):
+        return float(h.req["beta"]) + h.steps
+
+    def close(self, h):
+        self.live -= 1
+
+
+def test_every_request_completes_and_budget_is_respected():
+    reqs = serving_requests(40, rate=2000.0, seed=1, dcuts=(4, 6, 8), kmin=2, kmax=4)
+    be = FakeBackend()
+    budget = 3 * 10 * 8 ** 8
+    srv = Server(be, budget)
+    out = srv.serve(reqs, idle_sleep=0)
+    assert out["completed"] == 40 and out["censored_active"] == 0
+    assert srv.peak_used <= budget
+    assert be.live == 0
+    for r in srv.results:
+        assert r["latency"] >= 0 and r["admitted"] >= r["arrival"] and r["done"] >= r["admitted"]
+        # each run took exactly d * log2 L steps
+        assert r["lnz"] == pytest.approx(r["beta"] + 4 * (r["L"].bit_length() - 1))
+
+
+def test_same_shape_runs_share_calls():
+    reqs = [{"id": i, "arrival": 0.0, "beta": 0.149 + 1e-4 * i, "h": 0.0, "dcut": 6, "L": 16, "method": "hotrg"}
+            for i in range(5)]
+    be = FakeBackend(lag=1)
+    srv = Server(be, 10 ** 12)
+    srv.serve(reqs, idle_sleep=0)
+    assert all(n == 5 for n, _, _ in be.calls)
+    assert len(be.calls) == 16
+
+
+def test_continuous_admission_while_others_run():
+    """A request that arrives while another is being stepped is admitted
+    before that one finishes (no waiting for a full batch to drain)."""
+    reqs = [{"id": 0, "arrival": 0.0, "beta": 0.149, "h": 0.0, "dcut": 6, "L": 1024, "method": "hotrg"},
+            {"id": 1, "arrival": 0.01, "beta": 0.150, "h": 0.0, "dcut": 6, "L": 16, "method": "hotrg"}]
+    be = FakeBackend(lag=200)
+    srv = Server(be, 10 ** 12)
+    srv.serve(reqs, idle_sleep=1e-4)
+    res = {r["id"]: r for r in srv.results}
+    assert res[1]["admitted"] < res[0]["done"]
+    assert res[1]["done"] < res[0]["done"]
+
+
+def test_memory_bound_admission_waits_for_frees():
+    reqs = [{"id": i, "arrival": 0.0, "beta": 0.149, "h": 0.0, "dcut": 8, "L": 4, "method": "hotrg"} for i in range(3)]
+    be = FakeBackend(lag=1)
+    srv = Server(be, 10 * 8 ** 8)   # room for one run at a time
+    srv.serve(reqs, idle_sleep=0)
+    assert be.max_live == 1 and len(srv.results) == 3
+    done = sorted(srv.results, key=lambda r: r["id"])
+    assert done[0]["done"] <= done[1]["admitted"] + 1e-9
+
+
+def test_oversized_request_is_rejected():
+    be = FakeBackend()
+    srv = Server(be, 100)
+    with pytest.raises(ValueError):
+        srv.serve([{"id": 0, "arrival": 0.0, "beta": 0.15, "h": 0.0, "dcut": 8, "L": 4, "method": "hotrg"}])
+
+
+def test_window_censors_unfinished_runs():
+    reqs = [{"id": 0, "arrival": 0.0, "beta": 0.15, "h": 0.0, "dcut": 6, "L": 1024, "method": "hotrg"}]
+    be = FakeBackend(lag=10 ** 9)
+    srv = Server(be, 10 ** 12)
+    out = srv.serve(reqs, window=0.05)
+    assert out["completed"] == 0 and out["censored_active"] == 1
+    srv.close()
+    assert be.live == 0
