@@ -85,11 +85,14 @@ __global__ void trial_kernel(double *out, uint32_t count, uint32_t step, uint32_
 // numerically dependent on the previous ones (rank-deficient Y): that column
 // of Q is set to zero (column of Rinv zero) and its row of R is zero, so
 // Y = Q R still holds and no division by a vanishing pivot occurs.
+template <bool IN_LDS>
 __global__ void __launch_bounds__(256)
-chol_inv_kernel(const double *C, int n, double shift_coef, double *R, double *Rinv, int *err) {
+chol_inv_kernel(const double *C, int n, double shift_coef, double *Rg, double *Rinv, int *err) {
+  extern __shared__ double Rlds[];
   __shared__ double sh[256];
   __shared__ double shm[256];
   __shared__ int dead[1024];
+  double *R = IN_LDS ? Rlds : Rg;  // working copy of the factor
   const int t = threadIdx.x;
   double tr = 0.0, mx = 0.0;
   for (int i = t; i < n; i += 256) {
@@ -122,7 +125,7 @@ chol_inv_kernel(const double *C, int n, double shift_coef, double *R, double *Ri
       double dj = R[j * n + j];
       for (int k = 0; k < j; ++k) dj -= R[k * n + j] * R[k * n + j];
       if (!(dj > tol)) {
-        if (!(dj > -1e3 * tol) && !isfinite(dj)) *err |= 4;
+        if (!isfinite(dj)) *err |= 4;
         dead[j] = 1;
         dj = 1.0;
       }
@@ -151,8 +154,26 @@ chol_inv_kernel(const double *C, int n, double shift_coef, double *R, double *Ri
   for (int i = t; i < n * n; i += 256) {
     const int r = i / n, c = i % n;
     if (dead[c]) Rinv[i] = 0.0;
-    if (dead[r]) R[i] = 0.0;
+    const double v = dead[r] ? 0.0 : R[i];
+    if (IN_LDS) Rg[i] = v;
+    else R[i] = v;
   }
+}
+
+void launch_chol_inv(const double *C, int n, double shift, double *R, double *Rinv, int *err, hipStream_t st) {
+  TRG_REQUIRE(n >= 1 && n <= 1024, "chol: bad order");
+  if (n <= 128) {
+    static bool attr = false;
+    if (!attr) {
+      TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&chol_inv_kernel<true>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 128 * 8));
+      attr = true;
+    }
+    hipLaunchKernelGGL(chol_inv_kernel<true>, dim3(1), dim3(256), size_t(n) * n * 8, st, C, n, shift, R, Rinv, err);
+  } else {
+    hipLaunchKernelGGL(chol_inv_kernel<false>, dim3(1), dim3(256), 0, st, C, n, shift, R, Rinv, err);
+  }
+  TRG_HIP_CHECK(hipGetLastError());
 }
 
 // C = A B for n x n matrices (one workgroup)
@@ -343,8 +364,7 @@ void cholqr3(trg_ctx &c, const double *Y, int64_t m, int k, double *Q, double *R
   for (int pass = 0; pass < 3; ++pass) {
     einsum2(c, src, vy, src, rename(vy, {{"c", "c2"}}), Cg, {"c", "c2"}, TRG_FP64, "qr" + tag);
     const double shift = pass == 0 ? 11.0 * (double(m) * k + double(k) * (k + 1)) * u : 0.0;
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, c.st, Cg, k, shift, R, Ri, c.errp());
-    TRG_HIP_CHECK(hipGetLastError());
+    launch_chol_inv(Cg, k, shift, R, Ri, c.errp(), c.st);
     double *dst = pass == 2 ? Q : (pass == 0 ? bufA : bufB);
     einsum2(c, src, vk, Ri, contiguous({{"k", k}, {"c", k}}), dst, {"i", "c"}, TRG_FP64, "qm" + tag);
     if (Rout) {

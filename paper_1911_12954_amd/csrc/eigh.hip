@@ -157,6 +157,213 @@ jacobi_kernel(double *Aall, double *wall, double *Vall, int *sweeps_out, int n) 
   }
 }
 
+// ------------------------------------------ tridiagonalisation + QL (large n) ---
+// For larger orders a sweep-based Jacobi streams the whole matrix through one
+// CU thousands of times.  This solver reduces A to tridiagonal form with
+// Householder reflections (A <- H A H, H = I - 2 v v^T / v^T v, one column at
+// a time), accumulates Q = H_0 H_1 ..., then diagonalises the tridiagonal
+// matrix by implicit QL iterations with Wilkinson-type shifts.  Thread 0 runs
+// the scalar QL recurrence and records the Givens rotations of one sweep in
+// LDS; all threads then apply the sweep to their rows of the eigenvector
+// matrix.  Deterministic (fixed order everywhere).
+constexpr int TQ_THREADS = 1024;
+constexpr int TQ_MAX = 1024;
+
+__device__ inline double tq_sum(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = TQ_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(TQ_THREADS)
+tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) {
+  __shared__ double sh[TQ_THREADS];
+  __shared__ double vv[TQ_MAX], ww[TQ_MAX];
+  __shared__ double dd[TQ_MAX], ee[TQ_MAX];
+  __shared__ double rc[TQ_MAX], rs[TQ_MAX];
+  __shared__ int rank[TQ_MAX];
+  __shared__ int sweep_lo, sweep_hi, done_flag, iters_total;
+  const int b = blockIdx.x;
+  double *A = Aall + size_t(b) * n * n;
+  double *V = Vall + size_t(b) * n * n;   // Householder vectors, then Q, then eigenvectors
+  double *w = wall + size_t(b) * n;
+  const int t = threadIdx.x;
+
+  // ---- Householder tridiagonalisation; v_k stored in column k of V (rows k+1..n-1)
+  for (int i = t; i < n * n; i += TQ_THREADS) V[i] = 0.0;
+  __syncthreads();
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;              // length of the column below the diagonal
+    double s2 = 0.0;
+    for (int i = t; i < m; i += TQ_THREADS) {
+      const double x = A[(k + 1 + i) * n + k];
+      vv[i] = x;
+      s2 += x * x;
+    }
+    const double nrm2 = tq_sum(s2, sh);
+    const double x0 = vv[0];
+    const double alpha = x0 >= 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
+    const double vtv = nrm2 - 2.0 * alpha * x0 + alpha * alpha;  // |x - alpha e1|^2
+    __syncthreads();
+    if (t == 0) vv[0] = x0 - alpha;
+    __syncthreads();
+    if (!(vtv > 0.0)) continue;          // column already reduced: H = I
+    const double tau = 2.0 / vtv;
+    // p = tau A_sub v  (A symmetric: column access, coalesced across threads)
+    for (int j = t; j < m; j += TQ_THREADS) {
+      double acc = 0.0;
+      for (int i = 0; i < m; ++i) acc += A[(k + 1 + i) * n + (k + 1 + j)] * vv[i];
+      ww[j] = tau * acc;
+    }
+    __syncthreads();
+    double pv = 0.0;
+    for (int i = t; i < m; i += TQ_THREADS) pv += ww[i] * vv[i];
+    const double K = 0.5 * tau * tq_sum(pv, sh);
+    for (int j = t; j < m; j += TQ_THREADS) ww[j] -= K * vv[j];   // w = p - K v
+    __syncthreads();
+    // A_sub <- A_sub - v w^T - w v^T
+    for (int idx = t; idx < m * m; idx += TQ_THREADS) {
+      const int i = idx / m, j = idx % m;
+      A[(k + 1 + i) * n + (k + 1 + j)] -= vv[i] * ww[j] + ww[i] * vv[j];
+    }
+    for (int i = t; i < m; i += TQ_THREADS) {
+      const double val = i == 0 ? alpha : 0.0;
+      A[(k + 1 + i) * n + k] = val;
+      A[k * n + (k + 1 + i)] = val;
+      V[(k + 1 + i) * n + k] = vv[i] * sqrt(tau);   // scaled: H = I - u u^T
+    }
+    __syncthreads();
+  }
+  for (int i = t; i < n; i += TQ_THREADS) {
+    dd[i] = A[i * n + i];
+    ee[i] = i + 1 < n ? A[(i + 1) * n + i] : 0.0;
+  }
+  __syncthreads();
+  // ---- Q = H_0 H_1 ... H_{n-3}, built backwards in A (Q_k = H_k Q_{k+1})
+  for (int i = t; i < n * n; i += TQ_THREADS) A[i] = (i / n == i % n) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = n - 3; k >= 0; --k) {
+    const int m = n - k - 1;
+    for (int i = t; i < m; i += TQ_THREADS) vv[i] = V[(k + 1 + i) * n + k];
+    __syncthreads();
+    // ww[j] = sum_i u_i Q[k+1+i][k+1+j]; then Q_sub -= u ww^T
+    for (int j = t; j < m; j += TQ_THREADS) {
+      double acc = 0.0;
+      for (int i = 0; i < m; ++i) acc += vv[i] * A[(k + 1 + i) * n + (k + 1 + j)];
+      ww[j] = acc;
+    }
+    __syncthreads();
+    for (int idx = t; idx < m * m; idx += TQ_THREADS) {
+      const int i = idx / m, j = idx % m;
+      A[(k + 1 + i) * n + (k + 1 + j)] -= vv[i] * ww[j];
+    }
+    __syncthreads();
+  }
+  // ---- implicit QL on (dd, ee) with rotations applied to the rows of A (= Q).
+  // An off-diagonal entry deflates when it is at the rounding level of its
+  // neighbours or of the whole matrix (anorm): next to rounding-level zero
+  // diagonals (rank-deficient Grams) a purely relative test never fires.
+  __shared__ double anorm;
+  if (t == 0) {
+    iters_total = 0;
+    done_flag = 0;
+    double md = 0.0, me = 0.0;
+    for (int i = 0; i < n; ++i) {
+      md = fmax(md, fabs(dd[i]));
+      me = fmax(me, fabs(ee[i]));
+    }
+    anorm = md + me;
+  }
+  __syncthreads();
+  for (int l = 0; l < n; ++l) {
+    int iter = 0;
+    while (true) {
+      if (t == 0) {
+        int mm = l;
+        for (; mm < n - 1; ++mm) {
+          const double s = fabs(dd[mm]) + fabs(dd[mm + 1]);
+          if (fabs(ee[mm]) <= 2.220446049250313e-16 * (s + anorm)) break;
+        }
+        done_flag = (mm == l) || iter >= 60;
+        if (iter >= 60) iters_total = -1000000;
+        sweep_lo = l;
+        sweep_hi = l - 1;   // empty rotation list unless a sweep runs
+        if (!done_flag) {
+          double g = (dd[l + 1] - dd[l]) / (2.0 * ee[l]);
+          double r = hypot(g, 1.0);
+          g = dd[mm] - dd[l] + ee[l] / (g + (g >= 0.0 ? fabs(r) : -fabs(r)));
+          double s = 1.0, c = 1.0, p = 0.0;
+          int i = mm - 1;
+          bool underflow = false;
+          for (; i >= l; --i) {
+            const double f = s * ee[i], bb = c * ee[i];
+            r = hypot(f, g);
+            ee[i + 1] = r;
+            if (r == 0.0) {
+              dd[i + 1] -= p;
+              ee[mm] = 0.0;
+              underflow = true;
+              break;
+            }
+            s = f / r;
+            c = g / r;
+            g = dd[i + 1] - p;
+            r = (dd[i] - g) * s + 2.0 * c * bb;
+            p = s * r;
+            dd[i + 1] = g + p;
+            g = c * r - bb;
+            rc[i] = c;
+            rs[i] = s;
+          }
+          sweep_hi = mm - 1;
+          sweep_lo = underflow ? i + 1 : l;
+          if (!underflow) {
+            dd[l] -= p;
+            ee[l] = g;
+            ee[mm] = 0.0;
+          }
+          ++iters_total;
+        }
+      }
+      __syncthreads();
+      if (done_flag) break;
+      // rotations i = hi down to lo act on columns (i, i+1) of every row
+      const int lo = sweep_lo, hi = sweep_hi;
+      for (int row = t; row < n; row += TQ_THREADS) {
+        double *z = A + size_t(row) * n;
+        for (int i = hi; i >= lo; --i) {
+          const double f = z[i + 1];
+          z[i + 1] = rs[i] * z[i] + rc[i] * f;
+          z[i] = rc[i] * z[i] - rs[i] * f;
+        }
+      }
+      ++iter;
+      __syncthreads();
+    }
+  }
+  if (t == 0) status[b] = iters_total >= 0 ? iters_total : -1;
+  // ---- sort descending (ties by index) and write w, V
+  for (int i = t; i < n; i += TQ_THREADS) {
+    const double v = dd[i];
+    int rk = 0;
+    for (int j = 0; j < n; ++j) rk += (dd[j] > v) || (dd[j] == v && j < i);
+    rank[i] = rk;
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += TQ_THREADS) w[rank[i]] = dd[i];
+  for (int i = t; i < n * n; i += TQ_THREADS) {
+    const int row = i / n, col = i % n;
+    V[row * n + rank[col]] = A[i];
+  }
+}
+
 // ------------------------------------------------------------- selection ---
 constexpr int SEL_THREADS = 256;
 constexpr double TIE_REL = 1e-10;      // side rule: backward only if clearly better
@@ -260,9 +467,16 @@ select_kernel(const double *w2, const double *V2, const int *sweeps2, int n, int
 
 }  // namespace
 
+// Jacobi up to order 160 (accurate, and cheap while the matrix is small),
+// tridiagonalisation + QL above.
+constexpr int JACOBI_MAX_N = 160;
+
 void eigh_batched(double *A, double *w, double *V, int *sweeps, int n, int batch, hipStream_t st) {
   TRG_REQUIRE(n >= 1 && n <= MAX_N && batch >= 1, "eigh: order must be in [1, 1024]");
-  hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(EIGH_THREADS), 0, st, A, w, V, sweeps, n);
+  if (n <= JACOBI_MAX_N)
+    hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(EIGH_THREADS), 0, st, A, w, V, sweeps, n);
+  else
+    hipLaunchKernelGGL(tridiag_ql_kernel, dim3(batch), dim3(TQ_THREADS), 0, st, A, w, V, sweeps, n);
   TRG_HIP_CHECK(hipGetLastError());
 }
 

@@ -85,8 +85,10 @@ def test_gemm_bf16x3(M, N, K):
     assert np.max(np.abs(dC.cpu().numpy() - exact) / scale) < 2.0 ** -14
 
 
-@pytest.mark.parametrize("n", [1, 2, 4, 7, 16, 33, 100, 144])
+@pytest.mark.parametrize("n", [1, 2, 4, 7, 16, 33, 100, 144, 161, 200, 333, 576])
 def test_jacobi_eigh(n):
+    """Orders up to 160 use cyclic Jacobi, larger ones Householder
+    tridiagonalisation + implicit QL."""
     torch = need_gpu()
     from paper_1911_12954_amd import trg_eigh
     announce("eigh", n)
