@@ -47,7 +47,9 @@ def parse():
     p.add_argument("--serve", action="store_true",
                    help="serving benchmark: Poisson stream of HOTRG solves, time-boxed window")
     p.add_argument("--serve-n", type=int, default=200)
-    p.add_argument("--serve-rate", type=float, default=1.0, help="arrivals per second")
+    p.add_argument("--serve-rate", type=float, default=0.0,
+                   help="arrivals per second; 0 = 0.8 of the capacity measured by a calibration pass; "
+                        "<0 = every request arrives at the start (saturation)")
     p.add_argument("--serve-window", type=float, default=60.0)
     p.add_argument("--serve-dcuts", default="6,8,10")
     p.add_argument("--serve-k", default="4,10", help="L = 2^k, k uniform in [kmin, kmax]")
@@ -229,8 +231,33 @@ def main():
         from trg_inputs import serving_requests
         dcuts = tuple(int(x) for x in a.serve_dcuts.split(","))
         kmin, kmax = (int(x) for x in a.serve_k.split(","))
-        reqs = serving_requests(a.serve_n, a.serve_rate, seed=0, dcuts=dcuts, kmin=kmin, kmax=kmax)
-        srv = Server(TrgBackend(a.serve_precision), int(a.serve_budget_gb * 2 ** 30))
+        budget = int(a.serve_budget_gb * 2 ** 30)
+        rate, calib = a.serve_rate, None
+        if rate == 0:
+            # calibration: one solve per Dcut alone at L = 2^kmin; a solve of
+            # L = 2^k costs about k/kmin times as much; the stream runs at 0.8
+            # of the capacity these service times give
+            calib = {}
+            for D in dcuts:
+                one = Server(TrgBackend(a.serve_precision), budget)
+                t = time.perf_counter()
+                one.serve([{"id": 0, "arrival": 0.0, "beta": 0.1497, "h": 0.0, "dcut": D, "L": 2 ** kmin,
+                            "method": "hotrg"}], idle_sleep=1e-4)
+                calib[D] = time.perf_counter() - t
+                one.close()
+                progress(f"calibration: Dcut {D}, L 2^{kmin} alone: {calib[D]:.3f} s")
+            ks = range(kmin, kmax + 1)
+            mean_service = sum(calib[D] * k / kmin for D in dcuts for k in ks) / (len(dcuts) * len(ks))
+            rate = 0.8 / mean_service
+            progress(f"calibration: mean service {mean_service:.3f} s, arrival rate {rate:.3f}/s")
+        if rate < 0:
+            # saturation: every request is there at the start
+            reqs = serving_requests(a.serve_n, 1.0, seed=0, dcuts=dcuts, kmin=kmin, kmax=kmax)
+            for r in reqs:
+                r["arrival"] = 0.0
+        else:
+            reqs = serving_requests(a.serve_n, rate, seed=0, dcuts=dcuts, kmin=kmin, kmax=kmax)
+        srv = Server(TrgBackend(a.serve_precision), budget)
         progress(f"serving {len(reqs)} requests, window {a.serve_window} s")
         summ = srv.serve(reqs, window=a.serve_window)
         srv.close()
@@ -243,8 +270,9 @@ def main():
             "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
             "dtype": a.serve_precision, "data": "synthetic Poisson stream",
             "config": {"workload": "Poisson stream: beta~U[0.1490,0.1505], h in {0,1e-6,1e-5}, Dcut in %s, "
-                                   "L=2^k, k~U{%d..%d}, rate %.2f/s, window %.0f s" %
-                                   (list(dcuts), kmin, kmax, a.serve_rate, a.serve_window)},
+                                   "L=2^k, k~U{%d..%d}, rate %.3f/s (<0: all at t=0), window %.0f s" %
+                                   (list(dcuts), kmin, kmax, rate, a.serve_window),
+                       "calibration_s": calib},
             "summary": summ,
             "completed_by_dcut": {str(k): len(v) for k, v in sorted(by_dcut.items())}}), flush=True)
         return

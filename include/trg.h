@@ -68,7 +68,12 @@ typedef struct trg_config {
   uint64_t seed;          /* ATRG trial-matrix seed */
   void *stream;           /* hipStream_t; NULL = default stream */
   /* Device allocator.  NULL alloc = hipMalloc/hipFree.  alloc returns NULL on
-   * failure; free must accept any pointer alloc returned. */
+   * failure; free must accept any pointer alloc returned.  A custom allocator
+   * must be stream-ordered on `stream`: a block given to free may be handed
+   * out again only to work enqueued on that stream after the free (torch's
+   * caching allocator behaves so), because the library frees buffers that
+   * queued kernels still use without waiting for them.  With hipFree the
+   * library waits for the stream before a buffer is freed. */
   void *(*alloc)(size_t bytes, void *user);
   void (*free)(void *ptr, void *user);
   void *alloc_user;
@@ -178,9 +183,23 @@ int trg_step_log(trg_ctx *ctx, trg_step_rec *out, int cap, int *n);
 /* Free-energy accumulator sum_{k<=n} 2^{-k} ln c_k (synchronises). */
 int trg_accumulator(trg_ctx *ctx, double *acc);
 
-/* Device bytes a context keeps resident for (d, dcut, precision, method,
- * impure) at steady state, plus the join workspace it would use by default. */
+/* Device bytes of a context at steady state for (d, dcut, precision, method,
+ * impure): trg_resident_bytes = its tensors (kept for the whole run),
+ * trg_workspace_bytes = the join workspace of the default plan (whole Bt,
+ * slices of about 32768 GEMM rows of A), trg_footprint_bytes = the sum.
+ * Pure functions of their arguments (no device access). */
 size_t trg_footprint_bytes(int d, int dcut, int precision, int method, unsigned impure);
+size_t trg_resident_bytes(int d, int dcut, int precision, int method, unsigned impure);
+size_t trg_workspace_bytes(int d, int dcut, int precision, int method, unsigned impure);
+
+/* Let ctx use donor's workspace (its own is released).  Both contexts must
+ * use the same stream, and both hipMalloc or both a custom allocator; their
+ * calls must not overlap: steps of contexts that share a workspace are
+ * serialised on that stream (one serving lane).  The workspace lives until
+ * its last user is freed and is released through the free callback of the
+ * context that created it, which must stay callable until then.
+ * Errors: TRG_EINVAL for NULL or mismatched contexts. */
+int trg_share_workspace(trg_ctx *ctx, trg_ctx *donor);
 
 /* Wait for all work of the context's stream. */
 int trg_sync(trg_ctx *ctx);

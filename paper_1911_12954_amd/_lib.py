@@ -71,6 +71,9 @@ SIGNATURES = {
     "trg_step_log": (C.c_int, [C.c_void_p, C.POINTER(TrgStepRec), C.c_int, C.POINTER(C.c_int)]),
     "trg_accumulator": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "trg_footprint_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint]),
+    "trg_resident_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint]),
+    "trg_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint]),
+    "trg_share_workspace": (C.c_int, [C.c_void_p, C.c_void_p]),
     "trg_sync": (C.c_int, [C.c_void_p]),
     "trg_free": (None, [C.c_void_p]),
     "trg_last_error": (C.c_char_p, [C.c_void_p]),

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -70,6 +71,26 @@ struct Buffer {
 using trg::Buffer;
 using trg::Error;
 
+// Named scratch buffers of one or more contexts; freed with the allocator of
+// the context that created the pool when the last user lets go of it.
+struct WorkspacePool {
+  std::map<std::string, Buffer> bufs;
+  void (*free_fn)(void *, void *) = nullptr;
+  void *user = nullptr;
+  bool use_alloc = false;
+  explicit WorkspacePool(const trg_config &cfg) : free_fn(cfg.free), user(cfg.alloc_user), use_alloc(cfg.alloc != nullptr) {}
+  ~WorkspacePool() {
+    for (auto &kv : bufs) {
+      if (!kv.second.ptr) continue;
+      if (use_alloc) {
+        if (free_fn) free_fn(kv.second.ptr, user);
+      } else {
+        (void)hipFree(kv.second.ptr);
+      }
+    }
+  }
+};
+
 struct trg_ctx {
   int d = 0;
   int dims[4] = {0, 0, 0, 0};
@@ -90,7 +111,9 @@ struct trg_ctx {
   std::vector<trg_step_rec> host_rec;  // host-known parts
   Buffer U[4], spec[4];
   int Un[4] = {0, 0, 0, 0}, Uk[4] = {0, 0, 0, 0};
-  std::map<std::string, Buffer> ws;
+  // join/scratch workspace; contexts stepped one after another on the same
+  // stream may share one (trg_share_workspace)
+  std::shared_ptr<WorkspacePool> pool;
   int force_side = -1;
 
   // ATRG: T = sum_l G[b, l] H[l, f] (G: n x r, H: r x n), last swap spectrum
@@ -129,8 +152,9 @@ struct trg_ctx {
   void ensure(Buffer &b, size_t bytes) {
     if (b.cap >= bytes && b.ptr) return;
     if (b.ptr) {
-      // the stream may still read the old buffer
-      TRG_HIP_CHECK(hipStreamSynchronize(st));
+      // the stream may still read the old buffer: hipFree needs the wait, a
+      // custom allocator is stream-ordered on st by contract
+      if (!cfg.alloc) TRG_HIP_CHECK(hipStreamSynchronize(st));
       release(b.ptr);
       b.ptr = nullptr;
       b.cap = 0;
@@ -140,13 +164,15 @@ struct trg_ctx {
   }
   template <typename Tp>
   Tp *wsp(const std::string &name, size_t bytes) {
-    Buffer &b = ws[name];
+    if (!pool) pool = std::make_shared<WorkspacePool>(cfg);
+    Buffer &b = pool->bufs[name];
     ensure(b, bytes);
     return static_cast<Tp *>(b.ptr);
   }
   size_t ws_held() const {
     size_t s = 0;
-    for (const auto &kv : ws) s += kv.second.cap;
+    if (pool)
+      for (const auto &kv : pool->bufs) s += kv.second.cap;
     return s;
   }
   double *scal() { return static_cast<double *>(dev_scalars.ptr); }

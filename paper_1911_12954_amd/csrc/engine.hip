@@ -83,7 +83,7 @@ void ensure_records(trg_ctx &c, int need) {
   fill_zero(p, size_t(cap) * REC_BYTES, c.st);
   if (c.dev_rec.ptr) {
     TRG_HIP_CHECK(hipMemcpyAsync(p, c.dev_rec.ptr, size_t(c.rec_cap) * REC_BYTES, hipMemcpyDeviceToDevice, c.st));
-    TRG_HIP_CHECK(hipStreamSynchronize(c.st));
+    if (!c.cfg.alloc) TRG_HIP_CHECK(hipStreamSynchronize(c.st));
     c.release(c.dev_rec.ptr);
   }
   c.dev_rec.ptr = p;
@@ -136,6 +136,9 @@ void environment(trg_ctx &c, const double *T, int l1, int l2, double *out, const
 }
 
 // ------------------------------------------------------------ operands ---
+// target GEMM rows of one join launch (x0 slices of A)
+constexpr int64_t JOIN_ROWS = 32768;
+
 struct StepShape {
   int mu;
   std::vector<int> others, pre, post;
@@ -414,11 +417,14 @@ void contract_step(trg_ctx &c, StepPrep &prep, int mu) {
     TRG_HIP_CHECK(hipMemGetInfo(&fr, &tot));
     budget = 0.85 * double(fr + c.ws_held()) - 2.0e9;
   }
+  // natural plan: Bt whole, A in slices of about JOIN_ROWS GEMM rows; the
+  // memory budget can only shrink it
   int c2 = dmu;
   while (c2 > 1 && bytes_for(1, c2) > budget) --c2;
   if (bytes_for(1, c2) > budget) throw Error(TRG_ENOMEM, "join workspace does not fit the memory budget");
+  const int c0_max = int(std::max<int64_t>(1, std::min<int64_t>(dmu, JOIN_ROWS / sh.Mr)));
   int c0 = 1;
-  while (c0 < dmu && bytes_for(c0 + 1, c2) <= budget && double(c0 + 1) * sh.Mr * c2 * sh.Mr * esE < 16.0e9) ++c0;
+  while (c0 < c0_max && bytes_for(c0 + 1, c2) <= budget) ++c0;
 
   const int64_t cap_tensor = [&] {
     int64_t n = 1;
@@ -899,29 +905,56 @@ int trg_step_log(trg_ctx *ctx, trg_step_rec *out, int cap, int *n) {
   });
 }
 
-size_t trg_footprint_bytes(int d, int dcut, int precision, int method, unsigned impure) {
+size_t trg_resident_bytes(int d, int dcut, int precision, int method, unsigned impure) {
+  (void)precision;
   if (d < 2 || d > 4 || dcut < 1) return 0;
-  if (method == TRG_ATRG) {
-    // pieces (2 D^{d+1}) resident; workspace dominated by the D^{2d-1}
-    // intermediate of the contraction (GEMM output and its unpacked copy)
-    const double D = dcut;
-    const double pieces = 2.0 * std::pow(D, d + 1) * 8.0;
-    const double inter = 2.0 * std::pow(D, 2 * d - 1) * 8.0;
-    const double rs = 8.0 * std::pow(D, d) * 5.0 * D * 8.0;  // RSVD blocks (r = 5 Dcut)
-    return size_t(pieces + inter + rs);
-  }
-  // resident tensors: T and its next-step buffer, per impurity the same
-  double D = dcut;
-  double t = std::pow(D, 2 * d);
+  const double D = dcut;
+  if (method == TRG_ATRG) return size_t(2.0 * 2.0 * std::pow(D, d + 1) * 8.0);  // G, H and their next copies
   const int nt = 1 + ((impure & 1u) ? 1 : 0) + ((impure & 2u) ? 1 : 0);
-  double resident = 2.0 * nt * t * 8.0;
-  // default join workspace at steady state with x0 slices of one value and whole Bt
+  return size_t(2.0 * nt * std::pow(D, 2 * d) * 8.0);  // each tensor and its next-step buffer
+}
+
+size_t trg_workspace_bytes(int d, int dcut, int precision, int method, unsigned impure) {
+  if (d < 2 || d > 4 || dcut < 1) return 0;
+  const double D = dcut;
+  if (method == TRG_ATRG) {
+    // the D^{2d-1} contraction intermediate (GEMM output and its unpacked
+    // copy) plus the randomized-SVD blocks (r = 5 Dcut columns)
+    return size_t(2.0 * std::pow(D, 2 * d - 1) * 8.0 + 8.0 * std::pow(D, d) * 5.0 * D * 8.0);
+  }
+  // steady-state join of the natural plan (every leg at Dcut)
+  const int nt = 1 + ((impure & 1u) ? 1 : 0) + ((impure & 2u) ? 1 : 0);
   const int pre = d / 2, post = d - 1 - pre;
   const double Mr = std::pow(D, 2 * post + pre);
   const double K = std::pow(D, 1 + 2 * pre);
+  const double Kpad = double(round_up(size_t(K), precision == TRG_FP64 ? 16 : (precision == TRG_FP32 ? 32 : 64)));
   const double esz = precision == TRG_FP64 ? 8.0 : 4.0;
-  double ws = nt * (Mr + D * Mr) * K * esz + Mr * D * Mr * esz + D * t * 8.0;
-  return size_t(resident + ws);
+  const double c0 = std::max(1.0, std::min(D, std::floor(double(JOIN_ROWS) / Mr)));
+  const double Mp = double(round_up(size_t(c0 * Mr), 128)), Np = double(round_up(size_t(D * Mr), 128));
+  double b = nt * (Mp + Np) * Kpad * esz;                 // operands
+  b += D * std::pow(D, 2 * d - 1) * D * 8.0;              // operand build temporary
+  b += Mp * Np * esz;                                     // join result
+  if (post) b += c0 * D * std::pow(D, 2 * post + 2 * pre + post) * 8.0;  // post-join temporary
+  b += 12.0 * std::pow(D, 2 * d) * 8.0 / 1.0;             // Gram packing, partials, eigensystems (bound)
+  return size_t(b);
+}
+
+size_t trg_footprint_bytes(int d, int dcut, int precision, int method, unsigned impure) {
+  return trg_resident_bytes(d, dcut, precision, method, impure) +
+         trg_workspace_bytes(d, dcut, precision, method, impure);
+}
+
+int trg_share_workspace(trg_ctx *ctx, trg_ctx *donor) {
+  if (!ctx || !donor) return fail(ctx, TRG_EINVAL, "NULL context");
+  if (ctx->st != donor->st) return fail(ctx, TRG_EINVAL, "contexts sharing a workspace must share the stream");
+  if ((ctx->cfg.alloc != nullptr) != (donor->cfg.alloc != nullptr))
+    return fail(ctx, TRG_EINVAL, "contexts sharing a workspace must both use hipMalloc or both a custom allocator");
+  return guarded(ctx, [&]() -> int {
+    if (!donor->pool) donor->pool = std::make_shared<WorkspacePool>(donor->cfg);
+    TRG_HIP_CHECK(hipStreamSynchronize(ctx->st));
+    ctx->pool = donor->pool;
+    return TRG_OK;
+  });
 }
 
 int trg_sync(trg_ctx *ctx) {
@@ -959,7 +992,7 @@ void trg_free(trg_ctx *ctx) {
     rel(ctx->U[a]);
     rel(ctx->spec[a]);
   }
-  for (auto &kv : ctx->ws) rel(kv.second);
+  ctx->pool.reset();
   delete ctx;
 }
 

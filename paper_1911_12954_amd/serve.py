@@ -2,10 +2,18 @@
 
 Requests (beta, h, Dcut, L, method) arrive over time.  The server
 
-* admits a request while the summed device footprint of the admitted runs
-  (trg_footprint_bytes: resident tensors plus join workspace) stays within
-  the HBM budget; waiting requests are admitted as soon as finished runs
-  free their memory;
+* admits a request while the device memory of the admitted runs stays
+  within the HBM budget: each run's resident tensors (trg_resident_bytes)
+  plus one join workspace per lane (trg_workspace_bytes), which the runs of
+  a lane share (trg_share_workspace) because a lane steps them one after
+  another on its stream; waiting requests are admitted as soon as finished
+  runs free their memory;
+* bounds the work of one lane round: a lane holds at most
+  round_flops / (join flop of one step) runs (at least one), so a round of
+  a large bond dimension stays short and the runs admitted first finish
+  first instead of all sharing the device until the end of the stream;
+  requests wait in arrival order, and one whose lane is full does not hold
+  back requests of other lanes;
 * keeps each run's tensors resident until it finishes;
 * runs one lane (HIP stream) per bond dimension, so lanes of different Dcut
   overlap on the device; inside a lane, runs whose leg dims and next axis
@@ -49,17 +57,30 @@ class TrgBackend:
         self.precision = precision
         self.d = d
 
-    def footprint(self, req) -> int:
-        from .trg import trg_footprint_bytes
-        return trg_footprint_bytes(self.d, req["dcut"], self.precision, "hotrg")
+    def resident(self, req) -> int:
+        from .trg import trg_resident_bytes
+        return trg_resident_bytes(self.d, req["dcut"], self.precision, "hotrg")
+
+    def workspace(self, dcut) -> int:
+        from .trg import trg_workspace_bytes
+        return trg_workspace_bytes(self.d, dcut, self.precision, "hotrg")
+
+    def step_flops(self, dcut) -> float:
+        """Join flop of one steady-state step: 2 Dcut^(4d-1)."""
+        return 2.0 * float(dcut) ** (4 * self.d - 1)
 
     def new_lane(self, dcut):
         return self.torch.cuda.Stream()
 
-    def create(self, req, stream):
-        from .trg import trg_init_ising
-        return trg_init_ising(req["beta"], req["h"], self.d, dcut=req["dcut"], precision=self.precision,
-                              stream=stream)
+    def create(self, req, stream, donor=None):
+        """A run on the lane's stream; its join plan is sized to the lane's
+        workspace, which it shares with `donor` (a live run of the lane)."""
+        from .trg import trg_init_ising, trg_share_workspace
+        h = trg_init_ising(req["beta"], req["h"], self.d, dcut=req["dcut"], precision=self.precision,
+                           stream=stream, workspace_bytes=self.workspace(req["dcut"]))
+        if donor is not None:
+            trg_share_workspace(h, donor)
+        return h
 
     def dims(self, h):
         return h.dims()[0]
@@ -87,11 +108,14 @@ class TrgBackend:
 
 
 class Server:
-    def __init__(self, backend, hbm_budget: int, d: int = 4, max_batch: int = 64):
+    def __init__(self, backend, hbm_budget: int, d: int = 4, max_batch: int = 64,
+                 round_flops: float = 4e13, max_active: int = 256):
         self.be = backend
         self.budget = int(hbm_budget)
         self.d = d
         self.max_batch = max_batch
+        self.round_flops = float(round_flops)
+        self.max_active = int(max_active)
         self.lanes = {}
         self.used = 0
         self.peak_used = 0
@@ -104,17 +128,29 @@ class Server:
             self.lanes[dcut] = Lane(dcut, self.be.new_lane(dcut))
         return self.lanes[dcut]
 
+    def lane_cap(self, dcut) -> int:
+        """Runs a lane holds at once."""
+        return max(1, min(self.max_active, int(self.round_flops // self.be.step_flops(dcut))))
+
     def _admit(self, req, now):
-        fp = self.be.footprint(req)
-        if fp > self.budget:
-            raise ValueError(f"request {req['id']} needs {fp} bytes, more than the whole budget")
-        if self.used + fp > self.budget:
+        """Admit `req` if its lane has room and the memory fits.  Returns
+        True (admitted), "lane" (its lane is full) or False (no memory)."""
+        res = self.be.resident(req)
+        ws = self.be.workspace(req["dcut"])
+        if res + ws > self.budget:
+            raise ValueError(f"request {req['id']} needs {res + ws} bytes, more than the whole budget")
+        lane = self.lanes.get(req["dcut"])
+        if lane is not None and len(lane.runs) >= self.lane_cap(req["dcut"]):
+            return "lane"
+        need = res + (0 if lane is not None and lane.runs else ws)
+        if self.used + need > self.budget:
             return False
         lane = self._lane(req["dcut"])
-        h = self.be.create(req, lane.stream)
+        donor = lane.runs[0].handle if lane.runs else None
+        h = self.be.create(req, lane.stream, donor)
         m = req["L"].bit_length() - 1
         lane.runs.append(Run(req, h, self.d * m, 0, now))
-        self.used += fp
+        self.used += need
         self.peak_used = max(self.peak_used, self.used)
         return True
 
@@ -124,12 +160,13 @@ class Server:
         if not self.be.ready(lane.event):
             return False
         lane.event = None
+        had_runs = bool(lane.runs)
         still = []
         for run in lane.runs:
             if run.done >= run.total:
                 lnz = self.be.result(run.handle)
                 self.be.close(run.handle)
-                self.used -= self.be.footprint(run.req)
+                self.used -= self.be.resident(run.req)
                 t_done = time.perf_counter() - t0
                 self.results.append({"id": run.req["id"], "lnz": lnz, "arrival": run.req["arrival"],
                                      "admitted": run.t_admit, "done": t_done,
@@ -137,6 +174,8 @@ class Server:
                                      "L": run.req["L"], "beta": run.req["beta"], "h": run.req["h"]})
             else:
                 still.append(run)
+        if had_runs and not still:
+            self.used -= self.be.workspace(lane.dcut)   # the last user freed it
         lane.runs = still
         if not still:
             return True
@@ -171,9 +210,17 @@ class Server:
             while i < len(pending) and pending[i]["arrival"] <= now:
                 waiting.append(pending[i])
                 i += 1
-            # first come, first served while memory allows
-            while waiting and self._admit(waiting[0], now):
-                waiting.pop(0)
+            # first come, first served while memory allows; a request whose
+            # lane is full is passed over
+            keep = []
+            for j, req in enumerate(waiting):
+                got = self._admit(req, now)
+                if got is False:
+                    keep += waiting[j:]
+                    break
+                if got == "lane":
+                    keep.append(req)
+            waiting = keep
             progressed = False
             for lane in list(self.lanes.values()):
                 progressed |= self._advance(lane, now, t0)
@@ -207,4 +254,7 @@ class Server:
         for lane in self.lanes.values():
             for run in lane.runs:
                 self.be.close(run.handle)
+                self.used -= self.be.resident(run.req)
+            if lane.runs:
+                self.used -= self.be.workspace(lane.dcut)
             lane.runs = []

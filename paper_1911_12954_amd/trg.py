@@ -289,6 +289,23 @@ def trg_footprint_bytes(d, dcut, precision="fp64", method="hotrg", impure=()) ->
     return int(_lib().trg_footprint_bytes(d, dcut, PRECISIONS[precision], METHODS[method], bits))
 
 
+def trg_resident_bytes(d, dcut, precision="fp64", method="hotrg", impure=()) -> int:
+    bits = sum({"E": L.TRG_IMPURE_E, "M": L.TRG_IMPURE_M}[x] for x in impure)
+    return int(_lib().trg_resident_bytes(d, dcut, PRECISIONS[precision], METHODS[method], bits))
+
+
+def trg_workspace_bytes(d, dcut, precision="fp64", method="hotrg", impure=()) -> int:
+    bits = sum({"E": L.TRG_IMPURE_E, "M": L.TRG_IMPURE_M}[x] for x in impure)
+    return int(_lib().trg_workspace_bytes(d, dcut, PRECISIONS[precision], METHODS[method], bits))
+
+
+def trg_share_workspace(ctx: Context, donor: Context):
+    """ctx uses donor's workspace from now on (same stream required)."""
+    _err(_lib().trg_share_workspace(ctx.handle, donor.handle), ctx.handle)
+    # the shared workspace is released through donor's free callback
+    ctx._keep = list(ctx._keep) + list(donor._keep)
+
+
 def trg_gemm(precision, A_ptr, Bt_ptr, C_ptr, M, N, K, lda, ldb, ldc, accumulate=False, stream=None):
     _err(_lib().trg_gemm(PRECISIONS[precision] if isinstance(precision, str) else precision,
                          A_ptr, Bt_ptr, C_ptr, M, N, K, lda, ldb, ldc, 1 if accumulate else 0, stream))

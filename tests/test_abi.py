@@ -65,3 +65,12 @@ def test_gemm_tile_and_footprint(lib):
     # resident part alone: 2 buffers x D^8 doubles
     assert f10 > 2 * 10 ** 8 * 8
     assert lib.trg_footprint_bytes(5, 8, 0, 0, 0) == 0
+    for args in ((4, 10, L.TRG_FP64, L.TRG_HOTRG, 0), (4, 6, L.TRG_FP32, L.TRG_HOTRG, 3),
+                 (3, 12, L.TRG_BF16X3, L.TRG_HOTRG, 1), (4, 24, L.TRG_FP64, L.TRG_ATRG, 0)):
+        res, ws = lib.trg_resident_bytes(*args), lib.trg_workspace_bytes(*args)
+        assert res > 0 and ws > 0 and lib.trg_footprint_bytes(*args) == res + ws
+    # resident: T, S_E, S_M and their next-step buffers, D^8 doubles each
+    assert lib.trg_resident_bytes(4, 6, L.TRG_FP32, L.TRG_HOTRG, 3) == 6 * 6 ** 8 * 8
+    # the workspace at Dcut 10 holds at least the whole Bt operand and the
+    # D^9 operand-build temporary
+    assert lib.trg_workspace_bytes(4, 10, L.TRG_FP64, L.TRG_HOTRG, 0) > 10 ** 9 * 8 + 10 ** 5 * 10 ** 5 * 8

@@ -34,3 +34,44 @@ def test_results_in_the_mix_equal_results_alone(precision):
     if precision == "fp64":
         r = hotrg.run(0.1497, 1e-5, 4, 4, 16, impure=False)
         assert abs(mix[1] - r.ln_z_per_site) <= 1e-10 * abs(r.ln_z_per_site)
+
+
+def test_shared_workspace_gives_the_same_bits():
+    """Two runs stepped in turn on one stream with one shared workspace give
+    the bits of the same runs with their own workspaces, also after the
+    workspace's creator is freed."""
+    need_gpu()
+    import torch
+    from paper_1911_12954_amd import trg
+    announce("shared workspace")
+    st = torch.cuda.Stream()
+    betas, steps = (0.1490, 0.1500), 13
+
+    def alone(beta):
+        c = trg.trg_init_ising(beta, 0.0, 4, dcut=5, precision="fp64", stream=st)
+        for n in range(steps):
+            c.hotrg_step(n % 4, 5)
+        out = c.free_energy()
+        c.close()
+        return out
+
+    own = [alone(b) for b in betas]
+    a, b = (trg.trg_init_ising(x, 0.0, 4, dcut=5, precision="fp64", stream=st) for x in betas)
+    trg.trg_share_workspace(b, a)
+    for n in range(steps - 1):
+        a.hotrg_step(n % 4, 5)
+        b.hotrg_step(n % 4, 5)
+    a.hotrg_step((steps - 1) % 4, 5)
+    fa = a.free_energy()
+    a.close()                     # b keeps the shared workspace alive
+    b.hotrg_step((steps - 1) % 4, 5)
+    fb = b.free_energy()
+    b.close()
+    assert [fa, fb] == own
+    # contexts on different streams cannot share
+    e = trg.trg_init_ising(0.15, 0.0, 4, dcut=5, precision="fp64", stream=st)
+    other = trg.trg_init_ising(0.15, 0.0, 4, dcut=5, precision="fp64", stream=torch.cuda.Stream())
+    with pytest.raises(trg.TrgError):
+        trg.trg_share_workspace(e, other)
+    other.close()
+    e.close()

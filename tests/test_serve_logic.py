@@ -15,24 +15,37 @@ class FakeHandle:
 
 
 class FakeBackend:
-    """Footprint grows like D^8; a lane's step completes after `lag` polls."""
+    """Resident bytes grow like D^8, a lane's workspace like D^9; a lane's
+    step completes after `lag` polls."""
 
     def __init__(self, lag=2):
         self.lag = lag
         self.live = 0
         self.max_live = 0
         self.calls = []
+        self.workspaces = {}     # id of the first run of a lane's workspace -> users
+        self.max_workspaces = 0
 
-    def footprint(self, req):
+    def resident(self, req):
         return 10 * req["dcut"] ** 8
+
+    def workspace(self, dcut):
+        return dcut ** 9
+
+    def step_flops(self, dcut):
+        return 2.0 * dcut ** 15
 
     def new_lane(self, dcut):
         return {"dcut": dcut}
 
-    def create(self, req, stream):
+    def create(self, req, stream, donor=None):
         self.live += 1
         self.max_live = max(self.max_live, self.live)
-        return FakeHandle(req)
+        h = FakeHandle(req)
+        h.ws = donor.ws if donor is not None else id(h)
+        self.workspaces[h.ws] = self.workspaces.get(h.ws, 0) + 1
+        self.max_workspaces = max(self.max_workspaces, len(self.workspaces))
+        return h
 
     def dims(self, h):
         return tuple(h.dims)
@@ -59,17 +72,23 @@ class FakeBackend:
 
     def close(self, h):
         self.live -= 1
+        self.workspaces[h.ws] -= 1
+        if self.workspaces[h.ws] == 0:
+            del self.workspaces[h.ws]
+
 
 
 def test_every_request_completes_and_budget_is_respected():
     reqs = serving_requests(40, rate=2000.0, seed=1, dcuts=(4, 6, 8), kmin=2, kmax=4)
     be = FakeBackend()
-    budget = 3 * 10 * 8 ** 8
+    budget = 3 * 10 * 8 ** 8 + 8 ** 9
     srv = Server(be, budget)
     out = srv.serve(reqs, idle_sleep=0)
     assert out["completed"] == 40 and out["censored_active"] == 0
     assert srv.peak_used <= budget
-    assert be.live == 0
+    assert be.live == 0 and not be.workspaces and srv.used == 0
+    # at most one workspace per lane (Dcut) at any time
+    assert be.max_workspaces <= 3
     for r in srv.results:
         assert r["latency"] >= 0 and r["admitted"] >= r["arrival"] and r["done"] >= r["admitted"]
         # each run took exactly d * log2 L steps
@@ -102,7 +121,7 @@ def test_continuous_admission_while_others_run():
 def test_memory_bound_admission_waits_for_frees():
     reqs = [{"id": i, "arrival": 0.0, "beta": 0.149, "h": 0.0, "dcut": 8, "L": 4, "method": "hotrg"} for i in range(3)]
     be = FakeBackend(lag=1)
-    srv = Server(be, 10 * 8 ** 8)   # room for one run at a time
+    srv = Server(be, 10 * 8 ** 8 + 8 ** 9)   # room for one run at a time
     srv.serve(reqs, idle_sleep=0)
     assert be.max_live == 1 and len(srv.results) == 3
     done = sorted(srv.results, key=lambda r: r["id"])
@@ -124,3 +143,33 @@ def test_window_censors_unfinished_runs():
     assert out["completed"] == 0 and out["censored_active"] == 1
     srv.close()
     assert be.live == 0
+
+
+def test_runs_of_a_lane_share_one_workspace():
+    reqs = [{"id": i, "arrival": 0.0, "beta": 0.149, "h": 0.0, "dcut": 6, "L": 16, "method": "hotrg"} for i in range(4)]
+    be = FakeBackend(lag=1)
+    budget = 4 * 10 * 6 ** 8 + 6 ** 9      # four residents, one workspace
+    srv = Server(be, budget)
+    srv.serve(reqs, idle_sleep=0)
+    assert be.max_live == 4 and be.max_workspaces == 1
+    assert srv.peak_used == budget and srv.used == 0
+
+
+def test_lane_cap_bounds_a_round_and_keeps_arrival_order():
+    """Dcut 8 (7e13 flop per step) gets one run at a time under a 4e13 round;
+    Dcut 4 requests behind them are not held back."""
+    reqs = [{"id": i, "arrival": 0.0, "beta": 0.149, "h": 0.0, "dcut": 8, "L": 4, "method": "hotrg"} for i in range(3)]
+    reqs += [{"id": 3 + i, "arrival": 0.0, "beta": 0.149, "h": 0.0, "dcut": 4, "L": 4, "method": "hotrg"}
+             for i in range(3)]
+    be = FakeBackend(lag=1)
+    srv = Server(be, 10 ** 12)
+    assert srv.lane_cap(8) == 1 and srv.lane_cap(4) == 256
+    srv.serve(reqs, idle_sleep=0)
+    res = {r["id"]: r for r in srv.results}
+    assert len(res) == 6
+    # the Dcut 8 runs ran one after another, in arrival order
+    assert res[0]["done"] <= res[1]["admitted"] + 1e-9 and res[1]["done"] <= res[2]["admitted"] + 1e-9
+    # the Dcut 4 runs were admitted at once, beside the first Dcut 8 run
+    assert all(res[3 + i]["admitted"] < res[0]["done"] for i in range(3))
+    # calls on the Dcut 8 lane step one run
+    assert all(n == 1 for n, _, dc in be.calls if dc == 8)
