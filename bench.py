@@ -55,6 +55,9 @@ def parse():
     p.add_argument("--serve-k", default="4,10", help="L = 2^k, k uniform in [kmin, kmax]")
     p.add_argument("--serve-precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
     p.add_argument("--serve-budget-gb", type=float, default=200.0)
+    p.add_argument("--copy-cal", type=float, default=0.0,
+                   help="only copy this many GiB device to device three times (calibration of the "
+                        "FETCH_SIZE / WRITE_SIZE counters)")
     p.add_argument("--accuracy", default=None,
                    help="instead of timing: run 'dcut,L,beta,h' in FP64, FP32 and BF16x3 with impure E and M "
                         "and print the relative errors of f, E, M against the FP64 path")
@@ -218,11 +221,20 @@ def cpu_baseline(dcut, blocks):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is design-only "
-                                   "(see DESIGN.md), --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the multi-GPU sharding of the "
+                                   "step is a design, not built); use --gpus 1"}))
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.copy_cal > 0:
+        n = int(a.copy_cal * 2 ** 30) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
+        return
     if a.accuracy:
         print(json.dumps(accuracy(a.accuracy)), flush=True)
         return
@@ -298,8 +310,8 @@ def main():
     elapsed, join_ms, launches, lnz = time_steps(a.precision, D, a.beta, a.warmup, a.steps)
     steps_per_s = a.steps / elapsed
     alg_flops_step = 2.0 * D ** 15
-    mult = 3.0 if a.precision == "bf16x3" else 1.0
-    achieved = mult * alg_flops_step * a.steps / (join_ms * 1e-3) / 1e12 if join_ms > 0 else None
+    mult = 3.0 if a.precision == "bf16x3" else 1.0   # BF16 MFMA products per multiply-add
+    achieved = alg_flops_step * a.steps / (join_ms * 1e-3) / 1e12 if join_ms > 0 else None
     peak = PEAK_TFLOPS[a.precision]
     out = {
         "metric": "4D HOTRG RG-steps/s at Dcut=10 (steady-state step, 1 GPU)",
@@ -329,14 +341,14 @@ def main():
             "join_launches": launches,
             "join_ms_per_step": join_ms / a.steps,
             "join_share_of_step": (join_ms * 1e-3) / elapsed,
-            "fp32_equivalent_tflops": (alg_flops_step * a.steps / (join_ms * 1e-3) / 1e12) if join_ms > 0 else None,
+            "mfma_issued_tflops": mult * achieved if achieved else None,
+            "mfma_issued_frac": (mult * achieved / peak) if achieved else None,
         },
     }
     others = {}
-    for prec in [x for x in a.compare.split(",") if x and x != a.precision]:
+    for prec in [x for x in a.compare.split(",") if x in PEAK_TFLOPS and x != a.precision]:
         e, jm, nl, _ = time_steps(prec, D, a.beta, 0, 1)
-        m2 = 3.0 if prec == "bf16x3" else 1.0
-        ach = m2 * alg_flops_step / (jm * 1e-3) / 1e12
+        ach = alg_flops_step / (jm * 1e-3) / 1e12
         others[prec] = {"rg_steps_per_s": 1.0 / e, "join_tflops": ach, "frac_of_peak": ach / PEAK_TFLOPS[prec]}
     if others:
         out["other_precisions"] = others

@@ -927,10 +927,11 @@ size_t trg_workspace_bytes(int d, int dcut, int precision, int method, unsigned 
   const int pre = d / 2, post = d - 1 - pre;
   const double Mr = std::pow(D, 2 * post + pre);
   const double K = std::pow(D, 1 + 2 * pre);
-  const double Kpad = double(round_up(size_t(K), precision == TRG_FP64 ? 16 : (precision == TRG_FP32 ? 32 : 64)));
+  const GemmTile tile = gemm_tile(precision);
+  const double Kpad = double(round_up(size_t(K), tile.k));
   const double esz = precision == TRG_FP64 ? 8.0 : 4.0;
   const double c0 = std::max(1.0, std::min(D, std::floor(double(JOIN_ROWS) / Mr)));
-  const double Mp = double(round_up(size_t(c0 * Mr), 128)), Np = double(round_up(size_t(D * Mr), 128));
+  const double Mp = double(round_up(size_t(c0 * Mr), tile.m)), Np = double(round_up(size_t(D * Mr), tile.n));
   double b = nt * (Mp + Np) * Kpad * esz;                 // operands
   b += D * std::pow(D, 2 * d - 1) * D * 8.0;              // operand build temporary
   b += Mp * Np * esz;                                     // join result

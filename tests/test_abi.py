@@ -55,9 +55,9 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
 
 def test_gemm_tile_and_footprint(lib):
     m, n, k = C.c_int(), C.c_int(), C.c_int()
-    for prec, kk in ((L.TRG_FP64, 16), (L.TRG_FP32, 32), (L.TRG_BF16X3, 64)):
+    for prec, tile in ((L.TRG_FP64, (128, 128, 16)), (L.TRG_FP32, (128, 128, 32)), (L.TRG_BF16X3, (256, 256, 32))):
         assert lib.trg_gemm_tile(prec, C.byref(m), C.byref(n), C.byref(k)) == 0
-        assert (m.value, n.value, k.value) == (128, 128, kk)
+        assert (m.value, n.value, k.value) == tile
     f8 = lib.trg_footprint_bytes(4, 8, L.TRG_FP64, L.TRG_HOTRG, 0)
     f10 = lib.trg_footprint_bytes(4, 10, L.TRG_FP64, L.TRG_HOTRG, 0)
     f10m = lib.trg_footprint_bytes(4, 10, L.TRG_FP32, L.TRG_HOTRG, 0)

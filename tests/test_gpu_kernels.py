@@ -53,11 +53,14 @@ def test_gemm_fp32(M, N, K):
     assert np.max(np.abs(dC.cpu().numpy() - ref) / scale) < 4 * 2.0 ** -24 * np.sqrt(K) + 1e-7
 
 
-@pytest.mark.parametrize("M,N,K", [(128, 128, 64), (256, 384, 1088), (512, 256, 4096)])
-def test_gemm_bf16x3(M, N, K):
+@pytest.mark.parametrize("M,N,K,accumulate", [(256, 256, 32, False), (512, 768, 1088, False),
+                                              (768, 256, 4096, False), (512, 512, 1056, True)])
+def test_gemm_bf16x3(M, N, K, accumulate):
     torch = need_gpu()
-    from paper_1911_12954_amd import trg_gemm
-    announce("gemm bf16x3", M, N, K)
+    from paper_1911_12954_amd import trg_gemm, trg_gemm_tile
+    announce("gemm bf16x3", M, N, K, accumulate)
+    tm, tn, tk = trg_gemm_tile("bf16x3")
+    assert M % tm == 0 and N % tn == 0 and K % tk == 0
     A = random_matrix(M, K, 6)
     B = random_matrix(N, K, 7)
 
@@ -71,17 +74,21 @@ def test_gemm_bf16x3(M, N, K):
     bh, bl = split(B)
     dA = torch.stack([ah, al]).cuda().contiguous()
     dB = torch.stack([bh, bl]).cuda().contiguous()
-    dC = torch.empty((M, N), dtype=torch.float32, device="cuda")
-    trg_gemm("bf16x3", dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), M, N, K, K, K, N, False,
+    C0 = random_matrix(M, N, 8).astype(np.float32)
+    dC = torch.from_numpy(C0).cuda()
+    trg_gemm("bf16x3", dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), M, N, K, K, K, N, accumulate,
              torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     f = lambda t: t.double().numpy()
     ref = f(ah) @ f(bh).T + f(ah) @ f(bl).T + f(al) @ f(bh).T
     scale = np.abs(A) @ np.abs(B).T
+    exact = A @ B.T
+    if accumulate:
+        c0 = C0.astype(np.float64)
+        ref, exact, scale = ref + c0, exact + c0, scale + np.abs(c0)
     err = np.max(np.abs(dC.cpu().numpy() - ref) / scale)
     assert err < 4 * 2.0 ** -24 * np.sqrt(K) + 1e-7
     # and the split product is within ~2^-16 of the exact one
-    exact = A @ B.T
     assert np.max(np.abs(dC.cpu().numpy() - exact) / scale) < 2.0 ** -14
 
 
