@@ -3,6 +3,7 @@
 // padding, Frobenius normalisation, periodic traces and the initial Ising
 // tensors.
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "internal.h"
@@ -11,15 +12,38 @@ namespace trg {
 namespace {
 
 // ------------------------------------------------------------- tensor map ---
+// One thread per index of the thread dims; it keeps the NI outputs that
+// differ only in the inner dim (a dim the input does not have, only the
+// matrix: a leg that the contraction produces) in registers, so every input
+// element it sums is loaded once for all of them.
+constexpr int MAP_MAXI = 16;
 struct MapParams {
   int ndims, nsum;
   FastDiv div[MAP_MAXD];
   int64_t so[MAP_MAXD], si[MAP_MAXD], su[MAP_MAXD];
   int32_t ssize[2];
   int64_t ssi[2], ssu[2];
+  int32_t ni;           // inner dim size (1 = none)
+  int64_t iso, isu;     // its output and matrix strides
   uint32_t count;
   int64_t lo_plane;
 };
+
+template <int OUT>
+__device__ inline void map_store(void *out, int64_t o, int64_t lo_plane, double v) {
+  if constexpr (OUT == OUT_F64) {
+    static_cast<double *>(out)[o] = v;
+  } else if constexpr (OUT == OUT_F32) {
+    static_cast<float *>(out)[o] = float(v);
+  } else {
+    // v = hi + lo with hi = bf16(fl32(v)), lo = bf16(fl32(v) - hi)
+    const float a = float(v);
+    const uint16_t hi = f32_to_bf16_rne(a);
+    const uint16_t lo = f32_to_bf16_rne(a - bf16_to_f32(hi));
+    static_cast<uint16_t *>(out)[o] = hi;
+    static_cast<uint16_t *>(out)[o + lo_plane] = lo;
+  }
+}
 
 template <typename InT, int OUT>
 __global__ void __launch_bounds__(256)
@@ -40,6 +64,39 @@ map_kernel(const InT *__restrict__ in, const double *__restrict__ U, void *__res
       ou += int64_t(r) * p.su[j];
     }
   }
+  if (p.ni > 1) {
+    // inner dim in registers; the same summation order as below per output
+    double acc[MAP_MAXI];
+#pragma unroll
+    for (int k = 0; k < MAP_MAXI; ++k) acc[k] = 0.0;
+    if (p.nsum == 0) {
+      const double x = double(in[oi]);
+#pragma unroll
+      for (int k = 0; k < MAP_MAXI; ++k)
+        if (k < p.ni) acc[k] = x * U[ou + k * p.isu];
+    } else if (p.nsum == 1) {
+      for (int a = 0; a < p.ssize[0]; ++a) {
+        const double x = double(in[oi + a * p.ssi[0]]);
+        const double *pu = U + ou + a * p.ssu[0];
+#pragma unroll
+        for (int k = 0; k < MAP_MAXI; ++k)
+          if (k < p.ni) acc[k] += x * pu[k * p.isu];
+      }
+    } else {
+      for (int a = 0; a < p.ssize[0]; ++a)
+        for (int b = 0; b < p.ssize[1]; ++b) {
+          const double x = double(in[oi + a * p.ssi[0] + b * p.ssi[1]]);
+          const double *pu = U + ou + a * p.ssu[0] + b * p.ssu[1];
+#pragma unroll
+          for (int k = 0; k < MAP_MAXI; ++k)
+            if (k < p.ni) acc[k] += x * pu[k * p.isu];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < MAP_MAXI; ++k)
+      if (k < p.ni) map_store<OUT>(out, oo + k * p.iso, p.lo_plane, acc[k]);
+    return;
+  }
   double acc;
   if (p.nsum == 0) {
     acc = U ? double(in[oi]) * U[ou] : double(in[oi]);
@@ -54,18 +111,7 @@ map_kernel(const InT *__restrict__ in, const double *__restrict__ U, void *__res
       for (int b = 0; b < p.ssize[1]; ++b) acc += double(pi[b * p.ssi[1]]) * pu[b * p.ssu[1]];
     }
   }
-  if constexpr (OUT == OUT_F64) {
-    static_cast<double *>(out)[oo] = acc;
-  } else if constexpr (OUT == OUT_F32) {
-    static_cast<float *>(out)[oo] = float(acc);
-  } else {
-    // a = hi + lo with hi = bf16(fl32(a)), lo = bf16(fl32(a) - hi)
-    const float a = float(acc);
-    const uint16_t hi = f32_to_bf16_rne(a);
-    const uint16_t lo = f32_to_bf16_rne(a - bf16_to_f32(hi));
-    static_cast<uint16_t *>(out)[oo] = hi;
-    static_cast<uint16_t *>(out)[oo + p.lo_plane] = lo;
-  }
+  map_store<OUT>(out, oo, p.lo_plane, acc);
 }
 
 template <typename InT>
@@ -233,11 +279,26 @@ void tensor_map(const void *in, int in_kind, const double *U, void *out, int out
                 hipStream_t st) {
   TRG_REQUIRE(ndims >= 1 && ndims <= MAP_MAXD && nsum >= 0 && nsum <= 2, "tensor_map: bad rank");
   TRG_REQUIRE(nsum == 0 || U != nullptr, "tensor_map: summation needs a matrix");
-  int64_t total = 1;
-  for (int i = 0; i < ndims; ++i) {
+  for (int i = 0; i < ndims; ++i)
     TRG_REQUIRE(dims[i].size >= 1 && dims[i].size < (int64_t(1) << 31), "tensor_map: bad dim");
-    total *= dims[i].size;
-  }
+  // inner dim: a matrix-only dim (absent from the input) of 2..MAP_MAXI
+  // values, the one with the largest output stride
+  int in_dim = -1;
+  if (U)
+    for (int i = 0; i < ndims; ++i)
+      if (dims[i].si == 0 && dims[i].su != 0 && dims[i].size >= 2 && dims[i].size <= MAP_MAXI &&
+          (in_dim < 0 || std::llabs(dims[i].so) > std::llabs(dims[in_dim].so)))
+        in_dim = i;
+  const MapDim idim = in_dim >= 0 ? dims[in_dim] : MapDim{1, 0, 0, 0};
+  MapDim tdims[MAP_MAXD];
+  int nt = 0;
+  for (int i = 0; i < ndims; ++i)
+    if (i != in_dim) tdims[nt++] = dims[i];
+  if (nt == 0) tdims[nt++] = MapDim{1, 0, 0, 0};
+  dims = tdims;
+  ndims = nt;
+  int64_t total = 1;
+  for (int i = 0; i < ndims; ++i) total *= dims[i].size;
   // split the outermost dims into separate launches until a launch has < 2^32 - 256 elements
   int outer = 0;
   int64_t inner = total;
@@ -264,6 +325,9 @@ void tensor_map(const void *in, int in_kind, const double *U, void *out, int out
   }
   p.count = uint32_t(inner);
   p.lo_plane = lo_plane;
+  p.ni = int32_t(idim.size);
+  p.iso = idim.so;
+  p.isu = idim.su;
   const int esz_in = in_kind == IN_F64 ? 8 : 4;
   const int esz_out = out_kind == OUT_F64 ? 8 : (out_kind == OUT_F32 ? 4 : 2);
   for (int64_t o = 0; o < nouter; ++o) {
