@@ -28,6 +28,12 @@ if ROOT not in sys.path:
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per join launch of the steady Dcut 10 step (three full x0 slices
+# and one of a single x0 value per step, averaged), from rocprofv3 FETCH_SIZE
+# (x 2.0) and WRITE_SIZE (x 1.0) of the current BF16x3 join kernel; the
+# factors are what the two counters read for a device copy of 4 GiB.  Valid
+# for this kernel and workload only (null elsewhere).
+JOIN_TRAFFIC = {("bf16x3", 10): {"bytes_per_launch": 1.7127e12, "algorithmic_bytes_per_launch": 6.02e10}}
 
 
 def parse():
@@ -337,7 +343,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": (achieved / peak) if achieved else None,
-            "traffic": None,
+            "traffic": JOIN_TRAFFIC.get((a.precision, D), {}).get("bytes_per_launch"),
+            "traffic_algorithmic": JOIN_TRAFFIC.get((a.precision, D), {}).get("algorithmic_bytes_per_launch"),
             "join_launches": launches,
             "join_ms_per_step": join_ms / a.steps,
             "join_share_of_step": (join_ms * 1e-3) / elapsed,
