@@ -67,37 +67,46 @@ def parse():
     p.add_argument("--accuracy", default=None,
                    help="instead of timing: run 'dcut,L,beta,h' in FP64, FP32 and BF16x3 with impure E and M "
                         "and print the relative errors of f, E, M against the FP64 path")
+    p.add_argument("--accuracy-variants", default="fp32:0,bf16x3:0",
+                   help="precision:fp64_steps pairs compared with the FP64 path")
     return p.parse_args()
 
 
-def accuracy(spec):
-    """Errors of the mixed-precision joins against the FP64 path on one
-    whole run (4D, impure-tensor E and M)."""
+def accuracy(spec, variants):
+    """Errors of mixed-precision joins against the FP64 path on one whole
+    run (4D, impure-tensor E and M).  `variants`: "prec:n,..." with n the
+    number of leading steps joined in FP64 (fp64_steps)."""
     import torch
     from paper_1911_12954_amd import trg_init_ising
     dcut, L, beta, h = spec.split(",")
     dcut, L, beta, h = int(dcut), int(L), float(beta), float(h)
+    runs = [("fp64", 0)] + [(v.split(":")[0], int(v.split(":")[1])) for v in variants.split(",") if v]
     res = {}
-    for prec in ("fp64", "fp32", "bf16x3"):
+    for prec, n64 in runs:
+        key = prec if n64 == 0 else f"{prec}+fp64x{n64}"
         t0 = time.perf_counter()
-        ctx = trg_init_ising(beta, h, 4, dcut=dcut, precision=prec, impure=("E", "M"))
+        ctx = trg_init_ising(beta, h, 4, dcut=dcut, precision=prec, impure=("E", "M"), fp64_steps=n64)
         m = L.bit_length() - 1
         for n in range(1, 4 * m + 1):
             ctx.hotrg_step((n - 1) % 4, dcut)
             if n % 4 == 0:
                 ctx.sync()
-                progress(f"accuracy {prec}: step {n}/{4 * m} at {time.perf_counter() - t0:.1f} s")
-        res[prec] = {"f": ctx.free_energy(), "E": ctx.impure_energy(), "M": ctx.impure_magnetization(),
-                     "seconds": time.perf_counter() - t0,
-                     "degenerate_cuts": sum(sum(r.degenerate_cut) for r in ctx.step_log())}
+                progress(f"accuracy {key}: step {n}/{4 * m} at {time.perf_counter() - t0:.1f} s")
+        log = ctx.step_log()
+        res[key] = {"f": ctx.free_energy(), "E": ctx.impure_energy(), "M": ctx.impure_magnetization(),
+                    "seconds": time.perf_counter() - t0,
+                    "fp64_join_steps": sum(r.join_precision == "fp64" for r in log),
+                    "degenerate_cuts": sum(sum(r.degenerate_cut) for r in log)}
         ctx.close()
         torch.cuda.empty_cache()
-        progress(f"accuracy {prec}: {res[prec]}")
+        progress(f"accuracy {key}: {res[key]}")
     ref = res["fp64"]
     out = {"workload": f"4D Ising HOTRG Dcut={dcut} L={L} beta={beta} h={h}, impure E and M", "runs": res}
-    for prec in ("fp32", "bf16x3"):
-        out[f"rel_err_{prec}"] = {k: abs(res[prec][k] - ref[k]) / max(abs(ref[k]), 1e-300) for k in ("f", "E", "M")}
-        out[f"abs_err_{prec}"] = {k: abs(res[prec][k] - ref[k]) for k in ("f", "E", "M")}
+    for key in res:
+        if key == "fp64":
+            continue
+        out[f"rel_err_{key}"] = {k: abs(res[key][k] - ref[k]) / max(abs(ref[k]), 1e-300) for k in ("f", "E", "M")}
+        out[f"abs_err_{key}"] = {k: abs(res[key][k] - ref[k]) for k in ("f", "E", "M")}
     return out
 
 
@@ -242,7 +251,7 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
         return
     if a.accuracy:
-        print(json.dumps(accuracy(a.accuracy)), flush=True)
+        print(json.dumps(accuracy(a.accuracy, a.accuracy_variants)), flush=True)
         return
     if a.serve:
         from paper_1911_12954_amd.serve import Server, TrgBackend

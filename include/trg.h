@@ -78,6 +78,10 @@ typedef struct trg_config {
   void (*free)(void *ptr, void *user);
   void *alloc_user;
   size_t workspace_bytes; /* cap on the join workspace; 0 = automatic */
+  int fp64_steps;         /* HOTRG: the first fp64_steps steps join in FP64
+                             whatever `precision` is (0 = none).  Step n
+                             enters ln Z/V with weight 2^-n, so the leading
+                             steps dominate the rounding error of f. */
 } trg_config;
 
 typedef struct trg_ctx trg_ctx;
@@ -91,6 +95,7 @@ typedef struct trg_step_rec {
   int kept[4];            /* kept columns k_nu; 0 on the coarse-grained axis */
   int degenerate_cut[4];  /* 1 if the cut splits a degenerate eigenspace */
   int sweeps[4];          /* Jacobi sweeps used (chosen side) */
+  int join_precision;     /* TRG_FP64 / TRG_FP32 / TRG_BF16X3 of this step's join */
   double ln_c;            /* ln of the Frobenius norm c_n of the new tensor */
   double eps[4][2];       /* discarded eigenvalue sum, [axis][backward, forward] */
   double seconds;         /* host wall time between launch of the step and the

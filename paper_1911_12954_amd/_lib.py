@@ -31,6 +31,7 @@ class TrgConfig(C.Structure):
         ("free", FREE_FN),
         ("alloc_user", C.c_void_p),
         ("workspace_bytes", C.c_size_t),
+        ("fp64_steps", C.c_int),
     ]
 
 
@@ -43,6 +44,7 @@ class TrgStepRec(C.Structure):
         ("kept", C.c_int * 4),
         ("degenerate_cut", C.c_int * 4),
         ("sweeps", C.c_int * 4),
+        ("join_precision", C.c_int),
         ("ln_c", C.c_double),
         ("eps", (C.c_double * 2) * 4),
         ("seconds", C.c_double),

@@ -1000,6 +1000,7 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
   trg_step_rec hr{};
   hr.n = n_step;
   hr.axis = mu;
+  hr.join_precision = c.cfg.precision;
   for (int a = 0; a < 4; ++a) {
     hr.dims[a] = a < d ? nd[a] : 0;
     hr.side[a] = -1;

@@ -195,6 +195,11 @@ double *rec_d(trg_ctx &c, int n);
 int *rec_i(trg_ctx &c, int n);
 void ensure_records(trg_ctx &c, int need);
 
+// precision of the next HOTRG join: FP64 for the first cfg.fp64_steps steps
+inline int join_precision(const trg_ctx &c) {
+  return c.nsteps < c.cfg.fp64_steps ? int(TRG_FP64) : c.cfg.precision;
+}
+
 // C(out_names, contiguous) = sum over the legs shared by A and B of A * B,
 // through packed, padded operands and the MFMA GEMM (prec FP64 or FP32).
 void einsum2(trg_ctx &c, const double *A, const View &va, const double *B, const View &vb, double *C,

@@ -323,7 +323,7 @@ StepPrep prepare_step(trg_ctx &c, int mu, int dcut) {
   StepPrep p;
   StepShape &sh = p.sh;
   sh.mu = mu;
-  sh.prec = c.cfg.precision;
+  sh.prec = join_precision(c);
   for (int ax = 0; ax < d; ++ax)
     if (ax != mu) sh.others.push_back(ax);
   const size_t npre = (sh.others.size() + 1) / 2;
@@ -484,6 +484,7 @@ void contract_step(trg_ctx &c, StepPrep &prep, int mu) {
   trg_step_rec hr{};
   hr.n = n_step;
   hr.axis = mu;
+  hr.join_precision = sh.prec;
   for (int ax = 0; ax < 4; ++ax) {
     hr.dims[ax] = ax < d ? sh.nd[ax] : 0;
     hr.side[ax] = -1;
@@ -573,6 +574,7 @@ void validate_cfg(const trg_config *cfg, int d) {
   TRG_REQUIRE(cfg->dcut >= 0 && cfg->dcut <= 1024, "dcut out of range");
   TRG_REQUIRE((cfg->impure & ~3u) == 0, "unknown impurity bits");
   TRG_REQUIRE(!cfg->alloc == !cfg->free, "alloc and free must be given together");
+  TRG_REQUIRE(cfg->fp64_steps >= 0, "fp64_steps must be >= 0");
 }
 
 // normalise the freshly written tensors: c_0 = ||T||, acc = ln c_0
@@ -676,9 +678,9 @@ int trg_hotrg_step_batch(trg_ctx *const *ctxs, int n, int axis, int dcut) {
   if (!ctxs || n < 1) return fail(nullptr, TRG_EINVAL, "empty batch");
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i]) return fail(nullptr, TRG_EINVAL, "NULL context in batch");
-    if (ctxs[i]->d != ctxs[0]->d || ctxs[i]->cfg.precision != ctxs[0]->cfg.precision ||
+    if (ctxs[i]->d != ctxs[0]->d || join_precision(*ctxs[i]) != join_precision(*ctxs[0]) ||
         ctxs[i]->st != ctxs[0]->st)
-      return fail(nullptr, TRG_EINVAL, "batch contexts differ in d, precision or stream");
+      return fail(nullptr, TRG_EINVAL, "batch contexts differ in d, join precision or stream");
     for (int a = 0; a < ctxs[0]->d; ++a)
       if (ctxs[i]->dims[a] != ctxs[0]->dims[a]) return fail(nullptr, TRG_EINVAL, "batch contexts differ in dims");
   }

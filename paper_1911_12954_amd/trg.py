@@ -53,7 +53,7 @@ def _torch_allocator(stream_ptr):
 
 
 def make_config(precision="fp64", method="hotrg", dcut=8, impure=(), stream=None,
-                use_torch_allocator=True, workspace_bytes=0, rsvd_p=0, rsvd_q=0, seed=0):
+                use_torch_allocator=True, workspace_bytes=0, rsvd_p=0, rsvd_q=0, seed=0, fp64_steps=0):
     """Build a trg_config.  ``stream``: a torch.cuda.Stream, an int handle or
     None (torch's current stream when torch has a GPU, else the default)."""
     cfg = L.TrgConfig()
@@ -66,6 +66,7 @@ def make_config(precision="fp64", method="hotrg", dcut=8, impure=(), stream=None
     cfg.impure = bits
     cfg.rsvd_p, cfg.rsvd_q, cfg.seed = int(rsvd_p), int(rsvd_q), int(seed)
     cfg.workspace_bytes = int(workspace_bytes)
+    cfg.fp64_steps = int(fp64_steps)
     keep = []
     sp = None
     try:
@@ -95,6 +96,7 @@ class StepRecord:
     sweeps: tuple
     ln_c: float
     eps: tuple
+    join_precision: str = "fp64"
 
 
 class Context:
@@ -172,7 +174,8 @@ class Context:
             out.append(StepRecord(r.n, r.axis, tuple(r.dims[: self.d]), tuple(r.side[: self.d]),
                                   tuple(r.kept[: self.d]), tuple(r.degenerate_cut[: self.d]),
                                   tuple(r.sweeps[: self.d]), r.ln_c,
-                                  tuple(tuple(r.eps[a]) for a in range(self.d))))
+                                  tuple(tuple(r.eps[a]) for a in range(self.d)),
+                                  {v: k for k, v in PRECISIONS.items()}.get(r.join_precision, "?")))
         return out
 
     def atrg_step(self, axis: int, dcut: int):

@@ -190,3 +190,48 @@ def test_mixed_precision_dcut4_degenerate_case(precision):
     ef = abs(got["f"] - ref["f"]) / abs(ref["f"])
     print(f"[mixed {precision} dcut4] rel err f {ef:.3e}", flush=True)
     assert ef < 1e-3
+
+
+def test_fp64_steps_schedule():
+    """fp64_steps = n joins the first n steps in FP64: with n covering the
+    whole run the mixed-precision context gives the FP64 bits; with n = 5
+    the log shows the switch after step 5."""
+    need_gpu()
+    from paper_1911_12954_amd import trg_init_ising
+    announce("fp64_steps schedule")
+    ref = trg_init_ising(0.1497, 1e-5, 4, dcut=5, precision="fp64", impure=("E", "M"))
+    ref.run(8)
+    for prec in ("fp32", "bf16x3"):
+        a = trg_init_ising(0.1497, 1e-5, 4, dcut=5, precision=prec, impure=("E", "M"), fp64_steps=12)
+        a.run(8)
+        assert [r.join_precision for r in a.step_log()] == ["fp64"] * 12
+        assert (a.free_energy(), a.impure_energy(), a.impure_magnetization()) == \
+               (ref.free_energy(), ref.impure_energy(), ref.impure_magnetization())
+        a.close()
+        b = trg_init_ising(0.1497, 1e-5, 4, dcut=5, precision=prec, impure=("E", "M"), fp64_steps=5)
+        b.run(8)
+        assert [r.join_precision for r in b.step_log()] == ["fp64"] * 5 + [prec] * 7
+        assert abs(b.free_energy() - ref.free_energy()) < 1e-5 * abs(ref.free_energy())
+        b.close()
+    ref.close()
+
+
+@pytest.mark.parametrize("name", ["4d_dcut4_L16_h0", "4d_dcut4_L16_h1e-5", "3d_dcut6_L16_h1e-4",
+                                  "2d_dcut8_L1024_h0"])
+def test_fp64_path_matches_stored_oracle_values(name):
+    """The FP64 path against the oracle's stored results (tests/golden)."""
+    need_gpu()
+    import json
+    import os
+    from paper_1911_12954_amd import trg_init_ising
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_values.json")) as f:
+        c = json.load(f)["cases"][name]
+    announce("stored oracle values", name)
+    ctx = trg_init_ising(c["beta"], c["h"], c["d"], dcut=c["dcut"], precision="fp64", impure=("E", "M"))
+    ctx.run(c["L"])
+    f_, E, M = ctx.free_energy(), ctx.impure_energy(), ctx.impure_magnetization()
+    ctx.close()
+    assert abs(f_ - float(c["ln_z_per_site"])) <= 1e-10 * abs(float(c["ln_z_per_site"]))
+    assert abs(E - float(c["energy"])) <= 1e-10 * abs(float(c["energy"]))
+    m_ref = float(c["magnetization"])
+    assert abs(M - m_ref) <= 1e-10 * abs(m_ref) + 1e-12
