@@ -25,6 +25,7 @@
 // Contractions of named legs go through einsum2: both operands are packed
 // (K-contiguous, zero-padded) by the strided map kernel and multiplied by the
 // MFMA GEMM of the HOTRG join.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 
@@ -774,12 +775,24 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
     const int64_t sq = int64_t(dims[a]) * dims[a];
     nd[a] = a == mu ? dims[a] : int(sq < dcut ? sq : dcut);
   }
+  // Grams of every transverse axis first, so that axes of one order share
+  // one eigensolver launch (one workgroup per matrix)
+  int nnmax = 0;
+  bool same_n = true;
   for (int nu : perp) {
-    const int dn = dims[nu], nn = dn * dn, kn = nd[nu];
-    double *G2 = c.wsp<double>("gG", size_t(2) * nn * nn * 8);
-    double *Wv = c.wsp<double>("gW", size_t(2) * nn * 8);
-    double *Vv = c.wsp<double>("gV", size_t(2) * nn * nn * 8);
-    int *sw = c.wsp<int>("gsw", 16);
+    nnmax = std::max(nnmax, dims[nu] * dims[nu]);
+    same_n = same_n && dims[nu] == dims[perp[0]];
+  }
+  const int npp = int(perp.size());
+  double *Gall = c.wsp<double>("gG", size_t(2) * npp * nnmax * nnmax * 8);
+  double *Wall = c.wsp<double>("gW", size_t(2) * npp * nnmax * 8);
+  double *Vall = c.wsp<double>("gV", size_t(2) * npp * nnmax * nnmax * 8);
+  int *swall = c.wsp<int>("gsw", size_t(2) * npp * 4);
+  for (int idx = 0; idx < npp; ++idx) {
+    const int nu = perp[idx];
+    const int dn = dims[nu], nn = dn * dn;
+    double *G2 = Gall + size_t(2) * idx * nn * nn;   // contiguous batch when every nn agrees
+    if (!same_n) G2 = Gall + size_t(2) * idx * nnmax * nnmax;
     double *PA = c.wsp<double>("gPA", size_t(nn) * k * k * 8);
     double *Xw = c.wsp<double>("gXw", size_t(nsw) * dc * 8);
     double *QX = c.wsp<double>("gQX", size_t(nn) * k * k * 8);
@@ -830,7 +843,24 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
               contiguous({{"kB", k}, {"fb", dn}, {"kB2", k}, {"fb2", dn}}), G2 + size_t(nn) * nn,
               {"fa", "fb", "fa2", "fb2"}, TRG_FP64, "h4");
     }
-    eigh_batched(G2, Wv, Vv, sw, nn, 2, st);
+  }
+  if (same_n) {
+    const int nn = dims[perp[0]] * dims[perp[0]];
+    eigh_batched(Gall, Wall, Vall, swall, nn, 2 * npp, st);
+  } else {
+    for (int idx = 0; idx < npp; ++idx) {
+      const int nn = dims[perp[idx]] * dims[perp[idx]];
+      eigh_batched(Gall + size_t(2) * idx * nnmax * nnmax, Wall + size_t(2) * idx * nnmax,
+                   Vall + size_t(2) * idx * nnmax * nnmax, swall + 2 * idx, nn, 2, st);
+    }
+  }
+  for (int idx = 0; idx < npp; ++idx) {
+    const int nu = perp[idx];
+    const int dn = dims[nu], nn = dn * dn, kn = nd[nu];
+    const size_t stride = same_n ? size_t(nn) : size_t(nnmax);
+    const double *Wv = Wall + 2 * idx * stride;
+    const double *Vv = Vall + 2 * idx * stride * stride;
+    const int *sw = swall + 2 * idx;
     c.ensure(c.U[nu], size_t(nn) * kn * 8);
     c.ensure(c.spec[nu], size_t(nn) * 8);
     c.Un[nu] = nn;

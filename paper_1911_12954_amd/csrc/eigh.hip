@@ -266,7 +266,15 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
     }
     __syncthreads();
   }
-  // ---- implicit QL on (dd, ee) with rotations applied to the rows of A (= Q).
+  // ---- Z = Q^T into V (the Householder vectors are no longer needed), so
+  // that a rotation of columns (i, i+1) of Q reads and writes two contiguous
+  // rows of Z across the threads
+  for (int idx = t; idx < n * n; idx += TQ_THREADS) {
+    const int r = idx / n, c = idx % n;
+    V[c * n + r] = A[idx];
+  }
+  __syncthreads();
+  // ---- implicit QL on (dd, ee) with rotations applied to the columns of Q.
   // An off-diagonal entry deflates when it is at the rounding level of its
   // neighbours or of the whole matrix (anorm): next to rounding-level zero
   // diagonals (rank-deficient Grams) a purely relative test never fires.
@@ -334,14 +342,21 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
       }
       __syncthreads();
       if (done_flag) break;
-      // rotations i = hi down to lo act on columns (i, i+1) of every row
+      // rotations i = hi down to lo act on columns (i, i+1) of every row of
+      // Q, i.e. on rows (i, i+1) of Z; the new entry i is carried in a
+      // register into the next rotation
       const int lo = sweep_lo, hi = sweep_hi;
-      for (int row = t; row < n; row += TQ_THREADS) {
-        double *z = A + size_t(row) * n;
-        for (int i = hi; i >= lo; --i) {
-          const double f = z[i + 1];
-          z[i + 1] = rs[i] * z[i] + rc[i] * f;
-          z[i] = rc[i] * z[i] - rs[i] * f;
+      if (hi >= lo) {
+        for (int row = t; row < n; row += TQ_THREADS) {
+          double *z = V + row;
+          double zi1 = z[size_t(hi + 1) * n];
+          for (int i = hi; i >= lo; --i) {
+            const double zi = z[size_t(i) * n];
+            const double f = zi1;
+            z[size_t(i + 1) * n] = rs[i] * zi + rc[i] * f;
+            zi1 = rc[i] * zi - rs[i] * f;
+          }
+          z[size_t(lo) * n] = zi1;
         }
       }
       ++iter;
@@ -358,10 +373,13 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
   }
   __syncthreads();
   for (int i = t; i < n; i += TQ_THREADS) w[rank[i]] = dd[i];
+  // eigenvector col = row col of Z, sorted into column rank[col] of V
   for (int i = t; i < n * n; i += TQ_THREADS) {
-    const int row = i / n, col = i % n;
-    V[row * n + rank[col]] = A[i];
+    const int col = i / n, row = i % n;
+    A[row * n + rank[col]] = V[i];
   }
+  __syncthreads();
+  for (int i = t; i < n * n; i += TQ_THREADS) V[i] = A[i];
 }
 
 // ------------------------------------------------------------- selection ---

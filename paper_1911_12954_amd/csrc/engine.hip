@@ -15,6 +15,7 @@
 //   4. Frobenius normalisation c_n and acc += 2^{-n} ln c_n in FP64; impure
 //      tensors S' = [C(S,T) + C(T,S)] / (2 c_n) with the same isometries.
 // All of it is enqueued on the context's stream; no host synchronisation.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -346,15 +347,33 @@ StepPrep prepare_step(trg_ctx &c, int mu, int dcut) {
 void isometries_batch(std::vector<trg_ctx *> &cs, std::vector<StepPrep> &ps, int mu) {
   trg_ctx &c0 = *cs[0];
   const int nc = int(cs.size());
-  for (int ax : ps[0].sh.others) {
+  const std::vector<int> &others = ps[0].sh.others;
+  const int nax = int(others.size());
+  // every transverse axis first; axes of one order share one launch
+  int nmax = 0;
+  bool same_n = true;
+  for (int ax : others) {
+    nmax = std::max(nmax, c0.dims[ax] * c0.dims[ax]);
+    same_n = same_n && c0.dims[ax] == c0.dims[others[0]];
+  }
+  const size_t per_ax = size_t(nc) * 2;  // matrices per axis
+  double *G = c0.wsp<double>("gram_G", per_ax * nax * nmax * nmax * 8);
+  double *W = c0.wsp<double>("gram_W", per_ax * nax * nmax * 8);
+  double *V = c0.wsp<double>("gram_V", per_ax * nax * nmax * nmax * 8);
+  int *sw = c0.wsp<int>("gram_sweeps", per_ax * nax * 4);
+  // axis slot a holds per_ax matrices of order n_a, consecutive (stride
+  // n_a^2, n_a for eigenvalues) from offset a * per_ax * nmax^2 (nmax); when
+  // every order agrees the slots are contiguous: one batch of nax * per_ax
+  const size_t slot_n = size_t(nmax);   // = every n_a when same_n
+  auto gbase = [&](int a) { return size_t(a) * per_ax * slot_n * slot_n; };
+  auto wbase = [&](int a) { return size_t(a) * per_ax * slot_n; };
+  for (int a = 0; a < nax; ++a) {
+    const int ax = others[a];
     const int dn = c0.dims[ax];
     const int n = dn * dn;
+    const size_t ms = size_t(n) * n;   // matrix stride inside the slot
     const int dmu = c0.dims[mu];
     const int64_t R = int64_t(dmu) * dn;
-    double *G = c0.wsp<double>("gram_G", size_t(nc) * 2 * n * n * 8);
-    double *W = c0.wsp<double>("gram_W", size_t(nc) * 2 * n * 8);
-    double *V = c0.wsp<double>("gram_V", size_t(nc) * 2 * n * n * 8);
-    int *sw = c0.wsp<int>("gram_sweeps", size_t(nc) * 2 * 4);
     for (int i = 0; i < nc; ++i) {
       trg_ctx &c = *cs[i];
       double *PQ = c.wsp<double>("gram_PQ", size_t(2) * R * R * 8);
@@ -362,10 +381,22 @@ void isometries_batch(std::vector<trg_ctx *> &cs, std::vector<StepPrep> &ps, int
       for (int side = 0; side < 2; ++side) {
         environment(c, T, 2 * mu + 1, 2 * ax + side, PQ, "");
         environment(c, T, 2 * mu, 2 * ax + side, PQ + R * R, "");
-        gram_combine(PQ, PQ + R * R, dmu, dn, G + (size_t(i) * 2 + side) * n * n, c.st);
+        gram_combine(PQ, PQ + R * R, dmu, dn, G + gbase(a) + (size_t(i) * 2 + side) * ms, c.st);
       }
     }
-    eigh_batched(G, W, V, sw, n, 2 * nc, c0.st);
+  }
+  if (same_n) {
+    const int n = c0.dims[others[0]] * c0.dims[others[0]];
+    eigh_batched(G, W, V, sw, n, int(per_ax) * nax, c0.st);
+  } else {
+    for (int a = 0; a < nax; ++a) {
+      const int n = c0.dims[others[a]] * c0.dims[others[a]];
+      eigh_batched(G + gbase(a), W + wbase(a), V + gbase(a), sw + size_t(a) * per_ax, n, int(per_ax), c0.st);
+    }
+  }
+  for (int a = 0; a < nax; ++a) {
+    const int ax = others[a];
+    const int n = c0.dims[ax] * c0.dims[ax];
     for (int i = 0; i < nc; ++i) {
       trg_ctx &c = *cs[i];
       const int k = ps[i].sh.nd[ax];
@@ -373,9 +404,11 @@ void isometries_batch(std::vector<trg_ctx *> &cs, std::vector<StepPrep> &ps, int
       c.ensure(c.spec[ax], size_t(n) * 8);
       c.Un[ax] = n;
       c.Uk[ax] = k;
+      const size_t m = size_t(i) * 2;   // matrix index inside the slot
       SelectOut so{static_cast<double *>(c.U[ax].ptr), ps[i].rd + 1 + 2 * ax, ps[i].ri + 4 * ax,
                    static_cast<double *>(c.spec[ax].ptr)};
-      select_isometry(W + size_t(i) * 2 * n, V + size_t(i) * 2 * n * n, sw + 2 * i, n, k, c.force_side, so, c.st);
+      select_isometry(W + wbase(a) + m * n, V + gbase(a) + m * n * n, sw + size_t(a) * per_ax + m, n, k,
+                      c.force_side, so, c.st);
     }
   }
 }

@@ -127,15 +127,18 @@ void launch_map(const InT *in, const double *U, void *out, int out_kind, MapPara
 }
 
 // ------------------------------------------------------------------ padding ---
-__global__ void zero_pad_kernel(unsigned char *buf, int64_t rows, int64_t rows_pad, int64_t cols,
-                                int64_t ld, int eb, int planes, int64_t plane_stride) {
+// Elem: an unsigned integer type of the element size, so that every store
+// clears one whole element.
+template <typename Elem>
+__global__ void zero_pad_kernel(Elem *buf, int64_t rows, int64_t rows_pad, int64_t cols, int64_t ld, int planes,
+                                int64_t plane_stride) {
   // grid-stride over (plane, row) pairs; each row clears [cols, ld) or all of it
   const int64_t total = int64_t(planes) * rows_pad;
   for (int64_t rr = blockIdx.x; rr < total; rr += gridDim.x) {
     const int64_t plane = rr / rows_pad, row = rr % rows_pad;
-    unsigned char *base = buf + (plane * plane_stride + row * ld) * eb;
+    Elem *base = buf + plane * plane_stride + row * ld;
     const int64_t c0 = row < rows ? cols : 0;
-    for (int64_t c = c0 * eb + threadIdx.x; c < ld * eb; c += blockDim.x) base[c] = 0;
+    for (int64_t c = c0 + threadIdx.x; c < ld; c += blockDim.x) base[c] = Elem(0);
   }
 }
 
@@ -355,8 +358,22 @@ void zero_pad(void *buf, int64_t rows, int64_t rows_pad, int64_t cols, int64_t l
   if (cols == ld && rows == rows_pad) return;
   const int64_t work = int64_t(planes) * rows_pad;
   const uint32_t grid = uint32_t(work < 65536 ? work : 65536);
-  hipLaunchKernelGGL(zero_pad_kernel, dim3(grid), dim3(256), 0, st, static_cast<unsigned char *>(buf), rows,
-                     rows_pad, cols, ld, elem_bytes, planes, plane_stride);
+  switch (elem_bytes) {
+    case 2:
+      hipLaunchKernelGGL(zero_pad_kernel<uint16_t>, dim3(grid), dim3(256), 0, st, static_cast<uint16_t *>(buf), rows,
+                         rows_pad, cols, ld, planes, plane_stride);
+      break;
+    case 4:
+      hipLaunchKernelGGL(zero_pad_kernel<uint32_t>, dim3(grid), dim3(256), 0, st, static_cast<uint32_t *>(buf), rows,
+                         rows_pad, cols, ld, planes, plane_stride);
+      break;
+    case 8:
+      hipLaunchKernelGGL(zero_pad_kernel<uint64_t>, dim3(grid), dim3(256), 0, st, static_cast<uint64_t *>(buf), rows,
+                         rows_pad, cols, ld, planes, plane_stride);
+      break;
+    default:
+      throw Error(-1, "zero_pad: element size must be 2, 4 or 8 bytes");
+  }
   TRG_HIP_CHECK(hipGetLastError());
 }
 
