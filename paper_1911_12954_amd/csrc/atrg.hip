@@ -86,14 +86,11 @@ __global__ void trial_kernel(double *out, uint32_t count, uint32_t step, uint32_
 // numerically dependent on the previous ones (rank-deficient Y): that column
 // of Q is set to zero (column of Rinv zero) and its row of R is zero, so
 // Y = Q R still holds and no division by a vanishing pivot occurs.
-template <bool IN_LDS>
 __global__ void __launch_bounds__(256)
-chol_inv_kernel(const double *C, int n, double shift_coef, double *Rg, double *Rinv, int *err) {
-  extern __shared__ double Rlds[];
+chol_inv_kernel(const double *C, int n, double shift_coef, double *R, double *Rinv, int *err) {
   __shared__ double sh[256];
   __shared__ double shm[256];
   __shared__ int dead[1024];
-  double *R = IN_LDS ? Rlds : Rg;  // working copy of the factor
   const int t = threadIdx.x;
   double tr = 0.0, mx = 0.0;
   for (int i = t; i < n; i += 256) {
@@ -155,26 +152,190 @@ chol_inv_kernel(const double *C, int n, double shift_coef, double *Rg, double *R
   for (int i = t; i < n * n; i += 256) {
     const int r = i / n, c = i % n;
     if (dead[c]) Rinv[i] = 0.0;
-    const double v = dead[r] ? 0.0 : R[i];
-    if (IN_LDS) Rg[i] = v;
-    else R[i] = v;
+    if (dead[r]) R[i] = 0.0;
+  }
+}
+
+// The same factorisation for n <= 128 with both triangles packed in LDS
+// (row i of an upper triangle starts at i n - i (i - 1) / 2): the pivot sums
+// are block reductions, the rows of R and of Rinv are computed by all threads
+// at once (one barrier per row), so no thread runs an O(n^2) chain.
+constexpr int CHOL_PACK_MAX = 128;
+__device__ inline int tri(int i, int j, int n) { return i * n - (i * (i - 1)) / 2 + (j - i); }
+
+__global__ void __launch_bounds__(256)
+chol_inv_packed_kernel(const double *C, int n, double shift_coef, double *Rg, double *Rinv, int *err) {
+  extern __shared__ double lds[];
+  const int npk = n * (n + 1) / 2;
+  double *R = lds, *I = lds + npk;
+  __shared__ double sh[256];
+  __shared__ double shm[256];
+  __shared__ int dead[CHOL_PACK_MAX];
+  __shared__ double piv;
+  const int t = threadIdx.x;
+  double tr = 0.0, mx = 0.0;
+  for (int i = t; i < n; i += 256) {
+    tr += C[i * n + i];
+    mx = fmax(mx, C[i * n + i]);
+  }
+  sh[t] = tr;
+  shm[t] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      sh[t] += sh[t + s];
+      shm[t] = fmax(shm[t], shm[t + s]);
+    }
+    __syncthreads();
+  }
+  const double shift = shift_coef * sh[0];
+  const double tol = 1e-26 * (shm[0] + shift);
+  __syncthreads();
+  for (int idx = t; idx < n * n; idx += 256) {
+    const int r = idx / n, c = idx % n;
+    if (r <= c) R[tri(r, c, n)] = C[idx] + (r == c ? shift : 0.0);
+  }
+  for (int i = t; i < n; i += 256) dead[i] = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    // pivot: R[j][j] - sum_{k<j} R[k][j]^2
+    double s2 = 0.0;
+    for (int k = t; k < j; k += 256) {
+      const double v = R[tri(k, j, n)];
+      s2 += v * v;
+    }
+    sh[t] = s2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (t < s) sh[t] += sh[t + s];
+      __syncthreads();
+    }
+    if (t == 0) {
+      double dj = R[tri(j, j, n)] - sh[0];
+      if (!(dj > tol)) {
+        if (!isfinite(dj)) *err |= 4;
+        dead[j] = 1;
+        dj = 1.0;
+      }
+      piv = sqrt(dj);
+      R[tri(j, j, n)] = piv;
+    }
+    __syncthreads();
+    const double rjj = piv;
+    const bool dj_dead = dead[j] != 0;
+    for (int i = j + 1 + t; i < n; i += 256) {
+      double v = R[tri(j, i, n)];
+      for (int k = 0; k < j; ++k) v -= R[tri(k, j, n)] * R[tri(k, i, n)];
+      R[tri(j, i, n)] = dj_dead ? 0.0 : v / rjj;
+    }
+    __syncthreads();
+  }
+  // Rinv by rows from the bottom: I[i][j] = (delta_ij - sum_{i<k<=j} R[i][k] I[k][j]) / R[i][i]
+  for (int i = n - 1; i >= 0; --i) {
+    const double rii = R[tri(i, i, n)];
+    for (int j = i + t; j < n; j += 256) {
+      double v = (i == j) ? 1.0 : 0.0;
+      for (int k = i + 1; k <= j; ++k) v -= R[tri(i, k, n)] * I[tri(k, j, n)];
+      I[tri(i, j, n)] = v / rii;
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < n * n; idx += 256) {
+    const int r = idx / n, c = idx % n;
+    Rinv[idx] = (r <= c && !dead[c]) ? I[tri(r, c, n)] : 0.0;
+    Rg[idx] = (r <= c && !dead[r]) ? R[tri(r, c, n)] : 0.0;
   }
 }
 
 void launch_chol_inv(const double *C, int n, double shift, double *R, double *Rinv, int *err, hipStream_t st) {
   TRG_REQUIRE(n >= 1 && n <= 1024, "chol: bad order");
-  if (n <= 128) {
+  if (n <= CHOL_PACK_MAX) {
+    const size_t lds = size_t(n) * (n + 1) * 8;   // two packed triangles
     static bool attr = false;
     if (!attr) {
-      TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&chol_inv_kernel<true>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 128 * 8));
+      TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&chol_inv_packed_kernel),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        CHOL_PACK_MAX * (CHOL_PACK_MAX + 1) * 8));
       attr = true;
     }
-    hipLaunchKernelGGL(chol_inv_kernel<true>, dim3(1), dim3(256), size_t(n) * n * 8, st, C, n, shift, R, Rinv, err);
+    hipLaunchKernelGGL(chol_inv_packed_kernel, dim3(1), dim3(256), lds, st, C, n, shift, R, Rinv, err);
   } else {
-    hipLaunchKernelGGL(chol_inv_kernel<false>, dim3(1), dim3(256), 0, st, C, n, shift, R, Rinv, err);
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, st, C, n, shift, R, Rinv, err);
   }
   TRG_HIP_CHECK(hipGetLastError());
+}
+
+// Tall-skinny products of the CholeskyQR passes, for k <= 128 columns,
+// read straight from the row-major m x k matrix Y (no packing):
+//   ts_gram: part[b] = Y[rows of block b]^T Y[rows of block b]; each thread
+//            owns an 8 x 8 block of the 128 x 128 output, the rows are staged
+//            through LDS in chunks of 32 (zero-padded to 128 columns);
+//   ts_mul:  Q = Y R, R k x k, one thread per (row, column) of Q, the rows of
+//            Y staged through LDS.
+constexpr int TS_MAXK = 128;
+constexpr int TS_CHUNK = 32;
+
+__global__ void __launch_bounds__(256)
+ts_gram_kernel(const double *Y, int64_t m, int k, int64_t rows_per_block, double *part) {
+  __shared__ double L[TS_CHUNK][TS_MAXK];
+  const int t = threadIdx.x;
+  const int ta = t / 16, tb = t % 16;
+  const int64_t r0 = int64_t(blockIdx.x) * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < m ? r0 + rows_per_block : m;
+  double acc[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+  for (int64_t base = r0; base < r1; base += TS_CHUNK) {
+    const int rows = int(r1 - base < TS_CHUNK ? r1 - base : TS_CHUNK);
+    for (int idx = t; idx < TS_CHUNK * TS_MAXK; idx += 256) {
+      const int r = idx / TS_MAXK, c = idx % TS_MAXK;
+      L[r][c] = (r < rows && c < k) ? Y[(base + r) * k + c] : 0.0;
+    }
+    __syncthreads();
+    for (int r = 0; r < rows; ++r) {
+      double av[8], bv[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) av[a] = L[r][ta * 8 + a];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) bv[b] = L[r][tb * 8 + b];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] += av[a] * bv[b];
+    }
+    __syncthreads();
+  }
+  double *out = part + size_t(blockIdx.x) * k * k;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = ta * 8 + a, j = tb * 8 + b;
+      if (i < k && j < k) out[i * k + j] = acc[a][b];
+    }
+}
+
+constexpr int TS_MUL_ROWS = 16;
+
+__global__ void __launch_bounds__(256)
+ts_mul_kernel(const double *Y, int64_t m, int k, const double *R, double *Q) {
+  __shared__ double L[TS_MUL_ROWS][TS_MAXK];
+  const int t = threadIdx.x;
+  const int64_t r0 = int64_t(blockIdx.x) * TS_MUL_ROWS;
+  const int rows = int(m - r0 < TS_MUL_ROWS ? m - r0 : TS_MUL_ROWS);
+  for (int idx = t; idx < TS_MUL_ROWS * TS_MAXK; idx += 256) {
+    const int r = idx / TS_MAXK, c = idx % TS_MAXK;
+    L[r][c] = (r < rows && c < k) ? Y[(r0 + r) * k + c] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = t; idx < rows * k; idx += 256) {
+    const int r = idx / k, c = idx % k;
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += L[r][j] * R[j * k + c];
+    Q[(r0 + r) * k + c] = acc;
+  }
 }
 
 // C = A B for n x n matrices (one workgroup)
@@ -310,6 +471,10 @@ __global__ void __launch_bounds__(256) sum_partials(const double *partial, int n
 }
 
 // ------------------------------------------------------------- host helpers ---
+// Step trace for diagnosing an ATRG run: with TRG_DEBUG set in the
+// environment, every named intermediate is copied back and summarised on
+// stderr (size, non-finite count, max |x|, 2-norm, device error flags).  Off
+// by default (one cached getenv, no synchronisation).
 void dbg(trg_ctx &c, const char *name, const double *p, int64_t count) {
   static const bool on = std::getenv("TRG_DEBUG") != nullptr;
   if (!on) return;
@@ -362,12 +527,28 @@ void cholqr3(trg_ctx &c, const double *Y, int64_t m, int k, double *Q, double *R
   const View vk = contiguous({{"i", m}, {"k", k}});
   const double u = std::ldexp(1.0, -53);
   const double *src = Y;
+  const bool ts = k <= TS_MAXK;
+  const int64_t ts_rows = std::max<int64_t>(TS_CHUNK, (m + 63) / 64);   // about 64 blocks
+  const int64_t ts_blocks = (m + ts_rows - 1) / ts_rows;
+  double *part = ts ? c.wsp<double>("qrP" + tag, size_t(ts_blocks) * k * k * 8) : nullptr;
   for (int pass = 0; pass < 3; ++pass) {
-    einsum2(c, src, vy, src, rename(vy, {{"c", "c2"}}), Cg, {"c", "c2"}, TRG_FP64, "qr" + tag);
+    if (ts) {
+      hipLaunchKernelGGL(ts_gram_kernel, dim3(uint32_t(ts_blocks)), dim3(256), 0, c.st, src, m, k, ts_rows, part);
+      TRG_HIP_CHECK(hipGetLastError());
+      reduce_splits(part, int(ts_blocks), k, k, k, int64_t(k) * k, Cg, k, c.st);
+    } else {
+      einsum2(c, src, vy, src, rename(vy, {{"c", "c2"}}), Cg, {"c", "c2"}, TRG_FP64, "qr" + tag);
+    }
     const double shift = pass == 0 ? 11.0 * (double(m) * k + double(k) * (k + 1)) * u : 0.0;
     launch_chol_inv(Cg, k, shift, R, Ri, c.errp(), c.st);
     double *dst = pass == 2 ? Q : (pass == 0 ? bufA : bufB);
-    einsum2(c, src, vk, Ri, contiguous({{"k", k}, {"c", k}}), dst, {"i", "c"}, TRG_FP64, "qm" + tag);
+    if (ts) {
+      hipLaunchKernelGGL(ts_mul_kernel, dim3(uint32_t((m + TS_MUL_ROWS - 1) / TS_MUL_ROWS)), dim3(256), 0, c.st, src,
+                         m, k, Ri, dst);
+      TRG_HIP_CHECK(hipGetLastError());
+    } else {
+      einsum2(c, src, vk, Ri, contiguous({{"k", k}, {"c", k}}), dst, {"i", "c"}, TRG_FP64, "qm" + tag);
+    }
     if (Rout) {
       if (pass == 0) {
         TRG_HIP_CHECK(hipMemcpyAsync(Racc, R, size_t(k) * k * 8, hipMemcpyDeviceToDevice, c.st));

@@ -74,3 +74,49 @@ def test_gemm_tile_and_footprint(lib):
     # the workspace at Dcut 10 holds at least the whole Bt operand and the
     # D^9 operand-build temporary
     assert lib.trg_workspace_bytes(4, 10, L.TRG_FP64, L.TRG_HOTRG, 0) > 10 ** 9 * 8 + 10 ** 5 * 10 ** 5 * 8
+
+
+def test_more_argument_checks_on_the_host(lib):
+    """Every rejected call returns TRG_EINVAL and sets a message before any
+    device work (these run without a GPU)."""
+    h = C.c_void_p()
+    cfg = L.TrgConfig()
+    cfg.fp64_steps = -1
+    assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
+    assert b"fp64_steps" in lib.trg_last_error(None)
+    cfg = L.TrgConfig()
+    cfg.method, cfg.precision = L.TRG_ATRG, L.TRG_BF16X3
+    assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
+    cfg = L.TrgConfig()
+    cfg.method, cfg.impure = L.TRG_ATRG, L.TRG_IMPURE_M
+    assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
+    cfg = L.TrgConfig()
+    cfg.dcut = 2000
+    assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
+    cfg = L.TrgConfig()
+    cfg.impure = 4
+    assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
+    cfg = L.TrgConfig()
+    cfg.alloc = L.ALLOC_FN(lambda n, u: None)     # alloc without free
+    assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
+    assert b"together" in lib.trg_last_error(None)
+    assert lib.trg_init_ising(C.byref(h), 0.1, float("inf"), 4, None) == L.TRG_EINVAL
+    # batches, sharing, kernel-level entries
+    assert lib.trg_hotrg_step_batch(None, 1, 0, 4) == L.TRG_EINVAL
+    arr = (C.c_void_p * 2)(None, None)
+    assert lib.trg_hotrg_step_batch(arr, 0, 0, 4) == L.TRG_EINVAL
+    assert lib.trg_hotrg_step_batch(arr, 2, 0, 4) == L.TRG_EINVAL
+    assert lib.trg_share_workspace(None, None) == L.TRG_EINVAL
+    assert lib.trg_atrg_step(None, 0, 4) == L.TRG_EINVAL
+    assert lib.trg_free_energy(None, None) == L.TRG_EINVAL
+    one = C.c_double()
+    # GEMM sizes that are not tile multiples, eigh orders out of range
+    assert lib.trg_gemm(L.TRG_FP64, C.byref(one), C.byref(one), C.byref(one), 100, 128, 16, 16, 16, 128, 0, None) \
+        == L.TRG_EINVAL
+    assert b"tile multiples" in lib.trg_last_error(None)
+    assert lib.trg_gemm(5, C.byref(one), C.byref(one), C.byref(one), 128, 128, 16, 16, 16, 128, 0, None) == L.TRG_EINVAL
+    iv = C.c_int()
+    assert lib.trg_eigh(C.byref(one), C.byref(one), C.byref(one), C.byref(iv), 0, 1, None) == L.TRG_EINVAL
+    assert lib.trg_eigh(C.byref(one), C.byref(one), C.byref(one), C.byref(iv), 2000, 1, None) == L.TRG_EINVAL
+    dims = (C.c_int * 4)(2, 2, 2, 2)
+    assert lib.trg_init_factors(C.byref(h), 4, dims, 2, None, None, None) == L.TRG_EINVAL
