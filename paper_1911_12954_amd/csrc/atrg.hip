@@ -224,8 +224,17 @@ chol_inv_packed_kernel(const double *C, int n, double shift_coef, double *Rg, do
     const double rjj = piv;
     const bool dj_dead = dead[j] != 0;
     for (int i = j + 1 + t; i < n; i += 256) {
-      double v = R[tri(j, i, n)];
-      for (int k = 0; k < j; ++k) v -= R[tri(k, j, n)] * R[tri(k, i, n)];
+      // four partial sums keep several LDS loads in flight
+      double v0 = R[tri(j, i, n)], v1 = 0.0, v2 = 0.0, v3 = 0.0;
+      int k = 0;
+      for (; k + 4 <= j; k += 4) {
+        v0 -= R[tri(k, j, n)] * R[tri(k, i, n)];
+        v1 -= R[tri(k + 1, j, n)] * R[tri(k + 1, i, n)];
+        v2 -= R[tri(k + 2, j, n)] * R[tri(k + 2, i, n)];
+        v3 -= R[tri(k + 3, j, n)] * R[tri(k + 3, i, n)];
+      }
+      for (; k < j; ++k) v0 -= R[tri(k, j, n)] * R[tri(k, i, n)];
+      const double v = (v0 + v1) + (v2 + v3);
       R[tri(j, i, n)] = dj_dead ? 0.0 : v / rjj;
     }
     __syncthreads();
@@ -233,10 +242,18 @@ chol_inv_packed_kernel(const double *C, int n, double shift_coef, double *Rg, do
   // Rinv by rows from the bottom: I[i][j] = (delta_ij - sum_{i<k<=j} R[i][k] I[k][j]) / R[i][i]
   for (int i = n - 1; i >= 0; --i) {
     const double rii = R[tri(i, i, n)];
+    const int ri = tri(i, 0, n);   // R[i][k] = R[ri + k]
     for (int j = i + t; j < n; j += 256) {
-      double v = (i == j) ? 1.0 : 0.0;
-      for (int k = i + 1; k <= j; ++k) v -= R[tri(i, k, n)] * I[tri(k, j, n)];
-      I[tri(i, j, n)] = v / rii;
+      double v0 = (i == j) ? 1.0 : 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+      int k = i + 1;
+      for (; k + 4 <= j + 1; k += 4) {
+        v0 -= R[ri + k] * I[tri(k, j, n)];
+        v1 -= R[ri + k + 1] * I[tri(k + 1, j, n)];
+        v2 -= R[ri + k + 2] * I[tri(k + 2, j, n)];
+        v3 -= R[ri + k + 3] * I[tri(k + 3, j, n)];
+      }
+      for (; k <= j; ++k) v0 -= R[ri + k] * I[tri(k, j, n)];
+      I[tri(i, j, n)] = ((v0 + v1) + (v2 + v3)) / rii;
     }
     __syncthreads();
   }
@@ -265,77 +282,123 @@ void launch_chol_inv(const double *C, int n, double shift, double *R, double *Ri
   TRG_HIP_CHECK(hipGetLastError());
 }
 
-// Tall-skinny products of the CholeskyQR passes, for k <= 128 columns,
-// read straight from the row-major m x k matrix Y (no packing):
-//   ts_gram: part[b] = Y[rows of block b]^T Y[rows of block b]; each thread
-//            owns an 8 x 8 block of the 128 x 128 output, the rows are staged
-//            through LDS in chunks of 32 (zero-padded to 128 columns);
-//   ts_mul:  Q = Y R, R k x k, one thread per (row, column) of Q, the rows of
-//            Y staged through LDS.
-constexpr int TS_MAXK = 128;
-constexpr int TS_CHUNK = 32;
+// Gram matrix C = Y^T Y of a tall m x k row-major matrix (k <= 128) on FP64
+// MFMA, read in place: workgroup b sums the rows [b rpw, (b+1) rpw) into its
+// own 128 x 128 slab part[b] (columns beyond k are zero), four waves of
+// 64 x 64; rows are staged through LDS 32 at a time (row stride 144 doubles:
+// the four rows a k-step reads fall on disjoint halves of the banks).  The
+// slabs are then summed in a fixed order, so the result is deterministic.
+// v_mfma_f64_16x16x4: lane (g, r16) supplies A[r16][g] = Y[row g][col r16]
+// and B[r16][g] likewise; accumulator e of the lane is C[g + 4e][r16].
+constexpr int TSG_K = 128, TSG_ROWS = 32, TSG_LD = 144;
+typedef double tsg_v4d __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256)
-ts_gram_kernel(const double *Y, int64_t m, int k, int64_t rows_per_block, double *part) {
-  __shared__ double L[TS_CHUNK][TS_MAXK];
-  const int t = threadIdx.x;
-  const int ta = t / 16, tb = t % 16;
-  const int64_t r0 = int64_t(blockIdx.x) * rows_per_block;
-  const int64_t r1 = r0 + rows_per_block < m ? r0 + rows_per_block : m;
-  double acc[8][8];
+ts_gram_kernel(const double *__restrict__ Y, int64_t m, int k, int64_t rpw, double *__restrict__ part) {
+  __shared__ double L[TSG_ROWS * TSG_LD];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t r0 = int64_t(blockIdx.x) * rpw;
+  const int64_t r1 = r0 + rpw < m ? r0 + rpw : m;
+  tsg_v4d acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
-  for (int64_t base = r0; base < r1; base += TS_CHUNK) {
-    const int rows = int(r1 - base < TS_CHUNK ? r1 - base : TS_CHUNK);
-    for (int idx = t; idx < TS_CHUNK * TS_MAXK; idx += 256) {
-      const int r = idx / TS_MAXK, c = idx % TS_MAXK;
-      L[r][c] = (r < rows && c < k) ? Y[(base + r) * k + c] : 0.0;
+    for (int j = 0; j < 4; ++j) acc[i][j] = tsg_v4d{0.0, 0.0, 0.0, 0.0};
+  for (int64_t base = r0; base < r1; base += TSG_ROWS) {
+    const int64_t rows = r1 - base < TSG_ROWS ? r1 - base : TSG_ROWS;
+    for (int idx = t; idx < TSG_ROWS * TSG_K; idx += 256) {
+      const int r = idx / TSG_K, c = idx % TSG_K;
+      L[r * TSG_LD + c] = (r < rows && c < k) ? Y[(base + r) * k + c] : 0.0;
     }
     __syncthreads();
-    for (int r = 0; r < rows; ++r) {
-      double av[8], bv[8];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) av[a] = L[r][ta * 8 + a];
+    for (int s = 0; s < TSG_ROWS / 4; ++s) {
+      const double *row = L + (4 * s + g) * TSG_LD;
+      double a[4], b[4];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) bv[b] = L[r][tb * 8 + b];
+      for (int i = 0; i < 4; ++i) a[i] = row[64 * wm + 16 * i + r16];
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
+      for (int j = 0; j < 4; ++j) b[j] = row[64 * wn + 16 * j + r16];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) acc[a][b] += av[a] * bv[b];
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
-  double *out = part + size_t(blockIdx.x) * k * k;
+  double *out = part + size_t(blockIdx.x) * TSG_K * TSG_K;
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int i = ta * 8 + a, j = tb * 8 + b;
-      if (i < k && j < k) out[i * k + j] = acc[a][b];
-    }
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = 64 * wm + 16 * i + g + 4 * e, col = 64 * wn + 16 * j + r16;
+        out[row * TSG_K + col] = acc[i][j][e];
+      }
 }
 
-constexpr int TS_MUL_ROWS = 16;
+// Q = Y R for a tall m x k row-major Y and a k x k R (k <= 128) on FP64
+// MFMA, in place: a workgroup takes 128 rows of Y, staged in LDS with a row
+// stride of 130 doubles (the 16 rows x 2 k values that 32 lanes read fall on
+// distinct banks; 16 consecutive lanes store contiguous bytes), each wave 32
+// rows x 128 columns, so every fragment of R read from L2 feeds two MFMAs.
+constexpr int TSM_ROWS = 128, TSM_LD = 130;
 
 __global__ void __launch_bounds__(256)
-ts_mul_kernel(const double *Y, int64_t m, int k, const double *R, double *Q) {
-  __shared__ double L[TS_MUL_ROWS][TS_MAXK];
-  const int t = threadIdx.x;
-  const int64_t r0 = int64_t(blockIdx.x) * TS_MUL_ROWS;
-  const int rows = int(m - r0 < TS_MUL_ROWS ? m - r0 : TS_MUL_ROWS);
-  for (int idx = t; idx < TS_MUL_ROWS * TS_MAXK; idx += 256) {
-    const int r = idx / TS_MAXK, c = idx % TS_MAXK;
-    L[r][c] = (r < rows && c < k) ? Y[(r0 + r) * k + c] : 0.0;
+ts_mul_kernel(const double *__restrict__ Y, int64_t m, int k, const double *__restrict__ R, double *__restrict__ Q) {
+  extern __shared__ double L[];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  const int64_t r0 = int64_t(blockIdx.x) * TSM_ROWS;
+  const int64_t rows = m - r0 < TSM_ROWS ? m - r0 : TSM_ROWS;
+  for (int idx = t; idx < TSM_ROWS * TSG_K; idx += 256) {
+    const int r = idx / TSG_K, c = idx % TSG_K;
+    L[r * TSM_LD + c] = (r < rows && c < k) ? Y[(r0 + r) * k + c] : 0.0;
   }
   __syncthreads();
-  for (int idx = t; idx < rows * k; idx += 256) {
-    const int r = idx / k, c = idx % k;
-    double acc = 0.0;
-    for (int j = 0; j < k; ++j) acc += L[r][j] * R[j * k + c];
-    Q[(r0 + r) * k + c] = acc;
+  tsg_v4d acc[2][8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[h][j] = tsg_v4d{0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < TSG_K / 4; ++s) {
+    const int kk = 4 * s + g;
+    double a[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) a[h] = L[(32 * wave + 16 * h + r16) * TSM_LD + kk];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int col = 16 * j + r16;
+      const double b = (kk < k && col < k) ? R[kk * k + col] : 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) acc[h][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], b, acc[h][j], 0, 0, 0);
+    }
   }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = 32 * wave + 16 * h + g + 4 * e;
+        const int col = 16 * j + r16;
+        if (row < rows && col < k) Q[(r0 + row) * k + col] = acc[h][j][e];
+      }
+}
+
+void launch_ts_mul(const double *Y, int64_t m, int k, const double *R, double *Q, hipStream_t st) {
+  const size_t lds = size_t(TSM_ROWS) * TSM_LD * 8;
+  static bool attr = false;
+  if (!attr) {
+    TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&ts_mul_kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    attr = true;
+  }
+  hipLaunchKernelGGL(ts_mul_kernel, dim3(uint32_t((m + TSM_ROWS - 1) / TSM_ROWS)), dim3(256), lds, st, Y, m, k, R, Q);
+  TRG_HIP_CHECK(hipGetLastError());
 }
 
 // C = A B for n x n matrices (one workgroup)
@@ -527,25 +590,23 @@ void cholqr3(trg_ctx &c, const double *Y, int64_t m, int k, double *Q, double *R
   const View vk = contiguous({{"i", m}, {"k", k}});
   const double u = std::ldexp(1.0, -53);
   const double *src = Y;
-  const bool ts = k <= TS_MAXK;
-  const int64_t ts_rows = std::max<int64_t>(TS_CHUNK, (m + 63) / 64);   // about 64 blocks
-  const int64_t ts_blocks = (m + ts_rows - 1) / ts_rows;
-  double *part = ts ? c.wsp<double>("qrP" + tag, size_t(ts_blocks) * k * k * 8) : nullptr;
+  const bool tsg = k <= TSG_K;
+  const int64_t tsg_rows = std::max<int64_t>(TSG_ROWS, (m + 255) / 256);   // about 256 workgroups
+  const int64_t tsg_wg = (m + tsg_rows - 1) / tsg_rows;
+  double *part = tsg ? c.wsp<double>("qrP" + tag, size_t(tsg_wg) * TSG_K * TSG_K * 8) : nullptr;
   for (int pass = 0; pass < 3; ++pass) {
-    if (ts) {
-      hipLaunchKernelGGL(ts_gram_kernel, dim3(uint32_t(ts_blocks)), dim3(256), 0, c.st, src, m, k, ts_rows, part);
+    if (tsg) {
+      hipLaunchKernelGGL(ts_gram_kernel, dim3(uint32_t(tsg_wg)), dim3(256), 0, c.st, src, m, k, tsg_rows, part);
       TRG_HIP_CHECK(hipGetLastError());
-      reduce_splits(part, int(ts_blocks), k, k, k, int64_t(k) * k, Cg, k, c.st);
+      reduce_splits(part, int(tsg_wg), k, k, TSG_K, int64_t(TSG_K) * TSG_K, Cg, k, c.st);
     } else {
       einsum2(c, src, vy, src, rename(vy, {{"c", "c2"}}), Cg, {"c", "c2"}, TRG_FP64, "qr" + tag);
     }
     const double shift = pass == 0 ? 11.0 * (double(m) * k + double(k) * (k + 1)) * u : 0.0;
     launch_chol_inv(Cg, k, shift, R, Ri, c.errp(), c.st);
     double *dst = pass == 2 ? Q : (pass == 0 ? bufA : bufB);
-    if (ts) {
-      hipLaunchKernelGGL(ts_mul_kernel, dim3(uint32_t((m + TS_MUL_ROWS - 1) / TS_MUL_ROWS)), dim3(256), 0, c.st, src,
-                         m, k, Ri, dst);
-      TRG_HIP_CHECK(hipGetLastError());
+    if (tsg) {
+      launch_ts_mul(src, m, k, Ri, dst, c.st);
     } else {
       einsum2(c, src, vk, Ri, contiguous({{"k", k}, {"c", k}}), dst, {"i", "c"}, TRG_FP64, "qm" + tag);
     }
