@@ -9,9 +9,9 @@
 //
 //   FP64   v_mfma_f64_16x16x4_f64   128 x 128 tile, four 64 x 64 waves,
 //          RB 128 (16 doubles, 4 MFMA k-steps), two padded LDS stages
-//   FP32   v_mfma_f32_16x16x4_f32   128 x 128 tile, four 64 x 64 waves,
-//          RB 128 (32 floats, 8 k-steps), one padded stage (two workgroups
-//          per CU)
+//   FP32   v_mfma_f32_16x16x4_f32   128 x 128 tile, eight 64 x 32 waves,
+//          RB 128 (32 floats, 8 k-steps), two padded stages; the MFMA sums
+//          4 K tiles (128 products) in FP32, the groups are summed in FP64
 //   BF16X3 v_mfma_f32_16x16x32_bf16 256 x 256 tile, eight 128 x 64 waves,
 //          RB 64 (32 bf16 per plane, 1 k-step, three products hi*hi +
 //          hi*lo + lo*hi into one FP32 accumulator), two swizzled stages
@@ -38,6 +38,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int NUM_XCD = 8;
+// FP32 join: K tiles (32 floats each) summed by the MFMA in FP32 before the
+// partial sum is added to the FP64 accumulator
+constexpr uint32_t F32_FLUSH = 4;
 #ifndef TRG_GROUP_M
 #define TRG_GROUP_M 8
 #endif
@@ -48,7 +51,10 @@ constexpr int GROUP_M = TRG_GROUP_M;
 #define TRG_F64_STAGES 2
 #endif
 #ifndef TRG_F32_STAGES
-#define TRG_F32_STAGES 1
+#define TRG_F32_STAGES 2
+#endif
+#ifndef TRG_F32_WN
+#define TRG_F32_WN 4
 #endif
 
 template <int PREC> struct Prec;
@@ -200,6 +206,17 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{};
+  // FP32 products: the MFMA accumulates one group of F32_FLUSH K tiles in
+  // FP32, the groups are summed in FP64, so the rounding of the sum no longer
+  // grows with the full length of K
+  constexpr bool F64SUM = PREC == 1;
+  v4d acc64[F64SUM ? FM : 1][F64SUM ? FN : 1];
+  if constexpr (F64SUM) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc64[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
 
   gload(0);
   if constexpr (STAGES == 2) {
@@ -272,6 +289,18 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
             }
     }
 
+    if constexpr (F64SUM) {
+      if ((kt + 1) % F32_FLUSH == 0 || kt + 1 == ktiles) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc64[i][j][e] += double(acc[i][j][e]);
+            acc[i][j] = acc_t{};
+          }
+      }
+    }
     if constexpr (STAGES == 2) {
       if (kt + 1 < ktiles) sstore(cur ^ 1);
     }
@@ -291,10 +320,17 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
         const uint64_t m = m0 + wm * TM + i * 16 + row;
         const uint64_t n = n0 + wn * TN + j * 16 + r16;
         auto *dst = C + m * ldc + n;
-        if constexpr (ACCUM)
-          *dst += acc[i][j][e];
-        else
-          *dst = acc[i][j][e];
+        if constexpr (F64SUM) {
+          if constexpr (ACCUM)
+            *dst = float(double(*dst) + acc64[i][j][e]);
+          else
+            *dst = float(acc64[i][j][e]);
+        } else {
+          if constexpr (ACCUM)
+            *dst += acc[i][j][e];
+          else
+            *dst = acc[i][j][e];
+        }
       }
 }
 
@@ -367,7 +403,7 @@ void gemm_nt(int prec, const void *A, const void *Bt, void *C, uint64_t M, uint6
              uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st) {
   switch (prec) {
     case 0: launch_gemm<0, 128, 128, 2, 2, TRG_F64_STAGES>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
-    case 1: launch_gemm<1, 128, 128, 2, 2, TRG_F32_STAGES>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
+    case 1: launch_gemm<1, 128, 128, 2, TRG_F32_WN, TRG_F32_STAGES>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
     case 2:
       launch_gemm<2, BF::BM, BF::BN, BF::WM, BF::WN, BF::S, BF::RB, BF::SWZ>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st);
       return;
