@@ -27,7 +27,10 @@ struct MapParams {
   int64_t iso, isu;     // its output and matrix strides
   uint32_t count;
   int64_t lo_plane;
+  int32_t u_lds;        // > 0: the matrix entries [0, u_lds) are staged in LDS
 };
+// largest matrix (doubles) a map workgroup stages in LDS
+constexpr int MAP_ULDS_MAX = 6144;
 
 template <int OUT>
 __device__ inline void map_store(void *out, int64_t o, int64_t lo_plane, double v) {
@@ -47,8 +50,16 @@ __device__ inline void map_store(void *out, int64_t o, int64_t lo_plane, double 
 
 template <typename InT, int OUT>
 __global__ void __launch_bounds__(256)
-map_kernel(const InT *__restrict__ in, const double *__restrict__ U, void *__restrict__ out,
+map_kernel(const InT *__restrict__ in, const double *__restrict__ Ug, void *__restrict__ out,
            MapParams p) {
+  extern __shared__ double Us[];
+  const double *U = Ug;
+  if (p.u_lds > 0) {
+    // every thread of the block reaches this barrier (the bound check follows)
+    for (int i = threadIdx.x; i < p.u_lds; i += 256) Us[i] = Ug[i];
+    __syncthreads();
+    U = Us;
+  }
   const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
   if (idx >= p.count) return;
   uint32_t q = idx;
@@ -117,10 +128,11 @@ map_kernel(const InT *__restrict__ in, const double *__restrict__ U, void *__res
 template <typename InT>
 void launch_map(const InT *in, const double *U, void *out, int out_kind, MapParams &p, hipStream_t st) {
   const dim3 grid((p.count + 255) / 256), block(256);
+  const size_t lds = p.u_lds > 0 ? size_t(p.u_lds) * 8 : 0;
   switch (out_kind) {
-    case OUT_F64: hipLaunchKernelGGL((map_kernel<InT, OUT_F64>), grid, block, 0, st, in, U, out, p); break;
-    case OUT_F32: hipLaunchKernelGGL((map_kernel<InT, OUT_F32>), grid, block, 0, st, in, U, out, p); break;
-    case OUT_BF16X2: hipLaunchKernelGGL((map_kernel<InT, OUT_BF16X2>), grid, block, 0, st, in, U, out, p); break;
+    case OUT_F64: hipLaunchKernelGGL((map_kernel<InT, OUT_F64>), grid, block, lds, st, in, U, out, p); break;
+    case OUT_F32: hipLaunchKernelGGL((map_kernel<InT, OUT_F32>), grid, block, lds, st, in, U, out, p); break;
+    case OUT_BF16X2: hipLaunchKernelGGL((map_kernel<InT, OUT_BF16X2>), grid, block, lds, st, in, U, out, p); break;
     default: throw Error(-1, "tensor_map: bad output kind");
   }
   TRG_HIP_CHECK(hipGetLastError());
@@ -331,6 +343,22 @@ void tensor_map(const void *in, int in_kind, const double *U, void *out, int out
   p.ni = int32_t(idim.size);
   p.iso = idim.so;
   p.isu = idim.su;
+  // matrix entries one launch can touch, from its base: stage them in LDS
+  // when the register-held inner dim multiplies the matrix reads
+  p.u_lds = 0;
+  if (U && p.ni > 1) {
+    bool nonneg = idim.su >= 0;
+    int64_t span = 1 + (idim.size - 1) * idim.su;
+    for (int i = outer; i < ndims; ++i) {
+      nonneg = nonneg && dims[i].su >= 0;
+      span += (dims[i].size - 1) * dims[i].su;
+    }
+    for (int j = 0; j < nsum; ++j) {
+      nonneg = nonneg && sums[j].su >= 0;
+      span += (sums[j].size - 1) * sums[j].su;
+    }
+    if (nonneg && span <= MAP_ULDS_MAX) p.u_lds = int32_t(span);
+  }
   const int esz_in = in_kind == IN_F64 ? 8 : 4;
   const int esz_out = out_kind == OUT_F64 ? 8 : (out_kind == OUT_F32 ? 4 : 2);
   for (int64_t o = 0; o < nouter; ++o) {
