@@ -329,7 +329,7 @@ def main():
     achieved = alg_flops_step * a.steps / (join_ms * 1e-3) / 1e12 if join_ms > 0 else None
     peak = PEAK_TFLOPS[a.precision]
     out = {
-        "metric": "4D HOTRG RG-steps/s at Dcut=10 (steady-state step, 1 GPU)",
+        "metric": "4D HOTRG RG-steps/s at Dcut=%d (steady-state step, 1 GPU)" % D,
         "value": steps_per_s,
         "unit": "RG-steps/s",
         "n_gpus": 1,
