@@ -157,31 +157,36 @@ chol_inv_kernel(const double *C, int n, double shift_coef, double *R, double *Ri
 }
 
 // The same factorisation for n <= 128 with both triangles packed in LDS
-// (row i of an upper triangle starts at i n - i (i - 1) / 2): the pivot sums
-// are block reductions, the rows of R and of Rinv are computed by all threads
-// at once (one barrier per row), so no thread runs an O(n^2) chain.
+// (row i of an upper triangle starts at i n - i (i - 1) / 2), right-looking:
+// after row j of R is formed, the trailing triangle is updated by all
+// threads at once (A[p][q] -= R[j][p] R[j][q]); the inverse likewise, from
+// the last row up (X[p][j] -= R[p][k] X[k][j] once row k of X is final).
+// Every element update is independent, so no thread runs a long chain; the
+// four waves take every fourth row of an update, the lanes its columns.
 constexpr int CHOL_PACK_MAX = 128;
 __device__ inline int tri(int i, int j, int n) { return i * n - (i * (i - 1)) / 2 + (j - i); }
 
-__global__ void __launch_bounds__(256)
+constexpr int CHOL_THREADS = 256;
+
+__global__ void __launch_bounds__(CHOL_THREADS)
 chol_inv_packed_kernel(const double *C, int n, double shift_coef, double *Rg, double *Rinv, int *err) {
   extern __shared__ double lds[];
   const int npk = n * (n + 1) / 2;
   double *R = lds, *I = lds + npk;
-  __shared__ double sh[256];
-  __shared__ double shm[256];
+  __shared__ double sh[CHOL_THREADS];
+  __shared__ double shm[CHOL_THREADS];
   __shared__ int dead[CHOL_PACK_MAX];
   __shared__ double piv;
   const int t = threadIdx.x;
   double tr = 0.0, mx = 0.0;
-  for (int i = t; i < n; i += 256) {
+  for (int i = t; i < n; i += CHOL_THREADS) {
     tr += C[i * n + i];
     mx = fmax(mx, C[i * n + i]);
   }
   sh[t] = tr;
   shm[t] = mx;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = CHOL_THREADS / 2; s > 0; s >>= 1) {
     if (t < s) {
       sh[t] += sh[t + s];
       shm[t] = fmax(shm[t], shm[t + s]);
@@ -191,27 +196,18 @@ chol_inv_packed_kernel(const double *C, int n, double shift_coef, double *Rg, do
   const double shift = shift_coef * sh[0];
   const double tol = 1e-26 * (shm[0] + shift);
   __syncthreads();
-  for (int idx = t; idx < n * n; idx += 256) {
+  for (int idx = t; idx < n * n; idx += CHOL_THREADS) {
     const int r = idx / n, c = idx % n;
-    if (r <= c) R[tri(r, c, n)] = C[idx] + (r == c ? shift : 0.0);
+    if (r <= c) {
+      R[tri(r, c, n)] = C[idx] + (r == c ? shift : 0.0);
+      I[tri(r, c, n)] = r == c ? 1.0 : 0.0;
+    }
   }
-  for (int i = t; i < n; i += 256) dead[i] = 0;
+  for (int i = t; i < n; i += CHOL_THREADS) dead[i] = 0;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    // pivot: R[j][j] - sum_{k<j} R[k][j]^2
-    double s2 = 0.0;
-    for (int k = t; k < j; k += 256) {
-      const double v = R[tri(k, j, n)];
-      s2 += v * v;
-    }
-    sh[t] = s2;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (t < s) sh[t] += sh[t + s];
-      __syncthreads();
-    }
     if (t == 0) {
-      double dj = R[tri(j, j, n)] - sh[0];
+      double dj = R[tri(j, j, n)];   // all updates from the rows above applied
       if (!(dj > tol)) {
         if (!isfinite(dj)) *err |= 4;
         dead[j] = 1;
@@ -221,43 +217,35 @@ chol_inv_packed_kernel(const double *C, int n, double shift_coef, double *Rg, do
       R[tri(j, j, n)] = piv;
     }
     __syncthreads();
-    const double rjj = piv;
     const bool dj_dead = dead[j] != 0;
-    for (int i = j + 1 + t; i < n; i += 256) {
-      // four partial sums keep several LDS loads in flight
-      double v0 = R[tri(j, i, n)], v1 = 0.0, v2 = 0.0, v3 = 0.0;
-      int k = 0;
-      for (; k + 4 <= j; k += 4) {
-        v0 -= R[tri(k, j, n)] * R[tri(k, i, n)];
-        v1 -= R[tri(k + 1, j, n)] * R[tri(k + 1, i, n)];
-        v2 -= R[tri(k + 2, j, n)] * R[tri(k + 2, i, n)];
-        v3 -= R[tri(k + 3, j, n)] * R[tri(k + 3, i, n)];
-      }
-      for (; k < j; ++k) v0 -= R[tri(k, j, n)] * R[tri(k, i, n)];
-      const double v = (v0 + v1) + (v2 + v3);
-      R[tri(j, i, n)] = dj_dead ? 0.0 : v / rjj;
+    const double rjj = piv;
+    for (int i = j + 1 + t; i < n; i += CHOL_THREADS) {
+      const int o = tri(j, i, n);
+      R[o] = dj_dead ? 0.0 : R[o] / rjj;
+    }
+    __syncthreads();
+    const int rowj = tri(j, 0, n);   // R[j][q] = R[rowj + q]
+    for (int p = j + 1 + (t >> 6); p < n; p += CHOL_THREADS / 64) {
+      const double rjp = R[rowj + p];
+      const int rowp = tri(p, 0, n);
+      for (int q = p + (t & 63); q < n; q += 64) R[rowp + q] -= rjp * R[rowj + q];
     }
     __syncthreads();
   }
-  // Rinv by rows from the bottom: I[i][j] = (delta_ij - sum_{i<k<=j} R[i][k] I[k][j]) / R[i][i]
-  for (int i = n - 1; i >= 0; --i) {
-    const double rii = R[tri(i, i, n)];
-    const int ri = tri(i, 0, n);   // R[i][k] = R[ri + k]
-    for (int j = i + t; j < n; j += 256) {
-      double v0 = (i == j) ? 1.0 : 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-      int k = i + 1;
-      for (; k + 4 <= j + 1; k += 4) {
-        v0 -= R[ri + k] * I[tri(k, j, n)];
-        v1 -= R[ri + k + 1] * I[tri(k + 1, j, n)];
-        v2 -= R[ri + k + 2] * I[tri(k + 2, j, n)];
-        v3 -= R[ri + k + 3] * I[tri(k + 3, j, n)];
-      }
-      for (; k <= j; ++k) v0 -= R[ri + k] * I[tri(k, j, n)];
-      I[tri(i, j, n)] = ((v0 + v1) + (v2 + v3)) / rii;
+  // inverse: rows of X = R^-1 from the bottom; dead rows of R are unit rows
+  for (int k = n - 1; k >= 0; --k) {
+    const double inv = 1.0 / R[tri(k, k, n)];
+    for (int j = k + t; j < n; j += CHOL_THREADS) I[tri(k, j, n)] *= inv;
+    __syncthreads();
+    const int rowk = tri(k, 0, n);
+    for (int p = t >> 6; p < k; p += CHOL_THREADS / 64) {
+      const int rowp = tri(p, 0, n);
+      const double rpk = R[rowp + k];
+      for (int jj = k + (t & 63); jj < n; jj += 64) I[rowp + jj] -= rpk * I[rowk + jj];
     }
     __syncthreads();
   }
-  for (int idx = t; idx < n * n; idx += 256) {
+  for (int idx = t; idx < n * n; idx += CHOL_THREADS) {
     const int r = idx / n, c = idx % n;
     Rinv[idx] = (r <= c && !dead[c]) ? I[tri(r, c, n)] : 0.0;
     Rg[idx] = (r <= c && !dead[r]) ? R[tri(r, c, n)] : 0.0;
@@ -275,7 +263,7 @@ void launch_chol_inv(const double *C, int n, double shift, double *R, double *Ri
                                         CHOL_PACK_MAX * (CHOL_PACK_MAX + 1) * 8));
       attr = true;
     }
-    hipLaunchKernelGGL(chol_inv_packed_kernel, dim3(1), dim3(256), lds, st, C, n, shift, R, Rinv, err);
+    hipLaunchKernelGGL(chol_inv_packed_kernel, dim3(1), dim3(CHOL_THREADS), lds, st, C, n, shift, R, Rinv, err);
   } else {
     hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, st, C, n, shift, R, Rinv, err);
   }
