@@ -61,6 +61,9 @@ def parse():
     p.add_argument("--serve-k", default="4,10", help="L = 2^k, k uniform in [kmin, kmax]")
     p.add_argument("--serve-precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
     p.add_argument("--serve-budget-gb", type=float, default=200.0)
+    p.add_argument("--tc-bisect", default=None,
+                   help="instead of timing: 'd,dcut,steps,beta_lo,beta_hi,tol' bisection of the transition on the "
+                        "degeneracy indicator X (FP64)")
     p.add_argument("--copy-cal", type=float, default=0.0,
                    help="only copy this many GiB device to device three times (calibration of the "
                         "FETCH_SIZE / WRITE_SIZE counters)")
@@ -252,6 +255,23 @@ def main():
         return
     if a.accuracy:
         print(json.dumps(accuracy(a.accuracy, a.accuracy_variants)), flush=True)
+        return
+    if a.tc_bisect:
+        from paper_1911_12954_amd.scan import bisect_transition, indicator_after
+        d, dcut, steps, blo, bhi, tol = a.tc_bisect.split(",")
+        d, dcut, steps, blo, bhi, tol = int(d), int(dcut), int(steps), float(blo), float(bhi), float(tol)
+        t0 = time.perf_counter()
+
+        def ev(beta):
+            x = indicator_after(beta, d, dcut, steps)
+            progress(f"tc-bisect: beta {beta:.8f} X {x:.6f} at {time.perf_counter() - t0:.1f} s")
+            return x
+
+        b = bisect_transition(d, dcut, blo, bhi, steps, tol, evaluate=ev)
+        print(json.dumps({"metric": "transition bracket from the indicator X (bisection on beta)",
+                          "d": d, "dcut": dcut, "steps": steps, "beta_lo": b.beta_lo, "beta_hi": b.beta_hi,
+                          "T_lo": 1.0 / b.beta_hi, "T_hi": 1.0 / b.beta_lo, "evaluations": b.evaluations,
+                          "seconds": time.perf_counter() - t0}), flush=True)
         return
     if a.serve:
         from paper_1911_12954_amd.serve import Server, TrgBackend

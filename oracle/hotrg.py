@@ -319,6 +319,27 @@ def periodic_trace(T: np.ndarray) -> float:
     return float(np.einsum("".join(ch + ch for ch in L) + "->", T))
 
 
+def indicator_matrix(T: np.ndarray, axis: int = 0) -> np.ndarray:
+    """M[a][a'] = T with its two legs on `axis` open (a backward, a' forward)
+    and every other axis' leg pair joined (traced), as on a lattice that is
+    one site wide in all other directions."""
+    d = T.ndim // 2
+    L = _letters(d)            # lower-case letters: the open pair uses upper case
+    spec = "".join(("YZ" if k == axis else ch + ch) for k, ch in enumerate(L))
+    return np.einsum(spec + "->YZ", T)
+
+
+def indicator_x(T: np.ndarray, axis: int = 0) -> float:
+    """Degeneracy indicator of the largest tensor components (the quantity
+    the paper plots against the HOTRG iteration, Sec. 3.1, Fig. 3, taken from
+    Gu and Wen): X = (Tr M)^2 / Tr(M M), with M the matrix above, i.e. the
+    squared one-site trace over the trace of two sites joined along `axis`.
+    It is 1 for a single dominant component (disordered phase) and 2 for
+    two degenerate ones (Z2 broken)."""
+    M = indicator_matrix(T, axis)
+    return float(np.trace(M) ** 2 / np.trace(M @ M))
+
+
 @dataclass
 class RunResult:
     ln_z_per_site: float

@@ -6,4 +6,5 @@ The computation lives in the HIP library ``libtrg.so`` (C-ABI declared in
 """
 from .trg import (Context, TrgError, trg_atrg_step, trg_eigh, trg_footprint_bytes, trg_free_energy,  # noqa: F401
                   trg_gemm, trg_gemm_tile, trg_hotrg_step, trg_hotrg_step_batch, trg_impure_energy,
-                  trg_impure_magnetization, trg_init_factors, trg_init_ising, trg_init_tensor, trg_run)
+                  trg_impure_magnetization, trg_indicator_x, trg_init_factors, trg_init_ising, trg_init_tensor,
+                  trg_resident_bytes, trg_run, trg_share_workspace, trg_workspace_bytes)

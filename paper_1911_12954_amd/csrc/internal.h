@@ -62,6 +62,9 @@ int norm_blocks();
 void scale_by_inverse(double *x, int64_t n, const double *scal, double factor, hipStream_t st);
 
 // traces: out[j] = sum_{x_nu} X_j[x, x, y, y, ...] for up to 3 tensors
+// {Tr M, Tr(M M)} into out[0..1] for M[a][a'] = T with the legs of `axis`
+// open and every other axis' leg pair traced (M: dims[axis]^2 workspace)
+void indicator_traces(const double *T, const int *dims, int d, int axis, double *M, double *out, hipStream_t st);
 void periodic_traces(const double *const *X, int count, const int *dims, int d, double *out,
                      hipStream_t st);
 

@@ -468,6 +468,83 @@ void periodic_traces(const double *const *X, int count, const int *dims, int d, 
   TRG_HIP_CHECK(hipGetLastError());
 }
 
+namespace {
+
+// Degeneracy indicator: M[a][a'] = T with the legs of `axis` open and every
+// other axis' pair traced (one workgroup per entry, fixed reduction tree),
+// then out = {Tr M, Tr(M M)} from one workgroup.
+struct IndicatorParams {
+  int n;                  // dims[axis]
+  int64_t s0, s1;         // strides of the backward / forward leg of axis
+  int nother;
+  int odims[3];
+  int64_t odiag[3];       // stride of the diagonal of each other axis
+};
+
+__global__ void __launch_bounds__(256) indicator_matrix_kernel(const double *T, IndicatorParams p, double *M) {
+  __shared__ double sh[256];
+  const int a = blockIdx.x / p.n, a2 = blockIdx.x % p.n;
+  int64_t total = 1;
+  for (int b = 0; b < p.nother; ++b) total *= p.odims[b];
+  const double *base = T + int64_t(a) * p.s0 + int64_t(a2) * p.s1;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < total; i += 256) {
+    int64_t q = i, off = 0;
+    for (int b = p.nother - 1; b >= 0; --b) {
+      off += (q % p.odims[b]) * p.odiag[b];
+      q /= p.odims[b];
+    }
+    s += base[off];
+  }
+  const double r = block_sum(s, sh);
+  if (threadIdx.x == 0) M[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(256) indicator_reduce_kernel(const double *M, int n, double *out) {
+  __shared__ double sh[256];
+  double tr = 0.0, tr2 = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) tr += M[i * n + i];
+  for (int64_t ij = threadIdx.x; ij < int64_t(n) * n; ij += 256) {
+    const int i = int(ij / n), j = int(ij % n);
+    tr2 += M[i * n + j] * M[j * n + i];
+  }
+  const double a = block_sum(tr, sh);
+  __syncthreads();
+  const double b = block_sum(tr2, sh);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+}  // namespace
+
+void indicator_traces(const double *T, const int *dims, int d, int axis, double *M, double *out, hipStream_t st) {
+  TRG_REQUIRE(d >= 1 && d <= 4 && axis >= 0 && axis < d, "indicator: bad arguments");
+  int64_t stride[8];
+  int64_t s = 1;
+  for (int l = 2 * d - 1; l >= 0; --l) {
+    stride[l] = s;
+    s *= dims[l / 2];
+  }
+  IndicatorParams p{};
+  p.n = dims[axis];
+  p.s0 = stride[2 * axis];
+  p.s1 = stride[2 * axis + 1];
+  for (int b = 0; b < d; ++b) {
+    if (b == axis) continue;
+    p.odims[p.nother] = dims[b];
+    p.odiag[p.nother] = stride[2 * b] + stride[2 * b + 1];
+    ++p.nother;
+  }
+  const int64_t nn = int64_t(p.n) * p.n;
+  TRG_REQUIRE(nn < (int64_t(1) << 31), "indicator: leg too large");
+  hipLaunchKernelGGL(indicator_matrix_kernel, dim3(uint32_t(nn)), dim3(256), 0, st, T, p, M);
+  TRG_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(indicator_reduce_kernel, dim3(1), dim3(256), 0, st, M, p.n, out);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
 void ising_init(double *T, double *SE, double *SM, int d, double beta, double h, hipStream_t st) {
   const int n = 1 << (2 * d);
   hipLaunchKernelGGL(ising_kernel, dim3((n + 255) / 256), dim3(256), 0, st, T, SE, SM, d, beta, h);

@@ -129,6 +129,11 @@ class Context:
     def impure_magnetization(self) -> float:
         return self._dbl(_lib().trg_impure_magnetization)
 
+    def indicator_x(self, axis: int = 0) -> float:
+        out = C.c_double()
+        _err(_lib().trg_indicator_x(self.handle, int(axis), C.byref(out)), self.handle)
+        return out.value
+
     def accumulator(self) -> float:
         return self._dbl(_lib().trg_accumulator)
 
@@ -290,6 +295,10 @@ def trg_footprint_bytes(d, dcut, precision="fp64", method="hotrg", impure=()) ->
     for x in impure:
         bits |= {"E": L.TRG_IMPURE_E, "M": L.TRG_IMPURE_M}[x]
     return int(_lib().trg_footprint_bytes(d, dcut, PRECISIONS[precision], METHODS[method], bits))
+
+
+def trg_indicator_x(ctx: Context, axis: int = 0) -> float:
+    return ctx.indicator_x(axis)
 
 
 def trg_resident_bytes(d, dcut, precision="fp64", method="hotrg", impure=()) -> int:

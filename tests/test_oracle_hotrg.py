@@ -251,3 +251,63 @@ def test_sampled_blocks_equal_the_full_contraction():
     Ub[2] = U[2][:, :, [3]]; Uf[2] = U[2][:, :, [0]]
     blk = hotrg.coarse_grain(A, A, Ub, 0, x0s=[1], x2s=[0], U_forward=Uf)
     assert np.allclose(blk[0, 0, 0, 0, 0, 0], full[1, 0, 2, 1, 3, 0], atol=1e-13)
+
+
+def test_indicator_x_pins():
+    """X of the fixed-point tensors: 1 for one dominant component, 2 for the
+    two degenerate components of the ordered phase, n for n; the two-site
+    trace in the denominator equals the explicit contraction of two copies
+    of T joined along the axis."""
+    from oracle.hotrg import indicator_matrix, indicator_x
+    for d in (2, 3, 4):
+        for n in (1, 2, 3):
+            T = np.zeros((n,) * (2 * d))
+            for s in range(n):
+                T[(s,) * (2 * d)] = 1.0
+            assert indicator_x(T) == pytest.approx(n, rel=1e-14)
+    rng = np.random.default_rng(5)
+    T = rng.standard_normal((3, 3, 2, 2, 4, 4))
+    M = indicator_matrix(T, 0)
+    two_site = np.einsum("abyyzz,bavvww->", T, T)
+    one_site = np.einsum("aayyzz->", T)
+    assert np.trace(M @ M) == pytest.approx(two_site, rel=1e-13)
+    assert indicator_x(T, 0) == pytest.approx(one_site ** 2 / two_site, rel=1e-13)
+    M1 = indicator_matrix(T, 1)
+    assert indicator_x(T, 1) == pytest.approx(np.trace(M1) ** 2 / np.einsum("xxabzz,yybaww->", T, T), rel=1e-13)
+
+
+def test_indicator_x_phases():
+    """After many coarse-graining steps X tends to 1 in the disordered phase
+    (high temperature) and to 2 in the ordered one at h = 0 (2D, where
+    beta_c = ln(1 + sqrt 2)/2 = 0.4407)."""
+    from oracle.hotrg import hotrg_step, indicator_x
+    from oracle.ising import site_tensors
+    for beta, want in ((0.30, 1.0), (0.60, 2.0)):
+        T = site_tensors(beta, 0.0, 2)[0]
+        T = T / np.linalg.norm(T)
+        for n in range(30):
+            T, _, c, _ = hotrg_step(T, n % 2, 8, [], None, "fro", None)
+        assert indicator_x(T) == pytest.approx(want, abs=1e-3)
+
+
+def test_indicator_bisection_finds_onsager_transition():
+    """2D, Dcut 8: bisection on X after 30 steps brackets the exact critical
+    coupling ln(1 + sqrt 2)/2 = 0.440687 within the truncation error (the
+    bisection driver of the package, fed by the oracle)."""
+    import math
+    from oracle.hotrg import hotrg_step, indicator_x
+    from oracle.ising import site_tensors
+    from paper_1911_12954_amd.scan import bisect_transition
+
+    def x_after(beta):
+        T = site_tensors(beta, 0.0, 2)[0]
+        T = T / np.linalg.norm(T)
+        for n in range(30):
+            T, _, _, _ = hotrg_step(T, n % 2, 8, [], None, "fro", None)
+        return indicator_x(T)
+
+    b = bisect_transition(2, 8, 0.40, 0.48, 30, 1e-4, evaluate=x_after)
+    exact = 0.5 * math.log(1.0 + math.sqrt(2.0))
+    assert b.beta_hi - b.beta_lo <= 1e-4
+    # measured: [0.440732, 0.440742] against 0.440687 (Dcut 4: 0.44601, 12: 0.44067)
+    assert abs(0.5 * (b.beta_lo + b.beta_hi) - exact) < 3e-4 * exact
