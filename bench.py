@@ -64,6 +64,10 @@ def parse():
     p.add_argument("--tc-bisect", default=None,
                    help="instead of timing: 'd,dcut,steps,beta_lo,beta_hi,tol' bisection of the transition on the "
                         "degeneracy indicator X (FP64)")
+    p.add_argument("--atrg-study", default=None,
+                   help="instead of timing: 'dcuts;pq_dcut;hotrg_dcut' (e.g. '8,12,16,20,24;16;8'): ATRG f at "
+                        "T = 6.65035, L = 1024 for each Dcut, the RSVD (p, q) study at pq_dcut and the ratio to "
+                        "HOTRG at hotrg_dcut (FP64)")
     p.add_argument("--copy-cal", type=float, default=0.0,
                    help="only copy this many GiB device to device three times (calibration of the "
                         "FETCH_SIZE / WRITE_SIZE counters)")
@@ -110,6 +114,41 @@ def accuracy(spec, variants):
             continue
         out[f"rel_err_{key}"] = {k: abs(res[key][k] - ref[k]) / max(abs(ref[k]), 1e-300) for k in ("f", "E", "M")}
         out[f"abs_err_{key}"] = {k: abs(res[key][k] - ref[k]) for k in ("f", "E", "M")}
+    return out
+
+
+def atrg_study(spec):
+    """ATRG free energy at the paper's comparison temperature T = 6.65035 on
+    the 1024^4 lattice for several Dcut (p = 4 Dcut, q = 2 Dcut), the RSVD
+    (p, q) dependence at one Dcut, and the ratio to HOTRG at another."""
+    import torch
+    from paper_1911_12954_amd import trg_init_ising
+    dcuts, pq_dcut, hdcut = spec.split(";")
+    dcuts = [int(x) for x in dcuts.split(",")]
+    pq_dcut, hdcut = int(pq_dcut), int(hdcut)
+    beta, L = 1.0 / 6.65035, 1024
+
+    def run(method, D, p=0, q=0):
+        t0 = time.perf_counter()
+        ctx = trg_init_ising(beta, 0.0, 4, dcut=D, precision="fp64", method=method, rsvd_p=p, rsvd_q=q)
+        ctx.run(L)
+        f = ctx.free_energy()
+        ctx.close()
+        torch.cuda.empty_cache()
+        dt = time.perf_counter() - t0
+        progress(f"atrg-study: {method} Dcut {D} p {p} q {q}: lnZ/V {f:.12f} in {dt:.1f} s")
+        return f, dt
+
+    f_h, t_h = run("hotrg", hdcut)
+    out = {"workload": "4D Ising, T = 6.65035 (beta = %.8f), h = 0, L = 1024 (40 steps), FP64" % beta,
+           "hotrg": {"dcut": hdcut, "lnZ_per_site": f_h, "seconds": t_h}, "atrg": [], "pq": []}
+    for D in dcuts:
+        f, dt = run("atrg", D)
+        out["atrg"].append({"dcut": D, "p": 4 * D, "q": 2 * D, "lnZ_per_site": f, "seconds": dt,
+                            "ratio_to_hotrg": f / f_h})
+    for p, q in ((2 * pq_dcut, pq_dcut), (4 * pq_dcut, 2 * pq_dcut), (6 * pq_dcut, 3 * pq_dcut)):
+        f, dt = run("atrg", pq_dcut, p, q)
+        out["pq"].append({"dcut": pq_dcut, "p": p, "q": q, "lnZ_per_site": f, "seconds": dt})
     return out
 
 
@@ -255,6 +294,9 @@ def main():
         return
     if a.accuracy:
         print(json.dumps(accuracy(a.accuracy, a.accuracy_variants)), flush=True)
+        return
+    if a.atrg_study:
+        print(json.dumps(atrg_study(a.atrg_study)), flush=True)
         return
     if a.tc_bisect:
         from paper_1911_12954_amd.scan import bisect_transition, indicator_after
