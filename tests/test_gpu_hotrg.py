@@ -158,22 +158,29 @@ def test_field_reversal_symmetry():
     assert abs(a["M"] + b["M"]) < 1e-12
 
 
-@pytest.mark.parametrize("precision,tol_f", [("fp32", 1e-6), ("bf16x3", 2e-5)])
-def test_mixed_precision_error_dcut8(precision, tol_f):
+@pytest.mark.parametrize("precision,n64,tol_f,tol_E,tol_M", [("fp32", 0, 1e-6, 1e-6, 1e-3),
+                                                           ("bf16x3", 0, 2e-5, 1e-3, 1e-1),
+                                                           ("bf16x3", 8, 1e-6, 1e-3, 1e-1)])
+def test_mixed_precision_error_dcut8(precision, n64, tol_f, tol_E, tol_M):
     """4D, Dcut = 8, L = 16, beta = 0.1497, h = 1e-5: f, E, M of the mixed
-    joins against the GPU FP64 path (errors printed; f gated at the stated
-    tolerance, E and M reported: near T_c the field response amplifies
-    rounding, see the measurements in the design notes)."""
+    joins (optionally with the first n64 steps in FP64) against the GPU FP64
+    path.  The FP32 join (FP64 sums of 128-product groups) meets 1e-6 on f
+    and E; BF16x3 meets it on f with 8 leading FP64 steps; M near T_c is
+    amplified by the field response (errors printed)."""
     need_gpu()
-    announce("mixed dcut8", precision)
+    from paper_1911_12954_amd import trg_init_ising
+    announce("mixed dcut8", precision, n64)
     ref = _gpu_run(0.1497, 1e-5, 4, 8, 16)
-    got = _gpu_run(0.1497, 1e-5, 4, 8, 16, precision=precision)
+    ctx = trg_init_ising(0.1497, 1e-5, 4, dcut=8, impure=("E", "M"), precision=precision, fp64_steps=n64)
+    ctx.run(16)
+    got = {"f": ctx.free_energy(), "E": ctx.impure_energy(), "M": ctx.impure_magnetization()}
+    ctx.close()
     ef = abs(got["f"] - ref["f"]) / abs(ref["f"])
     eE = abs(got["E"] - ref["E"]) / abs(ref["E"])
     eM = abs(got["M"] - ref["M"]) / abs(ref["M"])
-    print(f"[mixed {precision} dcut8] rel err f {ef:.3e} E {eE:.3e} M {eM:.3e}", flush=True)
+    print(f"[mixed {precision} fp64x{n64} dcut8] rel err f {ef:.3e} E {eE:.3e} M {eM:.3e}", flush=True)
     assert ef < tol_f
-    assert eE < 1e-3 and eM < 1e-1
+    assert eE < tol_E and eM < tol_M
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
