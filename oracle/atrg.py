@@ -38,6 +38,31 @@ each choice below is listed in the design doc):
 * New pieces G'[b_mu, B_perp, l] and H'[l, F_perp, f_mu]; normalisation
   c = ||G' H'||_F = sqrt(Tr[(G'^T G')(H' H'^T)]), both pieces scaled by
   c^{-1/2}, acc += 2^{-n} ln c.  Tr T = sum_l sum_b G'[b, l] H'[l, b].
+* Impure tensors (Sec. 3.2 applies the impure-tensor method within ATRG
+  without spelling it out).  An impurity is kept as its own pair of pieces,
+  S = sum_m G_S[b, m] H_S[m, f].  Initially G_S is the pure backward piece
+  and H_S carries the impurity: S_M exactly, and the energy impurity with the
+  derivative of each bond weight put on the bond's forward end
+  (sum_k 2 W'[s, k] W[s', k] = d e^{beta s s'} / d beta), so that
+  -Tr S_E / Tr T is again <H>/V.  A step forms C(S, T) + C(T, S) over 2c:
+  - impurity on the lower site: the two-site middle matrix
+    M_1[(m, b_perp), (f_perp, kB)] = sum_j H_S[m, f_perp, j] Ut[j, b_perp, kB]
+    gets its own partial SVD of rank Dcut (the same randomized SVD as the
+    pure swap), M_1 ~ X_1 sigma_1 Y_1, and the pieces G_S X_1 sqrt(sigma_1),
+    sqrt(sigma_1) Y_1 Vt;
+  - impurity on the upper site: M_2[(kA, b_perp), (f_perp, m)] =
+    sum_j Vt[kA, f_perp, j] G_S[j, b_perp, m] likewise, pieces
+    Ut X_2 sqrt(sigma_2) and sqrt(sigma_2) Y_2 H_S;
+  - the two terms side by side (bond 2 Dcut), the pure step's HOSVD
+    isometries on the backward and the forward legs, c^{-1/2} on each piece
+    and the 1/2 on the forward one.
+  Only the isometries are shared with the pure tensor: projecting the
+  impure middle matrices on the pure swap's singular vectors instead loses
+  about 2 % of E in 2D at Dcut = 16 (their dominant directions differ).
+  The trial matrix of the impurity SVDs is drawn like the pure one with the
+  third counter word 1 + 2 kind + term (kind 0 energy, 1 magnetization;
+  term 0 lower site, 1 upper site).  With nothing truncated every SVD is
+  exact and E, M are exact.
 * RSVD (Halko et al. as in Erichson et al.): Q = orth(M Omega); q times
   Z = orth(M^T Q), Q = orth(M Z); then the SVD of Q^T M.  Omega has
   Dcut + p columns; entry (i, c) of step n comes from Philox4x32-10 with key
@@ -54,7 +79,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import hotrg
-from .ising import bond_split
+from .ising import bond_split, bond_split_dbeta
 
 # ------------------------------------------------------------------ Philox ---
 PHILOX_M0, PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
@@ -79,12 +104,12 @@ def philox4x32_10(counter, key):
     return c
 
 
-def philox4x32_10_vec(ctr0, ctr1, key):
+def philox4x32_10_vec(ctr0, ctr1, key, ctr2=0):
     """Vectorised Philox4x32-10 over arrays of the first two counter words
-    (the last two are zero); returns the first two output words."""
+    (the third is ctr2, the last zero); returns the first two output words."""
     c0 = np.asarray(ctr0, dtype=np.uint64) & MASK32
     c1 = np.asarray(ctr1, dtype=np.uint64) & MASK32
-    c2 = np.zeros_like(c0)
+    c2 = np.full_like(c0, int(ctr2) & MASK32)
     c3 = np.zeros_like(c0)
     k0, k1 = np.uint64(key[0] & MASK32), np.uint64(key[1] & MASK32)
     m0, m1 = np.uint64(PHILOX_M0), np.uint64(PHILOX_M1)
@@ -100,10 +125,11 @@ def philox4x32_10_vec(ctr0, ctr1, key):
     return c0, c1
 
 
-def trial_matrix(rows: int, cols: int, step: int, seed: int) -> np.ndarray:
-    """Gaussian trial matrix Omega[rows, cols] of ATRG step `step`."""
+def trial_matrix(rows: int, cols: int, step: int, seed: int, stream: int = 0) -> np.ndarray:
+    """Gaussian trial matrix Omega[rows, cols] of ATRG step `step` (stream 0:
+    the pure swap; stream s > 0: counter word 2 = s, the impurity SVDs)."""
     e = np.arange(rows * cols, dtype=np.uint64)
-    w0, w1 = philox4x32_10_vec(e, np.full_like(e, step), (seed & MASK32, (seed >> 32) & MASK32))
+    w0, w1 = philox4x32_10_vec(e, np.full_like(e, step), (seed & MASK32, (seed >> 32) & MASK32), stream)
     u1 = (w0.astype(np.float64) + 0.5) / 4294967296.0
     u2 = (w1.astype(np.float64) + 0.5) / 4294967296.0
     z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
@@ -145,6 +171,32 @@ def ising_factors(beta: float, h: float, d: int) -> Factors:
         U[..., row] = u
     V = np.moveaxis(U, -1, 0).copy()
     return Factors(U, np.ones(2), V)
+
+
+def ising_impurity_pieces(beta: float, h: float, d: int):
+    """Forward pieces H_E, H_M [sigma, f...] of the energy and magnetization
+    impurities on the backward piece of ising_factors: S = sum_sigma
+    u_sigma[b] H_S[sigma, f], with H_M = sigma v_sigma and
+    H_E = e^{beta h sigma/2} (h sigma prod_nu W[sigma, f_nu]
+          + sum_nu 2 W'[sigma, f_nu] prod_{nu' != nu} W[sigma, f_nu'])."""
+    W = bond_split(beta)
+    dW = bond_split_dbeta(beta) if beta > 0 else np.zeros((2, 2))
+    HE = np.zeros((2,) + (2,) * d)
+    HM = np.zeros((2,) + (2,) * d)
+    for row, spin in enumerate((1.0, -1.0)):
+        pref = math.exp(0.5 * beta * h * spin)
+        v = np.array(pref)
+        for _ in range(d):
+            v = np.multiply.outer(v, W[row])
+        HM[row] = spin * v
+        e = h * spin * v
+        for nu in range(d):
+            t = np.array(pref)
+            for a in range(d):
+                t = np.multiply.outer(t, 2.0 * dW[row] if a == nu else W[row])
+            e = e + t
+        HE[row] = e
+    return HE, HM
 
 
 def canonical(G: np.ndarray, H: np.ndarray, dcut: int) -> Factors:
@@ -347,9 +399,82 @@ class AtrgStep:
     axes: list = field(default_factory=list)
 
 
-def atrg_step(F: Factors, mu: int, dcut: int, p: int, q: int, step: int, seed: int, dense_swap=False):
+def middle_svd(A: np.ndarray, B: np.ndarray, dcut: int, p: int, q: int, step: int, seed: int, stream: int,
+               dense: bool = False):
+    """Rank-dcut partial SVD of M[(a, b), (f, c)] = sum_j A[a, f, j] B[j, b, c]
+    (A: [ra, nperp, dmu], B: [dmu, nperp, cb]) by the randomized SVD of the
+    pure swap (trial matrix of the given stream), or densely."""
+    ra, nperp, dmu = A.shape
+    cb = B.shape[2]
+    nr, nc = ra * nperp, nperp * cb
+
+    def mz(Z):          # M Z, Z rows (f, c)
+        t = np.einsum("afj,fcx->ajcx", A, Z.reshape(nperp, cb, -1), optimize=True)
+        return np.einsum("ajcx,jbc->abx", t, B, optimize=True).reshape(nr, -1)
+
+    def mtq(Q):         # M^T Q, Q rows (a, b)
+        t = np.einsum("jbc,abx->jcax", B, Q.reshape(ra, nperp, -1), optimize=True)
+        return np.einsum("afj,jcax->fcx", A, t, optimize=True).reshape(nc, -1)
+
+    if dense:
+        M = np.einsum("afj,jbc->abfc", A, B).reshape(nr, nc)
+        X, sig, Y = np.linalg.svd(M, full_matrices=False)
+        r = min(dcut, len(sig))
+        return X[:, :r], sig[:r], Y[:r]
+    r = min(dcut + p, nr, nc)
+    Q, _ = np.linalg.qr(mz(trial_matrix(nc, r, step, seed, stream)))
+    for _ in range(q):
+        Z, _ = np.linalg.qr(mtq(Q))
+        Q, _ = np.linalg.qr(mz(Z))
+    Wb, sig, Zt = np.linalg.svd(mtq(Q).T, full_matrices=False)
+    keep = min(dcut, len(sig))
+    return Q @ Wb[:, :keep], sig[:keep], Zt[:keep]
+
+
+def impurity_pieces_step(F: Factors, mu: int, GS: np.ndarray, HS: np.ndarray, kind: int, dcut: int, p: int,
+                         q: int, step: int, seed: int, dense: bool = False):
+    """The impurity's two-site pieces before the isometries: backward
+    [b^A..., b^B_perp..., m'] and forward [m', f^A_perp..., f^B...], m' =
+    (lower-site term, upper-site term)."""
+    d = F.d
+    k = F.s.shape[0]
+    rs = np.sqrt(F.s)
+    dims = F.dims()
+    perp = tuple(dims[a] for a in range(d) if a != mu)
+    nperp = int(np.prod(perp))
+    dmu = dims[mu]
+    m = GS.shape[-1]
+    Ut = F.U * rs                                           # [b..., k]
+    Vt = F.V * rs.reshape((-1,) + (1,) * d)                 # [k, f...]
+    Utp = np.moveaxis(Ut, mu, 0).reshape(dmu, nperp, k)     # [j, b_perp, kB]
+    Vtp = np.moveaxis(Vt, 1 + mu, -1).reshape(k, nperp, dmu)  # [kA, f_perp, j]
+    # lower site: M_1 = H_S (x)_j Ut
+    HSp = np.moveaxis(HS, 1 + mu, -1).reshape(m, nperp, dmu)
+    X1, s1, Y1 = middle_svd(HSp, Utp, dcut, p, q, step, seed, 1 + 2 * kind, dense)
+    r1 = len(s1)
+    X1s = (X1 * np.sqrt(s1)).reshape((m,) + perp + (r1,))
+    Y1s = (np.sqrt(s1)[:, None] * Y1).reshape((r1,) + perp + (k,))
+    G1 = np.tensordot(GS, X1s, axes=([d], [0]))
+    H1 = np.tensordot(Y1s, Vt, axes=([d], [0]))
+    # upper site: M_2 = Vt (x)_j G_S
+    GSp = np.moveaxis(GS, mu, 0).reshape(dmu, nperp, m)
+    X2, s2, Y2 = middle_svd(Vtp, GSp, dcut, p, q, step, seed, 2 + 2 * kind, dense)
+    r2 = len(s2)
+    X2s = (X2 * np.sqrt(s2)).reshape((k,) + perp + (r2,))
+    Y2s = (np.sqrt(s2)[:, None] * Y2).reshape((r2,) + perp + (m,))
+    G2 = np.tensordot(Ut, X2s, axes=([d], [0]))
+    H2 = np.tensordot(Y2s, HS, axes=([d], [0]))
+    return np.concatenate([G1, G2], axis=-1), 0.5 * np.concatenate([H1, H2], axis=0)
+
+
+def atrg_step(F: Factors, mu: int, dcut: int, p: int, q: int, step: int, seed: int, dense_swap=False,
+              imps=None):
     """One ATRG step along mu on canonical factors F.  Returns the new pieces
-    (G', H') normalised, c, and the step record."""
+    (G', H') normalised, c, and the step record; given a list of impurity
+    piece pairs ``imps`` (G_S, H_S) the return has a fifth entry, their new
+    pairs."""
+    with_imps = imps is not None
+    imps = imps or []
     d = F.d
     X, sig, Y = rsvd_swap(F, mu, dcut, p, q, step, seed, dense=dense_swap)
     G, H = _pieces(F, X, sig, Y, mu)
@@ -360,9 +485,17 @@ def atrg_step(F: Factors, mu: int, dcut: int, p: int, q: int, step: int, seed: i
     GtG = Gn.reshape(-1, r).T @ Gn.reshape(-1, r)
     HHt = Hn.reshape(r, -1) @ Hn.reshape(r, -1).T
     c = math.sqrt(float(np.sum(GtG * HHt)))
+    rec = AtrgStep(step, mu, math.log(c), sig, F.s, choices)
+    new_imps = []
+    for kind, (GS, HS) in enumerate(imps):
+        Gc, Hc = impurity_pieces_step(F, mu, GS, HS, kind, dcut, p, q, step, seed, dense_swap)
+        GSn, HSn = contract(Gc, Hc, P, mu, d)
+        new_imps.append((GSn / math.sqrt(c), HSn / math.sqrt(c)))
     Gn = Gn / math.sqrt(c)
     Hn = Hn / math.sqrt(c)
-    return Gn, Hn, c, AtrgStep(step, mu, math.log(c), sig, F.s, choices)
+    if not with_imps:
+        return Gn, Hn, c, rec
+    return Gn, Hn, c, rec, new_imps
 
 
 def periodic_trace(G: np.ndarray, H: np.ndarray) -> float:
@@ -377,11 +510,14 @@ class AtrgResult:
     acc: float
     trace: float
     steps: list
+    energy: float = float("nan")
+    magnetization: float = float("nan")
 
 
 def run(beta: float, h: float, d: int, dcut: int, L: int, p=None, q=None, seed: int = 0,
-        dense_swap: bool = False) -> AtrgResult:
-    """ATRG on the periodic L^d lattice: d*m steps along (n-1) mod d."""
+        dense_swap: bool = False, impure: bool = False) -> AtrgResult:
+    """ATRG on the periodic L^d lattice: d*m steps along (n-1) mod d.  With
+    ``impure`` (beta > 0) also E = -Tr S_E / Tr T and M = Tr S_M / Tr T."""
     m = int(round(math.log2(L)))
     if 2 ** m != L or m < 1:
         raise ValueError("L must be a power of two >= 2")
@@ -392,13 +528,21 @@ def run(beta: float, h: float, d: int, dcut: int, L: int, p=None, q=None, seed: 
     r = G.shape[-1]
     c0 = math.sqrt(float(np.sum((G.reshape(-1, r).T @ G.reshape(-1, r)) * (H.reshape(r, -1) @ H.reshape(r, -1).T))))
     G, H = G / math.sqrt(c0), H / math.sqrt(c0)
+    imps = [(G.copy(), x / math.sqrt(c0)) for x in ising_impurity_pieces(beta, h, d)] if impure else None
     acc = math.log(c0)
     steps = []
     for n in range(1, d * m + 1):
         mu = (n - 1) % d
         F = canonical(G, H, dcut)
-        G, H, c, rec = atrg_step(F, mu, dcut, p, q, n, seed, dense_swap)
+        if impure:
+            G, H, c, rec, imps = atrg_step(F, mu, dcut, p, q, n, seed, dense_swap, imps=imps)
+        else:
+            G, H, c, rec = atrg_step(F, mu, dcut, p, q, n, seed, dense_swap)
         acc += 2.0 ** (-n) * math.log(c)
         steps.append(rec)
     tr = periodic_trace(G, H)
-    return AtrgResult(acc + 2.0 ** (-(d * m)) * math.log(tr), acc, tr, steps)
+    res = AtrgResult(acc + 2.0 ** (-(d * m)) * math.log(tr), acc, tr, steps)
+    if impure:
+        res.energy = -periodic_trace(*imps[0]) / tr
+        res.magnetization = periodic_trace(*imps[1]) / tr
+    return res

@@ -105,3 +105,63 @@ def test_beta_zero_and_field_symmetry():
 def test_2d_large_lattice_approaches_onsager():
     r = atrg.run(0.2, 0.0, 2, 16, 2 ** 20)
     assert abs(r.ln_z_per_site - exact.onsager_lnz(0.2)) < 1e-7
+
+
+# ------------------------------------------------------------ impure tensors ---
+def test_impurity_pieces_reproduce_the_site_sums():
+    """S_M = sum_s s (...) exactly; the forward-carried energy impurity has
+    every bond derivative on the forward end: with each forward leg closed
+    on its own bond partner it sums the bond energies of the site."""
+    from oracle import ising
+    beta, h, d = 0.3, 0.1, 2
+    F = atrg.ising_factors(beta, h, d)
+    HE, HM = atrg.ising_impurity_pieces(beta, h, d)
+    order = [x for a in range(d) for x in (a, d + a)]
+    SM = np.transpose(np.tensordot(F.U, HM, axes=([d], [0])), order)
+    assert np.allclose(SM, ising.site_tensors(beta, h, d)[1], atol=1e-14)
+    # one site with a closed loop on every axis: T[b, f] with b_nu = f_nu is
+    # the single-site periodic lattice, sum_s e^{beta h s} prod_nu e^{beta}
+    SE = np.tensordot(F.U, HE, axes=([d], [0]))
+    T = F.dense()
+    idx = np.arange(2)
+    tr = lambda X: float(sum(X[i, j, i, j] for i in idx for j in idx))
+    z = 2.0 * math.cosh(beta * h) * math.exp(d * beta)
+    assert abs(tr(T) - z) < 1e-12 * z
+    # d/dbeta of the same sum: the bonds give d e^{d beta} / dbeta, the field h
+    dz = 2.0 * math.exp(d * beta) * (d * math.cosh(beta * h) + h * math.sinh(beta * h))
+    assert abs(tr(SE) - dz) < 1e-12 * dz
+
+
+@pytest.mark.parametrize("beta,h,d,L", [(0.3, 0.05, 2, 4), (0.4407, 0.0, 2, 4), (0.2, -0.1, 2, 4),
+                                        (0.25, 0.05, 3, 2)])
+def test_impure_untruncated_equals_brute_force(beta, h, d, L):
+    """Nothing truncated (dense SVDs): E and M of the impurity pieces equal
+    the spin sums."""
+    r = atrg.run(beta, h, d, 4096, L, dense_swap=True, impure=True)
+    lnz, E, M = exact.brute_force(beta, h, d, L)
+    assert abs(r.ln_z_per_site - lnz) < 1e-12
+    assert abs(r.energy - E) < 1e-12 * abs(E)
+    assert abs(r.magnetization - M) < 1e-12 * max(abs(M), 1.0)
+
+
+def test_impure_randomized_untruncated_equals_brute_force():
+    """The randomized partial SVDs (small p, q) with rank covering the whole
+    space are exact too."""
+    r = atrg.run(0.3, 0.05, 2, 64, 4, p=8, q=1, impure=True)
+    lnz, E, M = exact.brute_force(0.3, 0.05, 2, 4)
+    assert abs(r.energy - E) < 1e-11 * abs(E) and abs(r.magnetization - M) < 1e-11 * abs(M)
+
+
+def test_impurities_leave_the_pure_run_unchanged():
+    a = atrg.run(0.3, 0.05, 2, 8, 16, p=8, q=2)
+    b = atrg.run(0.3, 0.05, 2, 8, 16, p=8, q=2, impure=True)
+    assert a.ln_z_per_site == b.ln_z_per_site
+
+
+def test_impure_truncated_2d_energy_near_onsager():
+    """2D, K = 0.3 (disordered side), Dcut = 8, L = 2^10: E within 1e-2 of
+    Onsager's energy, M = 0 by symmetry at h = 0."""
+    K = 0.3
+    r = atrg.run(K, 0.0, 2, 8, 2 ** 10, p=16, q=4, impure=True)
+    assert abs(r.energy - exact.onsager_energy(K)) < 1e-2 * abs(exact.onsager_energy(K))
+    assert abs(r.magnetization) < 1e-10
