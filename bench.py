@@ -71,12 +71,68 @@ def parse():
     p.add_argument("--copy-cal", type=float, default=0.0,
                    help="only copy this many GiB device to device three times (calibration of the "
                         "FETCH_SIZE / WRITE_SIZE counters)")
+    p.add_argument("--vendor-gemm", default=None,
+                   help="instead of timing the step: 'M,N,K' (e.g. '30208,100096,100000', the full-slice join "
+                        "of the Dcut = 10 step): the BF16x3 join kernel against one plain BF16 torch.matmul "
+                        "(hipBLASLt) of the same shape, in MFMA TFLOP/s issued")
     p.add_argument("--accuracy", default=None,
                    help="instead of timing: run 'dcut,L,beta,h' in FP64, FP32 and BF16x3 with impure E and M "
                         "and print the relative errors of f, E, M against the FP64 path")
     p.add_argument("--accuracy-variants", default="fp32:0,bf16x3:0",
                    help="precision:fp64_steps pairs compared with the FP64 path")
     return p.parse_args()
+
+
+def vendor_gemm(spec):
+    """Issue rate of the BF16x3 join kernel (three BF16 products per
+    multiply-add) next to a plain BF16 GEMM of the vendor library at one
+    shape: both run the same MFMA instruction class, so the two TFLOP/s
+    figures say how close the hand-written kernel comes to the library."""
+    import torch
+    from paper_1911_12954_amd import trg_gemm, trg_gemm_tile
+    M, N, K = (int(x) for x in spec.split(","))
+    tm, tn, tk = trg_gemm_tile("bf16x3")
+    assert M % tm == 0 and N % tn == 0 and K % tk == 0, "M, N, K must be multiples of the join tile"
+    out = {"metric": "BF16 MFMA issue rate at the join shape", "M": M, "N": N, "K": K, "unit": "TFLOP/s"}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    # two bf16 planes (hi, lo) per operand, values in [1, 2)
+    A = torch.randint(0x3F80, 0x4000, (2, M, K), dtype=torch.int16, device="cuda", generator=g)
+    Bt = torch.randint(0x3F80, 0x4000, (2, N, K), dtype=torch.int16, device="cuda", generator=g)
+    Cm = torch.empty(M, N, dtype=torch.float32, device="cuda")
+    ms = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        trg_gemm("bf16x3", A.data_ptr(), Bt.data_ptr(), Cm.data_ptr(), M, N, K, K, K, N)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t = min(ms)
+    out["join_bf16x3_ms"] = t
+    out["join_bf16x3_issued_tflops"] = 3 * 2.0 * M * N * K / (t * 1e-3) / 1e12
+    progress(f"vendor-gemm: join kernel {t:.1f} ms")
+    del A, Bt, Cm
+    torch.cuda.empty_cache()
+    x = torch.randn(M, K, dtype=torch.bfloat16, device="cuda", generator=g)
+    y = torch.randn(K, N, dtype=torch.bfloat16, device="cuda", generator=g)
+    ms = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        z = torch.matmul(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        del z
+    t = min(ms)
+    out["torch_matmul_bf16_ms"] = t
+    out["torch_matmul_bf16_tflops"] = 2.0 * M * N * K / (t * 1e-3) / 1e12
+    out["join_vs_library"] = out["join_bf16x3_issued_tflops"] / out["torch_matmul_bf16_tflops"]
+    out["peak"] = 2500.0
+    return out
 
 
 def accuracy(spec, variants):
@@ -291,6 +347,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
+        return
+    if a.vendor_gemm:
+        print(json.dumps(vendor_gemm(a.vendor_gemm)), flush=True)
         return
     if a.accuracy:
         print(json.dumps(accuracy(a.accuracy, a.accuracy_variants)), flush=True)

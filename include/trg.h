@@ -140,8 +140,16 @@ int trg_hotrg_step_batch(trg_ctx *const *ctxs, int n, int axis, int dcut);
  * the two adjacent decomposed tensors and the contraction completing the
  * block-spin transformation; FP64 throughout, or the contraction GEMMs in
  * FP32 when cfg->precision == TRG_FP32.  The context must have been created
- * with method TRG_ATRG (trg_init_ising or trg_init_factors).  Asynchronous.
- * Errors: TRG_EINVAL, TRG_ESTATE, TRG_ENOMEM, TRG_EHIP. */
+ * with method TRG_ATRG (trg_init_ising or trg_init_factors).  Impure
+ * tensors requested by cfg->impure (trg_init_ising) are kept as their own
+ * pair of pieces S = sum_m G_S[b, m] H_S[m, f] (bond 2 dcut after a step):
+ * the energy impurity carries each bond's beta-derivative on its forward
+ * end (same -Tr S_E / Tr T), each impure two-site product gets its own
+ * randomized partial SVD of rank <= dcut (trial stream 1 + 2 kind + term,
+ * kind 0 = E, 1 = M; term 0 = impurity on the lower site, 1 = upper), and
+ * the pure step's HOSVD isometries and c_n are applied; the paper uses the
+ * impure-tensor method within ATRG (Sec. 3.2) without giving it.
+ * Asynchronous.  Errors: TRG_EINVAL, TRG_ESTATE, TRG_ENOMEM, TRG_EHIP. */
 int trg_atrg_step(trg_ctx *ctx, int axis, int dcut);
 
 /* Create an ATRG context from host pieces T[b, f] = sum_l G[b, l] H[l, f]:
@@ -175,7 +183,8 @@ int trg_free_energy(trg_ctx *ctx, double *lnz_per_site);
 int trg_indicator_x(trg_ctx *ctx, int axis, double *X);
 
 /* E = <H>/V = -Tr S_E / Tr T and M = <s> = Tr S_M / Tr T (impure-tensor
- * method, Sec. 3.1).  TRG_ESTATE if that impurity was not enabled. */
+ * method, Sec. 3.1; HOTRG and ATRG contexts).  Synchronises.  TRG_ESTATE if
+ * that impurity was not enabled. */
 int trg_impure_energy(trg_ctx *ctx, double *E);
 int trg_impure_magnetization(trg_ctx *ctx, double *M);
 

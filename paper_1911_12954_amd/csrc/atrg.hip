@@ -22,6 +22,12 @@
 //      dominant GEMM has M = D^4, K = D^2, N = D^3 in 4D;
 //   5. normalisation c = sqrt(Tr[(G'^T G')(H' H'^T)]), pieces scaled by
 //      c^{-1/2}, acc += 2^{-n} ln c.
+// Impure tensors: impurity j is its own pair of pieces G_S[b, m], H_S[m, f];
+// each impure two-site middle matrix (impurity on the lower site: H_S with
+// the pure Ut; on the upper site: the pure Vt with G_S) gets its own
+// randomized partial SVD of rank <= Dcut, the pure step's isometries
+// compress both terms, which sit side by side along m (bond 2 Dcut), and the
+// pieces take c^{-1/2} (and 1/2 on the forward piece).
 // Contractions of named legs go through einsum2: both operands are packed
 // (K-contiguous, zero-padded) by the strided map kernel and multiplied by the
 // MFMA GEMM of the HOTRG join.
@@ -49,6 +55,36 @@ __global__ void atrg_ising_kernel(double *G, double *H, int d, double beta, doub
   H[sig * n + b] = v;
 }
 
+// Forward pieces of the impurities on the backward piece U0 (bond sigma):
+// HM[sigma, f] = sigma H0[sigma, f]; HE[sigma, f] = e^{beta h sigma/2}
+// (h sigma prod_nu W[sigma, f_nu] + sum_nu 2 W'[sigma, f_nu] prod_{nu' != nu}
+// W[sigma, f_nu']): the derivative of each bond weight on its forward end.
+// Either pointer may be null.
+__global__ void atrg_impurity_kernel(double *HE, double *HM, int d, double beta, double h) {
+  const int n = 1 << d;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * n) return;
+  const int sig = idx & 1, b = idx >> 1;
+  const double spin = sig == 0 ? 1.0 : -1.0;
+  const double ch = cosh(beta), sh = sinh(beta);
+  const double w[2] = {sqrt(ch), spin * sqrt(sh)};
+  const double dw[2] = {sh / (2.0 * sqrt(ch)), spin * ch / (2.0 * sqrt(sh))};
+  const double pref = exp(0.5 * beta * h * spin);
+  double v = pref;
+  for (int a = 0; a < d; ++a) v *= w[(b >> (d - 1 - a)) & 1];
+  double e = h * spin * v;
+  for (int nu = 0; nu < d; ++nu) {
+    double t = pref;
+    for (int a = 0; a < d; ++a) {
+      const int bit = (b >> (d - 1 - a)) & 1;
+      t *= a == nu ? 2.0 * dw[bit] : w[bit];
+    }
+    e += t;
+  }
+  if (HM) HM[sig * n + b] = spin * v;
+  if (HE) HE[sig * n + b] = e;
+}
+
 // Philox4x32 with 10 rounds (Salmon et al., SC'11)
 __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
   for (int r = 0; r < 10; ++r) {
@@ -68,12 +104,14 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
   }
 }
 
-// Omega[e] for e < count: counter (e, step, 0, 0), key (k0, k1); Box-Muller
-// sqrt(-2 ln u1) cos(2 pi u2) with u = (w + 0.5) / 2^32
-__global__ void trial_kernel(double *out, uint32_t count, uint32_t step, uint32_t k0, uint32_t k1) {
+// Omega[e] for e < count: counter (e, step, stream, 0), key (k0, k1);
+// Box-Muller sqrt(-2 ln u1) cos(2 pi u2) with u = (w + 0.5) / 2^32.  Stream 0
+// is the pure swap, 1 + 2 kind + term the impurity SVDs.
+__global__ void trial_kernel(double *out, uint32_t count, uint32_t step, uint32_t stream, uint32_t k0,
+                             uint32_t k1) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= count) return;
-  uint32_t c[4] = {e, step, 0u, 0u};
+  uint32_t c[4] = {e, step, stream, 0u};
   philox4x32_10(c, k0, k1);
   const double u1 = (double(c[0]) + 0.5) / 4294967296.0;
   const double u2 = (double(c[1]) + 0.5) / 4294967296.0;
@@ -747,6 +785,18 @@ void atrg_init_ising(trg_ctx &c, double beta, double h) {
   scale_by_inverse(G, n * 2, c.scal(), 1.0, c.st);
   scale_by_inverse(H, n * 2, c.scal(), 1.0, c.st);
   dbg(c, "init scal", c.scal(), 4);
+  // impurities: G_S = the scaled pure backward piece, H_S from the closed form
+  for (int j = 0; j < c.nimp; ++j) {
+    c.ensure(c.S[j], size_t(n) * 2 * 8);
+    c.ensure(c.Sn[j], size_t(n) * 2 * 8);
+    TRG_HIP_CHECK(hipMemcpyAsync(c.S[j].ptr, G, size_t(n) * 2 * 8, hipMemcpyDeviceToDevice, c.st));
+    double *HS = static_cast<double *>(c.Sn[j].ptr);
+    hipLaunchKernelGGL(atrg_impurity_kernel, dim3(1), dim3(64), 0, c.st, c.imp_kind[j] == 0 ? HS : nullptr,
+                       c.imp_kind[j] == 1 ? HS : nullptr, d, beta, h);
+    TRG_HIP_CHECK(hipGetLastError());
+    scale_by_inverse(HS, n * 2, c.scal(), 1.0, c.st);
+    c.imp_r[j] = 2;
+  }
   TRG_HIP_CHECK(hipMemcpyAsync(rec_d(c, 0), c.scal() + 2, 8, hipMemcpyDeviceToDevice, c.st));
 }
 
@@ -763,6 +813,22 @@ double atrg_trace(trg_ctx &c) {
   sync_check(c);
   double v = 0.0;
   TRG_HIP_CHECK(hipMemcpy(&v, c.scal() + 4, 8, hipMemcpyDeviceToHost));
+  return v;
+}
+
+double atrg_impurity_trace(trg_ctx &c, int j) {
+  int64_t n = 1;
+  for (int a = 0; a < c.d; ++a) n *= c.dims[a];
+  const int nb = 256;
+  double *partial = c.wsp<double>("trpart", nb * 8);
+  hipLaunchKernelGGL(gh_trace_partial, dim3(nb), dim3(256), 0, c.st, static_cast<const double *>(c.S[j].ptr),
+                     static_cast<const double *>(c.Sn[j].ptr), n, c.imp_r[j], partial);
+  TRG_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, c.st, partial, nb, c.scal() + 5);
+  TRG_HIP_CHECK(hipGetLastError());
+  sync_check(c);
+  double v = 0.0;
+  TRG_HIP_CHECK(hipMemcpy(&v, c.scal() + 5, 8, hipMemcpyDeviceToHost));
   return v;
 }
 
@@ -851,101 +917,118 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
   const View vUt = contiguous(lb), vVt = contiguous(lf);
 
   // ---- 2. swap by randomized SVD of M[(kA, b_perp), (f_perp, kB)]
-  // M Z: t[kA, j, kB, c] = sum_f Vt[kA, f_perp, j] Z[f_perp, kB, c];
-  //      out[kA, b_perp, c] = sum_{j, kB} t Ut[j, b_perp, kB]
   const View vVA = rename(vVt, {{"kk", "kA"}, {fn[mu], "j"}});
   const View vUB = rename(vUt, {{"kk", "kB"}, {bn[mu], "j"}});
   const int64_t nsw = int64_t(k) * nperp;
-  int r2 = dcut + p;
-  if (r2 > nsw) r2 = int(nsw);
   std::vector<std::string> fperp, bperp;
   for (int a : perp) {
     fperp.push_back(fn[a]);
     bperp.push_back(bn[a]);
   }
-  auto zview = [&](int64_t cols) {  // rows (f_perp, kB)
-    std::vector<std::pair<std::string, int64_t>> l;
-    for (int a : perp) l.push_back({fn[a], dims[a]});
-    l.push_back({"kB", k});
-    l.push_back({"c", cols});
-    return contiguous(l);
+  // Partial SVD of rank <= dcut of M[(kA, b_perp), (f_perp, kB)] =
+  // sum_j A[kA, f_perp, j] B[j, b_perp, kB] (kA of size ra, kB of size cb):
+  // randomized, with the trial matrix of `stream`; M Z and M^T Z are applied
+  // in factored form (two GEMMs each).  Returns Xs[kA, b_perp, l] =
+  // Q W sqrt(sigma), Ys[l, f_perp, kB] = sqrt(sigma) (Qbt Z)^T and sigma in
+  // workspace buffers named with `tag`, and the rank.
+  struct SwapOut {
+    double *Xs, *Ys, *sig;
+    int dc;
   };
-  auto qview = [&](int64_t cols) {  // rows (kA, b_perp)
-    std::vector<std::pair<std::string, int64_t>> l;
-    l.push_back({"kA", k});
-    for (int a : perp) l.push_back({bn[a], dims[a]});
-    l.push_back({"c", cols});
-    return contiguous(l);
+  auto partial_svd = [&](const double *A, const View &vA, int64_t ra, const double *B, const View &vB,
+                         int64_t cb, uint32_t stream, const std::string &tag) -> SwapOut {
+    const int64_t nr = ra * nperp, nc = nperp * cb;
+    int r2 = dcut + p;
+    if (r2 > nr) r2 = int(nr);
+    if (r2 > nc) r2 = int(nc);
+    auto zview = [&](int64_t cols) {  // rows (f_perp, kB)
+      std::vector<std::pair<std::string, int64_t>> l;
+      for (int a : perp) l.push_back({fn[a], dims[a]});
+      l.push_back({"kB", cb});
+      l.push_back({"c", cols});
+      return contiguous(l);
+    };
+    auto qview = [&](int64_t cols) {  // rows (kA, b_perp)
+      std::vector<std::pair<std::string, int64_t>> l;
+      l.push_back({"kA", ra});
+      for (int a : perp) l.push_back({bn[a], dims[a]});
+      l.push_back({"c", cols});
+      return contiguous(l);
+    };
+    double *tbuf = c.wsp<double>("swT" + tag, size_t(ra) * dims[mu] * cb * r2 * 8);
+    auto apply_M = [&](const double *Zin, double *out) {
+      // t[kA, j, kB, c] = sum_f A[kA, f_perp, j] Z[f_perp, kB, c];
+      // out[kA, b_perp, c] = sum_{j, kB} t B[j, b_perp, kB]
+      einsum2(c, A, vA, Zin, zview(r2), tbuf, {"kA", "j", "kB", "c"}, TRG_FP64, "sw1");
+      const View vt = contiguous({{"kA", ra}, {"j", dims[mu]}, {"kB", cb}, {"c", r2}});
+      std::vector<std::string> o{"kA"};
+      o.insert(o.end(), bperp.begin(), bperp.end());
+      o.push_back("c");
+      einsum2(c, tbuf, vt, B, vB, out, o, TRG_FP64, "sw2");
+    };
+    auto apply_MT = [&](const double *Qin, double *out) {
+      einsum2(c, B, vB, Qin, qview(r2), tbuf, {"j", "kB", "kA", "c"}, TRG_FP64, "sw3");
+      const View vt = contiguous({{"j", dims[mu]}, {"kB", cb}, {"kA", ra}, {"c", r2}});
+      std::vector<std::string> o = fperp;
+      o.push_back("kB");
+      o.push_back("c");
+      einsum2(c, A, vA, tbuf, vt, out, o, TRG_FP64, "sw4");
+    };
+    const int64_t nmax = nr > nc ? nr : nc;
+    double *Om = c.wsp<double>("swOm" + tag, size_t(nc) * r2 * 8);
+    double *Yb = c.wsp<double>("swY" + tag, size_t(nmax) * r2 * 8);
+    double *Qb = c.wsp<double>("swQ" + tag, size_t(nr) * r2 * 8);
+    double *Zb = c.wsp<double>("swZ" + tag, size_t(nc) * r2 * 8);
+    {
+      const uint64_t cnt = uint64_t(nc) * r2;
+      TRG_REQUIRE(cnt < (1ull << 32), "atrg: trial matrix too large");
+      const uint64_t seed = c.cfg.seed;
+      hipLaunchKernelGGL(trial_kernel, dim3(uint32_t((cnt + 255) / 256)), dim3(256), 0, st, Om, uint32_t(cnt),
+                         uint32_t(n_step), stream, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32));
+      TRG_HIP_CHECK(hipGetLastError());
+    }
+    dbg(c, "Om", Om, nc * r2);
+    apply_M(Om, Yb);
+    dbg(c, "MOm", Yb, nr * r2);
+    cholqr3(c, Yb, nr, r2, Qb, nullptr, "sw");
+    dbg(c, "Q0", Qb, nr * r2);
+    for (int it = 0; it < q; ++it) {
+      apply_MT(Qb, Yb);
+      cholqr3(c, Yb, nc, r2, Zb, nullptr, "sw");
+      apply_M(Zb, Yb);
+      cholqr3(c, Yb, nr, r2, Qb, nullptr, "sw");
+    }
+    // Bt = M^T Q = Qbt Rb; Q^T M = Rb^T Qbt^T; SVD of Rb^T
+    double *Rb = c.wsp<double>("swRb", size_t(r2) * r2 * 8);
+    double *RbT = c.wsp<double>("swRbT", size_t(r2) * r2 * 8);
+    apply_MT(Qb, Yb);
+    cholqr3(c, Yb, nc, r2, Zb, Rb, "sw");
+    apply_map(Rb, IN_F64, contiguous({{"i", r2}, {"j", r2}}), nullptr, {}, {}, RbT, OUT_F64, 0,
+              contiguous({{"j", r2}, {"i", r2}}), st);
+    const int dcx = r2 < dcut ? r2 : dcut;
+    double *sg = c.wsp<double>("swsig" + tag, size_t(dcx) * 8), *sqsig = c.wsp<double>("swsq", size_t(dcx) * 8);
+    double *Wb = c.wsp<double>("swW", size_t(r2) * dcx * 8), *Zs = c.wsp<double>("swZs", size_t(r2) * dcx * 8);
+    dbg(c, "Rb", Rb, int64_t(r2) * r2);
+    small_svd(c, RbT, r2, dcx, sg, sqsig, Wb, Zs, "sw");
+    dbg(c, "sigma", sg, dcx);
+    SwapOut o{c.wsp<double>("Xs" + tag, size_t(nr) * dcx * 8), c.wsp<double>("Ys" + tag, size_t(nc) * dcx * 8), sg,
+              dcx};
+    double *tmp = c.wsp<double>("swtmp", size_t(nmax) * dcx * 8);
+    einsum2(c, Qb, contiguous({{"i", nr}, {"j", r2}}), Wb, contiguous({{"j", r2}, {"l", dcx}}), tmp, {"i", "l"},
+            TRG_FP64, "sx");
+    apply_map(tmp, IN_F64, contiguous({{"i", nr}, {"l", dcx}}), sqsig, {{"l", 1}}, {}, o.Xs, OUT_F64, 0,
+              contiguous({{"i", nr}, {"l", dcx}}), st);
+    einsum2(c, Zb, contiguous({{"i", nc}, {"j", r2}}), Zs, contiguous({{"j", r2}, {"l", dcx}}), tmp, {"i", "l"},
+            TRG_FP64, "sx");
+    apply_map(tmp, IN_F64, contiguous({{"i", nc}, {"l", dcx}}), sqsig, {{"l", 1}}, {}, o.Ys, OUT_F64, 0,
+              contiguous({{"l", dcx}, {"i", nc}}), st);
+    return o;
   };
-  double *tbuf = c.wsp<double>("swT", size_t(k) * dims[mu] * k * r2 * 8);
-  auto apply_M = [&](const double *Zin, double *out) {
-    einsum2(c, Vt, vVA, Zin, zview(r2), tbuf, {"kA", "j", "kB", "c"}, TRG_FP64, "sw1");
-    const View vt = contiguous({{"kA", k}, {"j", dims[mu]}, {"kB", k}, {"c", r2}});
-    std::vector<std::string> o{"kA"};
-    o.insert(o.end(), bperp.begin(), bperp.end());
-    o.push_back("c");
-    einsum2(c, tbuf, vt, Ut, vUB, out, o, TRG_FP64, "sw2");
-  };
-  auto apply_MT = [&](const double *Qin, double *out) {
-    einsum2(c, Ut, vUB, Qin, qview(r2), tbuf, {"j", "kB", "kA", "c"}, TRG_FP64, "sw3");
-    const View vt = contiguous({{"j", dims[mu]}, {"kB", k}, {"kA", k}, {"c", r2}});
-    std::vector<std::string> o = fperp;
-    o.push_back("kB");
-    o.push_back("c");
-    einsum2(c, Vt, vVA, tbuf, vt, out, o, TRG_FP64, "sw4");
-  };
-  double *Om = c.wsp<double>("swOm", size_t(nsw) * r2 * 8);
-  double *Yb = c.wsp<double>("swY", size_t(nsw) * r2 * 8);
-  double *Qb = c.wsp<double>("swQ", size_t(nsw) * r2 * 8);
-  double *Zb = c.wsp<double>("swZ", size_t(nsw) * r2 * 8);
-  {
-    const uint64_t cnt = uint64_t(nsw) * r2;
-    TRG_REQUIRE(cnt < (1ull << 32), "atrg: trial matrix too large");
-    const uint64_t seed = c.cfg.seed;
-    hipLaunchKernelGGL(trial_kernel, dim3(uint32_t((cnt + 255) / 256)), dim3(256), 0, st, Om, uint32_t(cnt),
-                       uint32_t(n_step), uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32));
-    TRG_HIP_CHECK(hipGetLastError());
-  }
   dbg(c, "Ut", Ut, n * k);
   dbg(c, "Vt", Vt, n * k);
-  dbg(c, "Om", Om, nsw * r2);
-  apply_M(Om, Yb);
-  dbg(c, "MOm", Yb, nsw * r2);
-  cholqr3(c, Yb, nsw, r2, Qb, nullptr, "sw");
-  dbg(c, "Q0", Qb, nsw * r2);
-  for (int it = 0; it < q; ++it) {
-    apply_MT(Qb, Yb);
-    cholqr3(c, Yb, nsw, r2, Zb, nullptr, "sw");
-    apply_M(Zb, Yb);
-    cholqr3(c, Yb, nsw, r2, Qb, nullptr, "sw");
-  }
-  // Bt = M^T Q = Qbt Rb; Q^T M = Rb^T Qbt^T; SVD of Rb^T
-  double *Rb = c.wsp<double>("swRb", size_t(r2) * r2 * 8);
-  double *RbT = c.wsp<double>("swRbT", size_t(r2) * r2 * 8);
-  apply_MT(Qb, Yb);
-  cholqr3(c, Yb, nsw, r2, Zb, Rb, "sw");
-  apply_map(Rb, IN_F64, contiguous({{"i", r2}, {"j", r2}}), nullptr, {}, {}, RbT, OUT_F64, 0,
-            contiguous({{"j", r2}, {"i", r2}}), st);
-  const int dc = r2 < dcut ? r2 : dcut;
-  double *sig = c.wsp<double>("swsig", size_t(dc) * 8), *sqsig = c.wsp<double>("swsq", size_t(dc) * 8);
-  double *Wb = c.wsp<double>("swW", size_t(r2) * dc * 8), *Zs = c.wsp<double>("swZs", size_t(r2) * dc * 8);
-  dbg(c, "Rb", Rb, int64_t(r2) * r2);
-  small_svd(c, RbT, r2, dc, sig, sqsig, Wb, Zs, "sw");
-  dbg(c, "sigma", sig, dc);
-  // Xs[kA, b_perp, l] = Q W sqrt(sigma); Ys[l, f_perp, kB] = sqrt(sigma) (Qbt Z)^T
-  double *Xs = c.wsp<double>("Xs", size_t(nsw) * dc * 8);
-  double *Ys = c.wsp<double>("Ys", size_t(nsw) * dc * 8);
-  {
-    double *tmp = c.wsp<double>("swtmp", size_t(nsw) * dc * 8);
-    einsum2(c, Qb, contiguous({{"i", nsw}, {"j", r2}}), Wb, contiguous({{"j", r2}, {"l", dc}}), tmp, {"i", "l"},
-            TRG_FP64, "sx");
-    apply_map(tmp, IN_F64, contiguous({{"i", nsw}, {"l", dc}}), sqsig, {{"l", 1}}, {}, Xs, OUT_F64, 0,
-              contiguous({{"i", nsw}, {"l", dc}}), st);
-    einsum2(c, Zb, contiguous({{"i", nsw}, {"j", r2}}), Zs, contiguous({{"j", r2}, {"l", dc}}), tmp, {"i", "l"},
-            TRG_FP64, "sx");
-    apply_map(tmp, IN_F64, contiguous({{"i", nsw}, {"l", dc}}), sqsig, {{"l", 1}}, {}, Ys, OUT_F64, 0,
-              contiguous({{"l", dc}, {"i", nsw}}), st);
-  }
+  const SwapOut pure = partial_svd(Vt, vVA, k, Ut, vUB, k, 0u, "");
+  double *Xs = pure.Xs, *Ys = pure.Ys, *sig = pure.sig;
+  const int dc = pure.dc;
   c.ensure(c.atrg_sigma, size_t(dc) * 8);
   TRG_HIP_CHECK(hipMemcpyAsync(c.atrg_sigma.ptr, sig, size_t(dc) * 8, hipMemcpyDeviceToDevice, st));
   c.atrg_nsig = dc;
@@ -1110,7 +1193,10 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
   double *Hn = c.wsp<double>("newH", size_t(nnew) * dc * 8);
   const int nu1 = perp[0];
   auto P = [&](int nu) { return static_cast<const double *>(c.U[nu].ptr); };
-  {
+  // backward piece: Ut[bA..., kA] (kA of size k) and Xs[kA, bB_perp..., l]
+  // (l of size dc) through the isometries into Gn[canonical legs..., l]
+  auto gblock = [&](const double *Ut, const View &vUA, int64_t k, const double *Xs, const View &vXs,
+                    int64_t dc, double *Gn) {
     // G: UP = Ut[bA..., kA] P1[bA_nu1, bB_nu1, B_nu1]
     const View vP1 = contiguous({{nm("bA", nu1), dims[nu1]}, {nm("bB", nu1), dims[nu1]}, {nm("B", nu1), nd[nu1]}});
     std::vector<std::string> o;
@@ -1174,8 +1260,11 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
       tl.push_back({"l", dc});
       apply_map(G1, IN_F64, cur, nullptr, {}, {}, Gn, OUT_F64, 0, contiguous(tl), st);
     }
-  }
-  {
+    };
+  // forward piece: Ys[l, fA_perp..., kB] and Vt[kB, fB...] (kB of size k)
+  // through the isometries into Hn[l, canonical legs...]
+  auto hblock = [&](const double *Ys, const View &vYs, int64_t k, const double *Vt, const View &vVB,
+                    int64_t dc, double *Hn) {
     // H: VP = Vt[kB, fB...] P1[fA_nu1, fB_nu1, F_nu1]
     const View vP1 = contiguous({{nm("fA", nu1), dims[nu1]}, {nm("fB", nu1), dims[nu1]}, {nm("F", nu1), nd[nu1]}});
     std::vector<std::string> o{"kB"};
@@ -1235,7 +1324,9 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
                                                        : std::make_pair(nm("F", a), int64_t(nd[a])));
       apply_map(H1, IN_F64, cur, nullptr, {}, {}, Hn, OUT_F64, 0, contiguous(tl), st);
     }
-  }
+    };
+  gblock(Ut, vUA, k, Xs, vXs, dc, Gn);
+  hblock(Ys, vYs, k, Vt, vVB, dc, Hn);
 
   dbg(c, "Gn", Gn, nnew * dc);
   dbg(c, "Hn", Hn, nnew * dc);
@@ -1256,6 +1347,66 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
   c.ensure(c.H, size_t(nnew) * dc * 8);
   TRG_HIP_CHECK(hipMemcpyAsync(c.G.ptr, Gn, size_t(nnew) * dc * 8, hipMemcpyDeviceToDevice, st));
   TRG_HIP_CHECK(hipMemcpyAsync(c.H.ptr, Hn, size_t(nnew) * dc * 8, hipMemcpyDeviceToDevice, st));
+
+  // ---- impurities: [C(S, T) + C(T, S)] / 2c.  Impurity j is the pair
+  // G_S[b..., m] (S[j]) and H_S[m, f...] (Sn[j]); each impure two-site middle
+  // matrix gets its own partial SVD of rank <= dcut, the isometries are the
+  // pure step's, and the new impurity has the two terms side by side along m.
+  for (int j = 0; j < c.nimp; ++j) {
+    const uint32_t kind = uint32_t(c.imp_kind[j]);
+    const int64_t m = c.imp_r[j];
+    const double *GS = static_cast<const double *>(c.S[j].ptr);
+    const double *HS = static_cast<const double *>(c.Sn[j].ptr);
+    std::vector<std::pair<std::string, int64_t>> lbm, lfm{{"kk", m}};
+    for (int a = 0; a < d; ++a) lbm.push_back({bn[a], dims[a]});
+    lbm.push_back({"kk", m});
+    for (int a = 0; a < d; ++a) lfm.push_back({fn[a], dims[a]});
+    const View vGS = contiguous(lbm), vHS = contiguous(lfm);
+    View vGSA = vGS, vHSB = vHS;
+    for (int a = 0; a < d; ++a) {
+      vGSA = rename(vGSA, {{bn[a], nm("bA", a)}});
+      vHSB = rename(vHSB, {{fn[a], nm("fB", a)}});
+    }
+    vGSA = rename(vGSA, {{"kk", "kA"}});
+    vHSB = rename(vHSB, {{"kk", "kB"}});
+    auto xview = [&](int64_t rows, int64_t l) {  // [kA, bB_perp..., l]
+      std::vector<std::pair<std::string, int64_t>> v{{"kA", rows}};
+      for (int a : perp) v.push_back({nm("bB", a), dims[a]});
+      v.push_back({"l", l});
+      return contiguous(v);
+    };
+    auto yview = [&](int64_t l, int64_t cols) {  // [l, fA_perp..., kB]
+      std::vector<std::pair<std::string, int64_t>> v{{"l", l}};
+      for (int a : perp) v.push_back({nm("fA", a), dims[a]});
+      v.push_back({"kB", cols});
+      return contiguous(v);
+    };
+    const int64_t mcap = 2 * int64_t(dcut);
+    double *GSn = c.wsp<double>("iG", size_t(nnew) * mcap * 8);
+    double *HSn = c.wsp<double>("iH", size_t(nnew) * mcap * 8);
+    double *gt = c.wsp<double>("iGt", size_t(nnew) * dcut * 8);
+    // impurity on the lower site: M_1 = sum_j H_S[m, f_perp, j] Ut[j, b_perp, kB]
+    const SwapOut s1 = partial_svd(HS, rename(vHS, {{"kk", "kA"}, {fn[mu], "j"}}), m, Ut, vUB, k, 1u + 2u * kind, "i");
+    const int64_t d1 = s1.dc;
+    gblock(GS, vGSA, m, s1.Xs, xview(m, d1), d1, gt);
+    hblock(s1.Ys, yview(d1, k), k, Vt, vVB, d1, HSn);
+    // impurity on the upper site: M_2 = sum_j Vt[kA, f_perp, j] G_S[j, b_perp, m]
+    const SwapOut s2 = partial_svd(Vt, vVA, k, GS, rename(vGS, {{"kk", "kB"}, {bn[mu], "j"}}), m, 2u + 2u * kind, "i");
+    const int64_t d2 = s2.dc, mn = d1 + d2;
+    apply_map(gt, IN_F64, contiguous({{"b", nnew}, {"l", d1}}), nullptr, {}, {}, GSn, OUT_F64, 0,
+              View{Leg{"b", nnew, mn}, Leg{"l", d1, 1}}, st);
+    gblock(Ut, vUA, k, s2.Xs, xview(k, d2), d2, gt);
+    apply_map(gt, IN_F64, contiguous({{"b", nnew}, {"l", d2}}), nullptr, {}, {}, GSn + d1, OUT_F64, 0,
+              View{Leg{"b", nnew, mn}, Leg{"l", d2, 1}}, st);
+    hblock(s2.Ys, yview(d2, m), m, HS, vHSB, d2, HSn + size_t(d1) * nnew);
+    scale_by_inverse(GSn, nnew * mn, c.scal(), 1.0, st);
+    scale_by_inverse(HSn, nnew * mn, c.scal(), 0.5, st);
+    c.ensure(c.S[j], size_t(nnew) * mn * 8);
+    c.ensure(c.Sn[j], size_t(nnew) * mn * 8);
+    TRG_HIP_CHECK(hipMemcpyAsync(c.S[j].ptr, GSn, size_t(nnew) * mn * 8, hipMemcpyDeviceToDevice, st));
+    TRG_HIP_CHECK(hipMemcpyAsync(c.Sn[j].ptr, HSn, size_t(nnew) * mn * 8, hipMemcpyDeviceToDevice, st));
+    c.imp_r[j] = int(mn);
+  }
 
   trg_step_rec hr{};
   hr.n = n_step;

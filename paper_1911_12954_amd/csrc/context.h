@@ -118,6 +118,7 @@ struct trg_ctx {
 
   // ATRG: T = sum_l G[b, l] H[l, f] (G: n x r, H: r x n), last swap spectrum
   Buffer G, H, atrg_sigma;
+  int imp_r[2] = {0, 0};  // ATRG: bond of impurity j's pieces S[j] (G_S) and Sn[j] (H_S)
   int r = 0;
   int atrg_nsig = 0;
 
@@ -190,6 +191,8 @@ namespace trg {
 void atrg_init_ising(trg_ctx &c, double beta, double h);
 void atrg_step_impl(trg_ctx &c, int mu, int dcut);
 double atrg_trace(trg_ctx &c);
+// Tr S_j = sum G_S[b, m] H_S[m, b] of ATRG impurity j (synchronises)
+double atrg_impurity_trace(trg_ctx &c, int j);
 void sync_check(trg_ctx &c);
 double *rec_d(trg_ctx &c, int n);
 int *rec_i(trg_ctx &c, int n);

@@ -638,19 +638,18 @@ int trg_init_ising(trg_ctx **out, double beta, double h, int d, const trg_config
     const unsigned imp = cfg ? cfg->impure : 0u;
     TRG_REQUIRE(!(imp & TRG_IMPURE_E) || beta > 0.0, "the energy impurity needs beta > 0");
     const bool atrg = cfg && cfg->method == TRG_ATRG;
-    TRG_REQUIRE(!atrg || imp == 0, "ATRG contexts carry no impure tensors");
     TRG_REQUIRE(!atrg || cfg->precision != TRG_BF16X3, "ATRG supports FP64 and FP32 contractions");
     c = new_ctx(d, cfg);
     for (int a = 0; a < d; ++a) c->dims[a] = 2;
+    c->has_e = imp & TRG_IMPURE_E;
+    c->has_m = imp & TRG_IMPURE_M;
+    if (c->has_e) c->imp_kind[c->nimp++] = 0;
+    if (c->has_m) c->imp_kind[c->nimp++] = 1;
     if (atrg) {
       init_common(*c);
       atrg_init_ising(*c, beta, h);
       return TRG_OK;
     }
-    c->has_e = imp & TRG_IMPURE_E;
-    c->has_m = imp & TRG_IMPURE_M;
-    if (c->has_e) c->imp_kind[c->nimp++] = 0;
-    if (c->has_m) c->imp_kind[c->nimp++] = 1;
     init_common(*c);
     const size_t bytes = size_t(c->total()) * 8;
     c->ensure(c->T, bytes);
@@ -854,13 +853,28 @@ int trg_indicator_x(trg_ctx *ctx, int axis, double *X) {
   });
 }
 
+// Tr T and Tr S of the impurity of `kind` (0 E, 1 M)
+static void impure_traces(trg_ctx *ctx, int kind, double *tT, double *tS) {
+  if (ctx->cfg.method == TRG_ATRG) {
+    int j = 0;
+    while (j < ctx->nimp && ctx->imp_kind[j] != kind) ++j;
+    *tT = atrg_trace(*ctx);
+    *tS = atrg_impurity_trace(*ctx, j);
+    return;
+  }
+  double t[4];
+  traces(ctx, t);
+  *tT = t[1];
+  *tS = t[2 + kind];
+}
+
 int trg_impure_energy(trg_ctx *ctx, double *E) {
   if (!ctx || !E) return fail(ctx, TRG_EINVAL, "NULL argument");
   return guarded(ctx, [&]() -> int {
     if (!ctx->has_e) return fail(ctx, TRG_ESTATE, "energy impurity not enabled");
-    double t[4];
-    traces(ctx, t);
-    *E = -t[2] / t[1];
+    double tT = 0.0, tS = 0.0;
+    impure_traces(ctx, 0, &tT, &tS);
+    *E = -tS / tT;
     return TRG_OK;
   });
 }
@@ -869,9 +883,9 @@ int trg_impure_magnetization(trg_ctx *ctx, double *M) {
   if (!ctx || !M) return fail(ctx, TRG_EINVAL, "NULL argument");
   return guarded(ctx, [&]() -> int {
     if (!ctx->has_m) return fail(ctx, TRG_ESTATE, "magnetization impurity not enabled");
-    double t[4];
-    traces(ctx, t);
-    *M = t[3] / t[1];
+    double tT = 0.0, tS = 0.0;
+    impure_traces(ctx, 1, &tT, &tS);
+    *M = tS / tT;
     return TRG_OK;
   });
 }
@@ -962,7 +976,12 @@ size_t trg_resident_bytes(int d, int dcut, int precision, int method, unsigned i
   (void)precision;
   if (d < 2 || d > 4 || dcut < 1) return 0;
   const double D = dcut;
-  if (method == TRG_ATRG) return size_t(2.0 * 2.0 * std::pow(D, d + 1) * 8.0);  // G, H and their next copies
+  if (method == TRG_ATRG) {
+    // G, H and their next copies; each impurity: two pieces of bond 2 Dcut
+    // and their next copies
+    const int ni = ((impure & 1u) ? 1 : 0) + ((impure & 2u) ? 1 : 0);
+    return size_t((2.0 + 4.0 * ni) * 2.0 * std::pow(D, d + 1) * 8.0);
+  }
   const int nt = 1 + ((impure & 1u) ? 1 : 0) + ((impure & 2u) ? 1 : 0);
   return size_t(2.0 * nt * std::pow(D, 2 * d) * 8.0);  // each tensor and its next-step buffer
 }
@@ -972,8 +991,11 @@ size_t trg_workspace_bytes(int d, int dcut, int precision, int method, unsigned 
   const double D = dcut;
   if (method == TRG_ATRG) {
     // the D^{2d-1} contraction intermediate (GEMM output and its unpacked
-    // copy) plus the randomized-SVD blocks (r = 5 Dcut columns)
-    return size_t(2.0 * std::pow(D, 2 * d - 1) * 8.0 + 8.0 * std::pow(D, d) * 5.0 * D * 8.0);
+    // copy) plus the randomized-SVD blocks (r = 5 Dcut columns); the
+    // impurities' SVDs (rows up to 2 Dcut D^{d-1}) and new pieces on top
+    const bool imp = (impure & 3u) != 0;
+    return size_t(2.0 * std::pow(D, 2 * d - 1) * 8.0 + (imp ? 16.0 : 8.0) * std::pow(D, d) * 5.0 * D * 8.0 +
+                  (imp ? 5.0 * std::pow(D, d + 1) * 8.0 : 0.0));
   }
   // steady-state join of the natural plan (every leg at Dcut)
   const int nt = 1 + ((impure & 1u) ? 1 : 0) + ((impure & 2u) ? 1 : 0);

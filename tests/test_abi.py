@@ -88,8 +88,9 @@ def test_more_argument_checks_on_the_host(lib):
     cfg.method, cfg.precision = L.TRG_ATRG, L.TRG_BF16X3
     assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
     cfg = L.TrgConfig()
-    cfg.method, cfg.impure = L.TRG_ATRG, L.TRG_IMPURE_M
-    assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
+    cfg.method, cfg.impure = L.TRG_ATRG, L.TRG_IMPURE_E
+    assert lib.trg_init_ising(C.byref(h), 0.0, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
+    assert b"beta > 0" in lib.trg_last_error(None)
     cfg = L.TrgConfig()
     cfg.dcut = 2000
     assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL

@@ -90,3 +90,51 @@ def test_dcut24_swap_spectrum_on_random_pieces():
     # the pieces start unnormalised: after one step acc = ln c_1 / 2
     assert abs(ctx.accumulator() - 0.5 * ctx.step_log()[-1].ln_c) < 1e-12
     ctx.close()
+
+
+# ------------------------------------------------------------ impure tensors ---
+def _gpu_impure(beta, h, d, dcut, L, **cfg):
+    from paper_1911_12954_amd import trg_init_ising
+    ctx = trg_init_ising(beta, h, d, dcut=dcut, method="atrg", impure=("E", "M"), **cfg)
+    m = L.bit_length() - 1
+    for n in range(1, d * m + 1):
+        ctx.atrg_step((n - 1) % d, dcut)
+    out = {"f": ctx.free_energy(), "E": ctx.impure_energy(), "M": ctx.impure_magnetization()}
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("beta,h", [(0.4407, 0.0), (0.3, 0.05)])
+def test_impure_2d_L4_untruncated_equals_brute_force(beta, h):
+    """Every partial SVD keeps the whole space: E and M are the spin sums."""
+    need_gpu()
+    announce("atrg impure 2d brute", beta, h)
+    g = _gpu_impure(beta, h, 2, 128, 4, rsvd_p=8, rsvd_q=2)
+    lnz, E, M = exact.brute_force(beta, h, 2, 4)
+    print(f"[atrg impure 2d] dE {g['E'] - E:.3e} dM {g['M'] - M:.3e}", flush=True)
+    assert abs(g["f"] - lnz) < 1e-12
+    assert abs(g["E"] - E) < 1e-11 * abs(E)
+    assert abs(g["M"] - M) < 1e-11 * max(abs(M), 1.0)
+
+
+@pytest.mark.parametrize("dcut", [4, 6])
+def test_impure_4d_L4_matches_oracle(dcut):
+    """Truncated 4D run: the impurity SVDs draw the same trial matrices
+    (counter word 1 + 2 kind + term) on both sides."""
+    need_gpu()
+    announce("atrg impure 4d L4", dcut)
+    g = _gpu_impure(0.1497, 1e-3, 4, dcut, 4, seed=5)
+    r = atrg.run(0.1497, 1e-3, 4, dcut, 4, seed=5, impure=True)
+    print(f"[atrg impure 4d dcut {dcut}] E {g['E']:.12f} / {r.energy:.12f}  M {g['M']:.12f} / "
+          f"{r.magnetization:.12f}", flush=True)
+    assert abs(g["f"] - r.ln_z_per_site) <= 1e-10 * abs(r.ln_z_per_site)
+    assert abs(g["E"] - r.energy) <= 1e-9 * abs(r.energy)
+    assert abs(g["M"] - r.magnetization) <= 1e-9 * abs(r.magnetization)
+
+
+def test_impurities_leave_the_pure_atrg_run_unchanged():
+    need_gpu()
+    announce("atrg impure pure unchanged")
+    a = _gpu_run(0.1497, 1e-3, 4, 4, 4, seed=5)
+    b = _gpu_impure(0.1497, 1e-3, 4, 4, 4, seed=5)
+    assert a["f"] == b["f"]

@@ -68,6 +68,16 @@ def test_sliced_join_is_bitwise_equal(budget):
     assert a.step_log()[-1].ln_c == b.step_log()[-1].ln_c
 
 
+_FP64_REF = {}
+
+
+def _fp64_ref(*args):
+    """FP64 GPU run shared by the parametrised mixed-precision cases."""
+    if args not in _FP64_REF:
+        _FP64_REF[args] = _gpu_run(*args)
+    return _FP64_REF[args]
+
+
 def _gpu_run(beta, h, d, dcut, L, impure=("E", "M"), precision="fp64"):
     from paper_1911_12954_amd import trg_init_ising
     ctx = trg_init_ising(beta, h, d, dcut=dcut, impure=impure, precision=precision)
@@ -170,7 +180,7 @@ def test_mixed_precision_error_dcut8(precision, n64, tol_f, tol_E, tol_M):
     need_gpu()
     from paper_1911_12954_amd import trg_init_ising
     announce("mixed dcut8", precision, n64)
-    ref = _gpu_run(0.1497, 1e-5, 4, 8, 16)
+    ref = _fp64_ref(0.1497, 1e-5, 4, 8, 16)
     ctx = trg_init_ising(0.1497, 1e-5, 4, dcut=8, impure=("E", "M"), precision=precision, fp64_steps=n64)
     ctx.run(16)
     got = {"f": ctx.free_energy(), "E": ctx.impure_energy(), "M": ctx.impure_magnetization()}
