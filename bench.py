@@ -71,6 +71,9 @@ def parse():
     p.add_argument("--copy-cal", type=float, default=0.0,
                    help="only copy this many GiB device to device three times (calibration of the "
                         "FETCH_SIZE / WRITE_SIZE counters)")
+    p.add_argument("--atrg-impure", default=None,
+                   help="instead of timing: 'd;T;h;L;dcuts;hotrg_dcut' (e.g. '4;6.64;0;1024;8,12,16;8'): E and M "
+                        "by ATRG impure tensors for each Dcut next to HOTRG's at hotrg_dcut (0: none) (FP64)")
     p.add_argument("--vendor-gemm", default=None,
                    help="instead of timing the step: 'M,N,K' (e.g. '30208,100096,100000', the full-slice join "
                         "of the Dcut = 10 step): the BF16x3 join kernel against one plain BF16 torch.matmul "
@@ -170,6 +173,44 @@ def accuracy(spec, variants):
             continue
         out[f"rel_err_{key}"] = {k: abs(res[key][k] - ref[k]) / max(abs(ref[k]), 1e-300) for k in ("f", "E", "M")}
         out[f"abs_err_{key}"] = {k: abs(res[key][k] - ref[k]) for k in ("f", "E", "M")}
+    return out
+
+
+def atrg_impure(spec):
+    """E = <H>/V and M = <s> from the ATRG impure tensors at several Dcut,
+    with HOTRG's impure-tensor values beside them."""
+    import torch
+    from paper_1911_12954_amd import trg_init_ising
+    d, T, h, L, dcuts, hdcut = spec.split(";")
+    d, T, h, L, hdcut = int(d), float(T), float(h), int(L), int(hdcut)
+    beta = 1.0 / T
+    out = {"workload": f"{d}D Ising, T = {T} (beta = {beta:.8f}), h = {h}, L = {L}, FP64", "atrg": []}
+
+    def run(method, D):
+        t0 = time.perf_counter()
+        ctx = trg_init_ising(beta, h, d, dcut=D, precision="fp64", method=method, impure=("E", "M"))
+        nsteps = d * (L.bit_length() - 1)
+        for n in range(1, nsteps + 1):
+            if method == "atrg":
+                ctx.atrg_step((n - 1) % d, D)
+            else:
+                ctx.hotrg_step((n - 1) % d, D)
+            if n % 8 == 0:
+                progress(f"atrg-impure: {method} Dcut {D}: step {n}/{nsteps} lnZ/V {ctx.free_energy():.12f} "
+                         f"at {time.perf_counter() - t0:.1f} s")
+        r = {"dcut": D, "lnZ_per_site": ctx.free_energy(), "E": ctx.impure_energy(),
+             "M": ctx.impure_magnetization()}
+        ctx.close()
+        torch.cuda.empty_cache()
+        r["seconds"] = time.perf_counter() - t0
+        progress(f"atrg-impure: {method} Dcut {D}: lnZ/V {r['lnZ_per_site']:.12f} E {r['E']:.10f} "
+                 f"M {r['M']:.10f} in {r['seconds']:.1f} s")
+        return r
+
+    if hdcut > 0:
+        out["hotrg"] = run("hotrg", hdcut)
+    for D in (int(x) for x in dcuts.split(",")):
+        out["atrg"].append(run("atrg", D))
     return out
 
 
@@ -347,6 +388,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
+        return
+    if a.atrg_impure:
+        print(json.dumps(atrg_impure(a.atrg_impure)), flush=True)
         return
     if a.vendor_gemm:
         print(json.dumps(vendor_gemm(a.vendor_gemm)), flush=True)
