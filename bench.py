@@ -62,8 +62,8 @@ def parse():
     p.add_argument("--serve-precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
     p.add_argument("--serve-budget-gb", type=float, default=200.0)
     p.add_argument("--tc-bisect", default=None,
-                   help="instead of timing: 'd,dcut,steps,beta_lo,beta_hi,tol' bisection of the transition on the "
-                        "degeneracy indicator X (FP64)")
+                   help="instead of timing: 'd,dcut,steps,beta_lo,beta_hi,tol[,method]' bisection of the "
+                        "transition on the degeneracy indicator X (FP64; method hotrg or atrg)")
     p.add_argument("--atrg-study", default=None,
                    help="instead of timing: 'dcuts;pq_dcut;hotrg_dcut' (e.g. '8,12,16,20,24;16;8'): ATRG f at "
                         "T = 6.65035, L = 1024 for each Dcut, the RSVD (p, q) study at pq_dcut and the ratio to "
@@ -403,18 +403,20 @@ def main():
         return
     if a.tc_bisect:
         from paper_1911_12954_amd.scan import bisect_transition, indicator_after
-        d, dcut, steps, blo, bhi, tol = a.tc_bisect.split(",")
+        fields = a.tc_bisect.split(",")
+        d, dcut, steps, blo, bhi, tol = fields[:6]
+        method = fields[6] if len(fields) > 6 else "hotrg"
         d, dcut, steps, blo, bhi, tol = int(d), int(dcut), int(steps), float(blo), float(bhi), float(tol)
         t0 = time.perf_counter()
 
         def ev(beta):
-            x = indicator_after(beta, d, dcut, steps)
+            x = indicator_after(beta, d, dcut, steps, method=method)
             progress(f"tc-bisect: beta {beta:.8f} X {x:.6f} at {time.perf_counter() - t0:.1f} s")
             return x
 
         b = bisect_transition(d, dcut, blo, bhi, steps, tol, evaluate=ev)
         print(json.dumps({"metric": "transition bracket from the indicator X (bisection on beta)",
-                          "d": d, "dcut": dcut, "steps": steps, "beta_lo": b.beta_lo, "beta_hi": b.beta_hi,
+                          "method": method, "d": d, "dcut": dcut, "steps": steps, "beta_lo": b.beta_lo, "beta_hi": b.beta_hi,
                           "T_lo": 1.0 / b.beta_hi, "T_hi": 1.0 / b.beta_lo, "evaluations": b.evaluations,
                           "seconds": time.perf_counter() - t0}), flush=True)
         return

@@ -172,14 +172,17 @@ int trg_run(trg_ctx *ctx, long long L);
  * the same axis).  Synchronises.  Caller owns *out. */
 int trg_free_energy(trg_ctx *ctx, double *lnz_per_site);
 
-/* Degeneracy indicator of the current HOTRG tensor T (the quantity the
+/* Degeneracy indicator of the current tensor T (the quantity the
  * paper follows against the iteration to locate the transition, Sec. 3.1,
  * Fig. 3; defined in its reference by Gu and Wen):
  *   X = (Tr M)^2 / Tr(M M),  M[a][a'] = sum over the other axes' diagonals
  *   of T[.., a, a', ..] (the legs of `axis` open, every other pair traced).
  * X -> 1 in the disordered phase, 2 with the Z2 symmetry broken.  Scale
- * invariant.  Synchronises the stream.  Errors: TRG_EINVAL (bad axis, ATRG
- * context), TRG_ENUMERIC (vanishing two-site trace). */
+ * invariant.  HOTRG and ATRG contexts (on the factored pieces:
+ * M[a][a'] = sum_l sum G[.., a, .., l] H[l, .., a', ..] with the other legs
+ * joined; the paper follows X with ATRG too, Sec. 3.2).  Synchronises the
+ * stream.  Errors: TRG_EINVAL (bad axis), TRG_ENUMERIC (vanishing two-site
+ * trace). */
 int trg_indicator_x(trg_ctx *ctx, int axis, double *X);
 
 /* E = <H>/V = -Tr S_E / Tr T and M = <s> = Tr S_M / Tr T (impure-tensor

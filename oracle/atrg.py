@@ -512,6 +512,22 @@ class AtrgResult:
     steps: list
     energy: float = float("nan")
     magnetization: float = float("nan")
+    G: np.ndarray = None
+    H: np.ndarray = None
+
+
+def dense_tensor(G: np.ndarray, H: np.ndarray) -> np.ndarray:
+    """sum_l G[b..., l] H[l, f...] with the legs interleaved per axis
+    (b_0, f_0, b_1, f_1, ...), the layout of the HOTRG tensors."""
+    d = G.ndim - 1
+    T = np.tensordot(G, H, axes=([d], [0]))
+    return np.transpose(T, [x for a in range(d) for x in (a, d + a)])
+
+
+def indicator_x(G: np.ndarray, H: np.ndarray, axis: int = 0) -> float:
+    """The degeneracy indicator X (Sec. 3.1, defined as for HOTRG) of the
+    factored tensor, evaluated on its dense form."""
+    return hotrg.indicator_x(dense_tensor(G, H), axis)
 
 
 def run(beta: float, h: float, d: int, dcut: int, L: int, p=None, q=None, seed: int = 0,
@@ -541,7 +557,7 @@ def run(beta: float, h: float, d: int, dcut: int, L: int, p=None, q=None, seed: 
         acc += 2.0 ** (-n) * math.log(c)
         steps.append(rec)
     tr = periodic_trace(G, H)
-    res = AtrgResult(acc + 2.0 ** (-(d * m)) * math.log(tr), acc, tr, steps)
+    res = AtrgResult(acc + 2.0 ** (-(d * m)) * math.log(tr), acc, tr, steps, G=G, H=H)
     if impure:
         res.energy = -periodic_trace(*imps[0]) / tr
         res.magnetization = periodic_trace(*imps[1]) / tr

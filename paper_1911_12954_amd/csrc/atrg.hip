@@ -832,6 +832,22 @@ double atrg_impurity_trace(trg_ctx &c, int j) {
   return v;
 }
 
+// Indicator matrix of the factored tensor: the legs of `axis` open, every
+// other axis' backward leg (in G) joined to its forward leg (in H), the bond
+// l summed: one GEMM with K = r prod_{nu != axis} d_nu
+void atrg_indicator_traces(trg_ctx &c, int axis, double *M, double *out) {
+  const int d = c.d;
+  std::vector<std::pair<std::string, int64_t>> lg, lh{{"l", c.r}};
+  for (int a = 0; a < d; ++a) {
+    lg.push_back({a == axis ? std::string("x") : nm("t", a), c.dims[a]});
+    lh.push_back({a == axis ? std::string("xp") : nm("t", a), c.dims[a]});
+  }
+  lg.push_back({"l", c.r});
+  einsum2(c, static_cast<const double *>(c.G.ptr), contiguous(lg), static_cast<const double *>(c.H.ptr),
+          contiguous(lh), M, {"x", "xp"}, TRG_FP64, "ind");
+  indicator_reduce(M, c.dims[axis], out, c.st);
+}
+
 void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
   const int d = c.d;
   const int r = c.r;

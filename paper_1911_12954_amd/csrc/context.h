@@ -193,6 +193,8 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut);
 double atrg_trace(trg_ctx &c);
 // Tr S_j = sum G_S[b, m] H_S[m, b] of ATRG impurity j (synchronises)
 double atrg_impurity_trace(trg_ctx &c, int j);
+// {Tr M, Tr(M M)} into out for M[x][x'] = sum_{l, other legs traced} G[.., x, .., l] H[l, .., x', ..]
+void atrg_indicator_traces(trg_ctx &c, int axis, double *M, double *out);
 void sync_check(trg_ctx &c);
 double *rec_d(trg_ctx &c, int n);
 int *rec_i(trg_ctx &c, int n);

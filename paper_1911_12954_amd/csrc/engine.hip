@@ -838,12 +838,14 @@ int trg_free_energy(trg_ctx *ctx, double *lnz) {
 int trg_indicator_x(trg_ctx *ctx, int axis, double *X) {
   if (!ctx || !X) return fail(ctx, TRG_EINVAL, "NULL argument");
   return guarded(ctx, [&]() -> int {
-    TRG_REQUIRE(ctx->cfg.method == TRG_HOTRG, "the indicator is computed on HOTRG contexts");
     TRG_REQUIRE(axis >= 0 && axis < ctx->d, "axis out of range");
     const int n = ctx->dims[axis];
     double *M = ctx->wsp<double>("xind_M", size_t(n) * n * 8);
     double *out = ctx->wsp<double>("xind_out", 2 * 8);
-    indicator_traces(static_cast<const double *>(ctx->T.ptr), ctx->dims, ctx->d, axis, M, out, ctx->st);
+    if (ctx->cfg.method == TRG_ATRG)
+      atrg_indicator_traces(*ctx, axis, M, out);
+    else
+      indicator_traces(static_cast<const double *>(ctx->T.ptr), ctx->dims, ctx->d, axis, M, out, ctx->st);
     sync_check(*ctx);
     double t[2];
     TRG_HIP_CHECK(hipMemcpy(t, out, 2 * 8, hipMemcpyDeviceToHost));

@@ -65,6 +65,8 @@ void scale_by_inverse(double *x, int64_t n, const double *scal, double factor, h
 // {Tr M, Tr(M M)} into out[0..1] for M[a][a'] = T with the legs of `axis`
 // open and every other axis' leg pair traced (M: dims[axis]^2 workspace)
 void indicator_traces(const double *T, const int *dims, int d, int axis, double *M, double *out, hipStream_t st);
+// {Tr M, Tr(M M)} of an n x n matrix already formed
+void indicator_reduce(const double *M, int n, double *out, hipStream_t st);
 void periodic_traces(const double *const *X, int count, const int *dims, int d, double *out,
                      hipStream_t st);
 

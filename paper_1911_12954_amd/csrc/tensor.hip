@@ -545,6 +545,11 @@ void indicator_traces(const double *T, const int *dims, int d, int axis, double 
   TRG_HIP_CHECK(hipGetLastError());
 }
 
+void indicator_reduce(const double *M, int n, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(indicator_reduce_kernel, dim3(1), dim3(256), 0, st, M, n, out);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
 void ising_init(double *T, double *SE, double *SM, int d, double beta, double h, hipStream_t st) {
   const int n = 1 << (2 * d);
   hipLaunchKernelGGL(ising_kernel, dim3((n + 255) / 256), dim3(256), 0, st, T, SE, SM, d, beta, h);

@@ -17,24 +17,29 @@ class Bisection:
 
 
 def indicator_after(beta: float, d: int, dcut: int, steps: int, precision: str = "fp64", axis: int = 0,
-                    h: float = 0.0) -> float:
-    """X of the tensor after `steps` HOTRG steps (axes cycled from 0)."""
+                    h: float = 0.0, method: str = "hotrg") -> float:
+    """X of the tensor after `steps` HOTRG (or ATRG) steps (axes cycled
+    from 0)."""
     from .trg import trg_init_ising
-    ctx = trg_init_ising(beta, h, d, dcut=dcut, precision=precision)
+    ctx = trg_init_ising(beta, h, d, dcut=dcut, precision=precision, method=method)
     try:
         for n in range(steps):
-            ctx.hotrg_step(n % d, dcut)
+            if method == "atrg":
+                ctx.atrg_step(n % d, dcut)
+            else:
+                ctx.hotrg_step(n % d, dcut)
         return ctx.indicator_x(axis)
     finally:
         ctx.close()
 
 
 def bisect_transition(d: int, dcut: int, beta_lo: float, beta_hi: float, steps: int, tol: float,
-                      precision: str = "fp64", threshold: float = 1.5, evaluate=None) -> Bisection:
+                      precision: str = "fp64", threshold: float = 1.5, evaluate=None,
+                      method: str = "hotrg") -> Bisection:
     """Halve [beta_lo, beta_hi] until it is narrower than `tol`, keeping X
     below `threshold` at beta_lo and above it at beta_hi.  `evaluate(beta)`
     replaces the GPU run (tests)."""
-    ev = evaluate or (lambda b: indicator_after(b, d, dcut, steps, precision))
+    ev = evaluate or (lambda b: indicator_after(b, d, dcut, steps, precision, method=method))
     out = Bisection(beta_lo, beta_hi)
     x_lo, x_hi = ev(beta_lo), ev(beta_hi)
     out.evaluations += [(beta_lo, x_lo), (beta_hi, x_hi)]

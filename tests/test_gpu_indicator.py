@@ -50,3 +50,21 @@ def test_gpu_bisection_brackets_the_onsager_transition():
         assert b1 == b2 and x1 == pytest.approx(x2, rel=1e-9)
     exact = 0.5 * math.log(1.0 + math.sqrt(2.0))
     assert abs(0.5 * (gpu.beta_lo + gpu.beta_hi) - exact) < 3e-4 * exact
+
+
+@pytest.mark.parametrize("d,dcut,beta,L", [(4, 4, 0.1497, 4), (2, 8, 0.44, 2 ** 6)])
+def test_atrg_indicator_matches_oracle(d, dcut, beta, L):
+    """X of the factored ATRG tensor against the oracle's X of its own run
+    (same trial matrices), on every axis."""
+    need_gpu()
+    from oracle import atrg
+    from paper_1911_12954_amd import trg_init_ising
+    announce("atrg indicator", d, dcut, beta, L)
+    r = atrg.run(beta, 0.0, d, dcut, L, seed=3)
+    ctx = trg_init_ising(beta, 0.0, d, dcut=dcut, method="atrg", seed=3)
+    m = L.bit_length() - 1
+    for n in range(1, d * m + 1):
+        ctx.atrg_step((n - 1) % d, dcut)
+    for axis in range(d):
+        assert ctx.indicator_x(axis) == pytest.approx(atrg.indicator_x(r.G, r.H, axis), rel=1e-9)
+    ctx.close()

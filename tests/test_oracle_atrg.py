@@ -165,3 +165,24 @@ def test_impure_truncated_2d_energy_near_onsager():
     r = atrg.run(K, 0.0, 2, 8, 2 ** 10, p=16, q=4, impure=True)
     assert abs(r.energy - exact.onsager_energy(K)) < 1e-2 * abs(exact.onsager_energy(K))
     assert abs(r.magnetization) < 1e-10
+
+
+# ------------------------------------------------------------- indicator X ---
+def test_indicator_on_pieces_equals_dense_definition():
+    """The factored form's X is the HOTRG definition on the dense tensor; at
+    the start it is the single-site value computed by hand."""
+    from oracle import hotrg
+    F = atrg.ising_factors(0.3, 0.0, 2)
+    T = atrg.dense_tensor(F.U, F.V)
+    assert atrg.indicator_x(F.U, F.V, 0) == hotrg.indicator_x(T, 0)
+    # M[a][a'] = sum_y T[a, a', y, y]; X = (Tr M)^2 / Tr(M M)
+    M = np.einsum("abyy->ab", T)
+    assert abs(atrg.indicator_x(F.U, F.V, 0) - np.trace(M) ** 2 / np.trace(M @ M)) < 1e-14
+
+
+@pytest.mark.parametrize("K,expect", [(1.0, 2.0), (0.1, 1.0)])
+def test_indicator_phases_2d(K, expect):
+    """Deep in the ordered phase X -> 2 (two degenerate fixed-point
+    components), deep in the disordered phase X -> 1."""
+    r = atrg.run(K, 0.0, 2, 8, 2 ** 8, p=16, q=4)
+    assert abs(atrg.indicator_x(r.G, r.H, 0) - expect) < 1e-6
