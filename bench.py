@@ -60,6 +60,7 @@ def parse():
     p.add_argument("--serve-dcuts", default="6,8,10")
     p.add_argument("--serve-k", default="4,10", help="L = 2^k, k uniform in [kmin, kmax]")
     p.add_argument("--serve-precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    p.add_argument("--serve-methods", default="hotrg", help="methods of the request stream, e.g. hotrg,atrg")
     p.add_argument("--serve-budget-gb", type=float, default=200.0)
     p.add_argument("--tc-bisect", default=None,
                    help="instead of timing: 'd,dcut,steps,beta_lo,beta_hi,tol[,method]' bisection of the "
@@ -424,6 +425,7 @@ def main():
         from paper_1911_12954_amd.serve import Server, TrgBackend
         from trg_inputs import serving_requests
         dcuts = tuple(int(x) for x in a.serve_dcuts.split(","))
+        methods = tuple(a.serve_methods.split(","))
         kmin, kmax = (int(x) for x in a.serve_k.split(","))
         budget = int(a.serve_budget_gb * 2 ** 30)
         rate, calib = a.serve_rate, None
@@ -432,43 +434,47 @@ def main():
             # L = 2^k costs about k/kmin times as much; the stream runs at 0.8
             # of the capacity these service times give
             calib = {}
-            for D in dcuts:
-                one = Server(TrgBackend(a.serve_precision), budget)
-                t = time.perf_counter()
-                one.serve([{"id": 0, "arrival": 0.0, "beta": 0.1497, "h": 0.0, "dcut": D, "L": 2 ** kmin,
-                            "method": "hotrg"}], idle_sleep=1e-4)
-                calib[D] = time.perf_counter() - t
-                one.close()
-                progress(f"calibration: Dcut {D}, L 2^{kmin} alone: {calib[D]:.3f} s")
+            for m in methods:
+                for D in dcuts:
+                    one = Server(TrgBackend(a.serve_precision), budget)
+                    t = time.perf_counter()
+                    one.serve([{"id": 0, "arrival": 0.0, "beta": 0.1497, "h": 0.0, "dcut": D, "L": 2 ** kmin,
+                                "method": m}], idle_sleep=1e-4)
+                    calib[f"{m}:{D}"] = time.perf_counter() - t
+                    one.close()
+                    progress(f"calibration: {m} Dcut {D}, L 2^{kmin} alone: {calib[f'{m}:{D}']:.3f} s")
             ks = range(kmin, kmax + 1)
-            mean_service = sum(calib[D] * k / kmin for D in dcuts for k in ks) / (len(dcuts) * len(ks))
+            mean_service = sum(v * k / kmin for v in calib.values() for k in ks) / (len(calib) * len(ks))
             rate = 0.8 / mean_service
             progress(f"calibration: mean service {mean_service:.3f} s, arrival rate {rate:.3f}/s")
         if rate < 0:
             # saturation: every request is there at the start
-            reqs = serving_requests(a.serve_n, 1.0, seed=0, dcuts=dcuts, kmin=kmin, kmax=kmax)
+            reqs = serving_requests(a.serve_n, 1.0, seed=0, dcuts=dcuts, kmin=kmin, kmax=kmax, methods=methods)
             for r in reqs:
                 r["arrival"] = 0.0
         else:
-            reqs = serving_requests(a.serve_n, rate, seed=0, dcuts=dcuts, kmin=kmin, kmax=kmax)
+            reqs = serving_requests(a.serve_n, rate, seed=0, dcuts=dcuts, kmin=kmin, kmax=kmax, methods=methods)
         srv = Server(TrgBackend(a.serve_precision), budget)
         progress(f"serving {len(reqs)} requests, window {a.serve_window} s")
         summ = srv.serve(reqs, window=a.serve_window)
         srv.close()
         by_dcut = {}
         for r in srv.results:
-            by_dcut.setdefault(r["dcut"], []).append(r["latency"])
+            key = r["dcut"] if len(methods) == 1 else f"{r['method']}:{r['dcut']}"
+            by_dcut.setdefault(key, []).append(r["latency"])
         print(json.dumps({
-            "metric": "served HOTRG solves/s and latency (continuous batching, 1 GPU)",
+            "metric": "served %s solves/s and latency (continuous batching, 1 GPU)" % "+".join(
+                m.upper() for m in methods),
             "value": summ["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
             "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
             "dtype": a.serve_precision, "data": "synthetic Poisson stream",
             "config": {"workload": "Poisson stream: beta~U[0.1490,0.1505], h in {0,1e-6,1e-5}, Dcut in %s, "
-                                   "L=2^k, k~U{%d..%d}, rate %.3f/s (<0: all at t=0), window %.0f s" %
-                                   (list(dcuts), kmin, kmax, rate, a.serve_window),
+                                   "L=2^k, k~U{%d..%d}, methods %s, rate %.3f/s (<0: all at t=0), window %.0f s" %
+                                   (list(dcuts), kmin, kmax, list(methods), rate, a.serve_window),
                        "calibration_s": calib},
             "summary": summ,
-            "completed_by_dcut": {str(k): len(v) for k, v in sorted(by_dcut.items())}}), flush=True)
+            "completed_by_dcut": {str(k): len(v) for k, v in sorted(by_dcut.items(), key=lambda kv: str(kv[0]))}}),
+              flush=True)
         return
     if a.method == "atrg":
         D = a.dcut if a.dcut != 10 else 24

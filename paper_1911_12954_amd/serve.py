@@ -1,4 +1,5 @@
-"""Continuous-batching solve server for HOTRG runs (beta/h scans around T_c).
+"""Continuous-batching solve server for HOTRG and ATRG runs (beta/h scans
+around T_c).
 
 Requests (beta, h, Dcut, L, method) arrive over time.  The server
 
@@ -15,10 +16,11 @@ Requests (beta, h, Dcut, L, method) arrive over time.  The server
   requests wait in arrival order, and one whose lane is full does not hold
   back requests of other lanes;
 * keeps each run's tensors resident until it finishes;
-* runs one lane (HIP stream) per bond dimension, so lanes of different Dcut
-  overlap on the device; inside a lane, runs whose leg dims and next axis
+* runs one lane (HIP stream) per (method, bond dimension), so lanes overlap
+  on the device; inside a HOTRG lane, runs whose leg dims and next axis
   agree are stepped together by one batched library call
-  (trg_hotrg_step_batch), otherwise one call per run;
+  (trg_hotrg_step_batch), otherwise one call per run; ATRG runs take one
+  call each (trg_atrg_step);
 * advances a lane as soon as its previous step has completed (event query,
   no global barrier), and records arrival, admission and completion times.
 
@@ -46,6 +48,7 @@ class Lane:
     stream: object
     runs: list = field(default_factory=list)
     event: object = None
+    method: str = "hotrg"
 
 
 class TrgBackend:
@@ -57,17 +60,28 @@ class TrgBackend:
         self.precision = precision
         self.d = d
 
+    def _precision(self, method):
+        """ATRG contracts in FP64 or FP32: a BF16x3 server runs its ATRG
+        requests with FP32 contractions."""
+        return "fp32" if method == "atrg" and self.precision == "bf16x3" else self.precision
+
     def resident(self, req) -> int:
         from .trg import trg_resident_bytes
-        return trg_resident_bytes(self.d, req["dcut"], self.precision, "hotrg")
+        method = req.get("method", "hotrg")
+        return trg_resident_bytes(self.d, req["dcut"], self._precision(method), method)
 
-    def workspace(self, dcut) -> int:
+    def workspace(self, dcut, method="hotrg") -> int:
         from .trg import trg_workspace_bytes
-        return trg_workspace_bytes(self.d, dcut, self.precision, "hotrg")
+        return trg_workspace_bytes(self.d, dcut, self._precision(method), method)
 
-    def step_flops(self, dcut) -> float:
-        """Join flop of one steady-state step: 2 Dcut^(4d-1)."""
-        return 2.0 * float(dcut) ** (4 * self.d - 1)
+    def step_flops(self, dcut, method="hotrg") -> float:
+        """Flop of one steady-state step: the HOTRG join 2 Dcut^(4d-1); for
+        ATRG the contraction 4 Dcut^(2d+1) plus the randomized SVD's
+        (4 Dcut + 2) products of 2 Dcut^(d+2) x 5 Dcut flop."""
+        D = float(dcut)
+        if method == "atrg":
+            return 4.0 * D ** (2 * self.d + 1) + (4.0 * D + 2.0) * 2.0 * D ** (self.d + 2) * 5.0 * D
+        return 2.0 * D ** (4 * self.d - 1)
 
     def new_lane(self, dcut):
         return self.torch.cuda.Stream()
@@ -76,8 +90,9 @@ class TrgBackend:
         """A run on the lane's stream; its join plan is sized to the lane's
         workspace, which it shares with `donor` (a live run of the lane)."""
         from .trg import trg_init_ising, trg_share_workspace
-        h = trg_init_ising(req["beta"], req["h"], self.d, dcut=req["dcut"], precision=self.precision,
-                           stream=stream, workspace_bytes=self.workspace(req["dcut"]))
+        method = req.get("method", "hotrg")
+        h = trg_init_ising(req["beta"], req["h"], self.d, dcut=req["dcut"], precision=self._precision(method),
+                           method=method, stream=stream, workspace_bytes=self.workspace(req["dcut"], method))
         if donor is not None:
             trg_share_workspace(h, donor)
         return h
@@ -85,9 +100,12 @@ class TrgBackend:
     def dims(self, h):
         return h.dims()[0]
 
-    def step(self, handles, axis, dcut):
+    def step(self, handles, axis, dcut, method="hotrg"):
         from .trg import trg_hotrg_step_batch
-        if len(handles) == 1:
+        if method == "atrg":
+            for h in handles:
+                h.atrg_step(axis, dcut)
+        elif len(handles) == 1:
             handles[0].hotrg_step(axis, dcut)
         else:
             trg_hotrg_step_batch(handles, axis, dcut)
@@ -123,29 +141,31 @@ class Server:
         self.batch_calls = 0
         self.batched_runs = 0
 
-    def _lane(self, dcut):
-        if dcut not in self.lanes:
-            self.lanes[dcut] = Lane(dcut, self.be.new_lane(dcut))
-        return self.lanes[dcut]
+    def _lane(self, method, dcut):
+        key = (method, dcut)
+        if key not in self.lanes:
+            self.lanes[key] = Lane(dcut, self.be.new_lane(dcut), method=method)
+        return self.lanes[key]
 
-    def lane_cap(self, dcut) -> int:
+    def lane_cap(self, dcut, method="hotrg") -> int:
         """Runs a lane holds at once."""
-        return max(1, min(self.max_active, int(self.round_flops // self.be.step_flops(dcut))))
+        return max(1, min(self.max_active, int(self.round_flops // self.be.step_flops(dcut, method=method))))
 
     def _admit(self, req, now):
         """Admit `req` if its lane has room and the memory fits.  Returns
         True (admitted), "lane" (its lane is full) or False (no memory)."""
+        method = req.get("method", "hotrg")
         res = self.be.resident(req)
-        ws = self.be.workspace(req["dcut"])
+        ws = self.be.workspace(req["dcut"], method=method)
         if res + ws > self.budget:
             raise ValueError(f"request {req['id']} needs {res + ws} bytes, more than the whole budget")
-        lane = self.lanes.get(req["dcut"])
-        if lane is not None and len(lane.runs) >= self.lane_cap(req["dcut"]):
+        lane = self.lanes.get((method, req["dcut"]))
+        if lane is not None and len(lane.runs) >= self.lane_cap(req["dcut"], method):
             return "lane"
         need = res + (0 if lane is not None and lane.runs else ws)
         if self.used + need > self.budget:
             return False
-        lane = self._lane(req["dcut"])
+        lane = self._lane(method, req["dcut"])
         donor = lane.runs[0].handle if lane.runs else None
         h = self.be.create(req, lane.stream, donor)
         m = req["L"].bit_length() - 1
@@ -171,11 +191,12 @@ class Server:
                 self.results.append({"id": run.req["id"], "lnz": lnz, "arrival": run.req["arrival"],
                                      "admitted": run.t_admit, "done": t_done,
                                      "latency": t_done - run.req["arrival"], "dcut": run.req["dcut"],
+                                     "method": lane.method,
                                      "L": run.req["L"], "beta": run.req["beta"], "h": run.req["h"]})
             else:
                 still.append(run)
         if had_runs and not still:
-            self.used -= self.be.workspace(lane.dcut)   # the last user freed it
+            self.used -= self.be.workspace(lane.dcut, method=lane.method)   # the last user freed it
         lane.runs = still
         if not still:
             return True
@@ -187,7 +208,7 @@ class Server:
         for (dims, axis), runs in groups.items():
             for i in range(0, len(runs), self.max_batch):
                 chunk = runs[i:i + self.max_batch]
-                self.be.step([r.handle for r in chunk], axis, lane.dcut)
+                self.be.step([r.handle for r in chunk], axis, lane.dcut, method=lane.method)
                 self.batch_calls += 1
                 self.batched_runs += len(chunk)
                 for r in chunk:
@@ -256,5 +277,5 @@ class Server:
                 self.be.close(run.handle)
                 self.used -= self.be.resident(run.req)
             if lane.runs:
-                self.used -= self.be.workspace(lane.dcut)
+                self.used -= self.be.workspace(lane.dcut, method=lane.method)
             lane.runs = []

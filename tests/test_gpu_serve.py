@@ -3,7 +3,7 @@ are bit-for-bit those of the same runs alone, and one of them matches the
 oracle."""
 import pytest
 
-from oracle import hotrg
+from oracle import atrg, hotrg
 from tests.gpu_util import announce, need_gpu
 
 pytestmark = pytest.mark.gpu
@@ -75,3 +75,32 @@ def test_shared_workspace_gives_the_same_bits():
         trg.trg_share_workspace(e, other)
     other.close()
     e.close()
+
+
+MIX_METHODS = [
+    {"id": 0, "arrival": 0.00, "beta": 0.1490, "h": 0.0, "dcut": 4, "L": 8, "method": "atrg"},
+    {"id": 1, "arrival": 0.00, "beta": 0.1497, "h": 1e-3, "dcut": 4, "L": 4, "method": "atrg"},
+    {"id": 2, "arrival": 0.00, "beta": 0.1497, "h": 1e-3, "dcut": 4, "L": 4, "method": "hotrg"},
+    {"id": 3, "arrival": 0.01, "beta": 0.1505, "h": 0.0, "dcut": 6, "L": 4, "method": "atrg"},
+    {"id": 4, "arrival": 0.01, "beta": 0.1500, "h": 0.0, "dcut": 4, "L": 8, "method": "hotrg"},
+]
+
+
+def test_atrg_and_hotrg_requests_in_one_stream():
+    """ATRG requests get their own lanes next to the HOTRG ones; every result
+    equals the run alone, and an ATRG one equals the oracle (same trial
+    matrices, seed 0)."""
+    need_gpu()
+    from paper_1911_12954_amd.serve import Server, TrgBackend
+    announce("serve methods")
+    srv = Server(TrgBackend("fp64"), 64 * 2 ** 30)
+    out = srv.serve(MIX_METHODS)
+    assert out["completed"] == len(MIX_METHODS)
+    assert {k[0] for k in srv.lanes} == {"hotrg", "atrg"}
+    mix = {r["id"]: r["lnz"] for r in srv.results}
+    for req in MIX_METHODS:
+        alone = Server(TrgBackend("fp64"), 64 * 2 ** 30)
+        alone.serve([dict(req, arrival=0.0)])
+        assert alone.results[0]["lnz"] == mix[req["id"]], req
+    r = atrg.run(0.1497, 1e-3, 4, 4, 4)
+    assert abs(mix[1] - r.ln_z_per_site) <= 1e-10 * abs(r.ln_z_per_site)

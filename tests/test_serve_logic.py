@@ -29,10 +29,10 @@ class FakeBackend:
     def resident(self, req):
         return 10 * req["dcut"] ** 8
 
-    def workspace(self, dcut):
+    def workspace(self, dcut, method="hotrg"):
         return dcut ** 9
 
-    def step_flops(self, dcut):
+    def step_flops(self, dcut, method="hotrg"):
         return 2.0 * dcut ** 15
 
     def new_lane(self, dcut):
@@ -50,8 +50,8 @@ class FakeBackend:
     def dims(self, h):
         return tuple(h.dims)
 
-    def step(self, handles, axis, dcut):
-        self.calls.append((len(handles), axis, dcut))
+    def step(self, handles, axis, dcut, method="hotrg"):
+        self.calls.append((len(handles), axis, dcut, method))
         for h in handles:
             for a in range(4):
                 if a != axis:
@@ -101,7 +101,7 @@ def test_same_shape_runs_share_calls():
     be = FakeBackend(lag=1)
     srv = Server(be, 10 ** 12)
     srv.serve(reqs, idle_sleep=0)
-    assert all(n == 5 for n, _, _ in be.calls)
+    assert all(n == 5 for n, _, _, _ in be.calls)
     assert len(be.calls) == 16
 
 
@@ -172,4 +172,20 @@ def test_lane_cap_bounds_a_round_and_keeps_arrival_order():
     # the Dcut 4 runs were admitted at once, beside the first Dcut 8 run
     assert all(res[3 + i]["admitted"] < res[0]["done"] for i in range(3))
     # calls on the Dcut 8 lane step one run
-    assert all(n == 1 for n, _, dc in be.calls if dc == 8)
+    assert all(n == 1 for n, _, dc, _ in be.calls if dc == 8)
+
+
+def test_methods_get_separate_lanes():
+    """HOTRG and ATRG requests of one Dcut go to two lanes; both complete
+    with d log2 L steps each, and no call mixes the methods."""
+    reqs = [{"id": i, "arrival": 0.0, "beta": 0.149, "h": 0.0, "dcut": 6, "L": 16,
+             "method": "atrg" if i % 2 else "hotrg"} for i in range(6)]
+    be = FakeBackend()
+    srv = Server(be, 10 ** 12)
+    out = srv.serve(reqs, idle_sleep=0)
+    assert out["completed"] == 6
+    assert set(srv.lanes) == {("hotrg", 6), ("atrg", 6)}
+    assert {r["method"] for r in srv.results} == {"hotrg", "atrg"}
+    for r in srv.results:
+        assert r["lnz"] == pytest.approx(r["beta"] + 16)
+    assert {c[3] for c in be.calls} == {"hotrg", "atrg"}

@@ -65,11 +65,12 @@ def decaying_site_tensor(dims, seed: int, rank: int = 20, ratio: float = 0.8, no
 
 
 def serving_requests(n: int, rate: float, seed: int, dcuts=(6, 8, 10), kmin: int = 4, kmax: int = 10,
-                     fields=(0.0, 1e-6, 1e-5), beta_range=(0.1490, 0.1505)):
-    """A Poisson stream of n HOTRG solve requests (arrival rate `rate` per
+                     fields=(0.0, 1e-6, 1e-5), beta_range=(0.1490, 0.1505), methods=("hotrg",)):
+    """A Poisson stream of n solve requests (arrival rate `rate` per
     second): beta ~ U[beta_range], h uniform on `fields`, Dcut uniform on
-    `dcuts`, L = 2^k with k ~ U{kmin..kmax}.  Returns dicts sorted by arrival
-    time (seconds from the start)."""
+    `dcuts`, L = 2^k with k ~ U{kmin..kmax}, method uniform on `methods`
+    (one method: the stream of a single method).  Returns dicts sorted by
+    arrival time (seconds from the start)."""
     rng = np.random.default_rng(seed)
     t = np.cumsum(rng.exponential(1.0 / rate, size=n))
     out = []
@@ -81,6 +82,6 @@ def serving_requests(n: int, rate: float, seed: int, dcuts=(6, 8, 10), kmin: int
             "h": float(fields[rng.integers(len(fields))]),
             "dcut": int(dcuts[rng.integers(len(dcuts))]),
             "L": int(2 ** rng.integers(kmin, kmax + 1)),
-            "method": "hotrg",
+            "method": methods[0] if len(methods) == 1 else str(methods[rng.integers(len(methods))]),
         })
     return out
