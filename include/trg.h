@@ -204,6 +204,22 @@ int trg_get_tensor(trg_ctx *ctx, int which, double *host_out, size_t cap);
 int trg_get_isometry(trg_ctx *ctx, int nu, double *host_U, size_t capU,
                      double *host_spectrum, size_t capS);
 
+/* Checkpoint of a context (the state after step n: the tensors -- T and the
+ * impure S for HOTRG, the pieces G, H and each impurity's pair for ATRG --,
+ * the free-energy accumulator, n, dims, the step records and the settings
+ * that fix the numerics).  trg_export_state with host_buf NULL stores the
+ * blob size in *size; otherwise it writes the blob (cap >= *size, else
+ * TRG_EINVAL) to caller-owned host memory.  Synchronises.
+ * trg_import_state creates a context from such a blob; the blob fixes method,
+ * precision, dcut, impurities, RSVD settings and seed, cfg (may be NULL)
+ * contributes the stream, allocator and workspace budget.  Stepping the
+ * imported context gives the bits of the uninterrupted run.  The last ATRG
+ * swap spectrum and the latest isometries are not part of the state.
+ * Errors: TRG_EINVAL (NULL, bad magic, version or size, inconsistent
+ * header), TRG_ENOMEM, TRG_EHIP. */
+int trg_export_state(trg_ctx *ctx, void *host_buf, size_t cap, size_t *size);
+int trg_import_state(trg_ctx **out, const void *host_buf, size_t size, const trg_config *cfg);
+
 /* Copy up to cap step records (oldest first); *n receives the count. */
 int trg_step_log(trg_ctx *ctx, trg_step_rec *out, int cap, int *n);
 

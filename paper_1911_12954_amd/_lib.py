@@ -72,6 +72,8 @@ SIGNATURES = {
                                    C.POINTER(C.c_double), C.c_size_t]),
     "trg_step_log": (C.c_int, [C.c_void_p, C.POINTER(TrgStepRec), C.c_int, C.POINTER(C.c_int)]),
     "trg_accumulator": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "trg_export_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "trg_import_state": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.POINTER(TrgConfig)]),
     "trg_indicator_x": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double)]),
     "trg_footprint_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint]),
     "trg_resident_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint]),

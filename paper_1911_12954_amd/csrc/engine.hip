@@ -944,6 +944,193 @@ int trg_get_isometry(trg_ctx *ctx, int nu, double *host_U, size_t capU, double *
   });
 }
 
+// ------------------------------------------------------------ checkpoint ---
+namespace {
+struct StateHeader {
+  char magic[8];
+  uint32_t version, impure;
+  int32_t d, method, precision, dcut, rsvd_p, rsvd_q, fp64_steps, nsteps, nimp, r, force_side;
+  int32_t imp_kind[2], imp_r[2], dims[4];
+  uint64_t seed, rec_bytes, nhost, ndoubles;
+};
+constexpr char STATE_MAGIC[8] = {'T', 'R', 'G', 'S', 'T', 'A', 'T', 'E'};
+constexpr uint32_t STATE_VERSION = 1;
+
+// the device buffers of the state, in blob order, with their sizes in doubles
+std::vector<std::pair<void *, size_t>> state_tensors(trg_ctx &c) {
+  std::vector<std::pair<void *, size_t>> v;
+  if (c.cfg.method == TRG_ATRG) {
+    int64_t n = 1;
+    for (int a = 0; a < c.d; ++a) n *= c.dims[a];
+    v.push_back({c.G.ptr, size_t(n) * c.r});
+    v.push_back({c.H.ptr, size_t(n) * c.r});
+    for (int j = 0; j < c.nimp; ++j) {
+      v.push_back({c.S[j].ptr, size_t(n) * c.imp_r[j]});
+      v.push_back({c.Sn[j].ptr, size_t(n) * c.imp_r[j]});
+    }
+  } else {
+    v.push_back({c.T.ptr, size_t(c.total())});
+    for (int j = 0; j < c.nimp; ++j) v.push_back({c.S[j].ptr, size_t(c.total())});
+  }
+  return v;
+}
+}  // namespace
+
+int trg_export_state(trg_ctx *ctx, void *host_buf, size_t cap, size_t *size) {
+  if (!ctx || !size) return fail(ctx, TRG_EINVAL, "NULL argument");
+  return guarded(ctx, [&]() -> int {
+    sync_check(*ctx);
+    const auto ten = state_tensors(*ctx);
+    size_t nd = 0;
+    for (const auto &t : ten) nd += t.second;
+    const size_t rec_bytes = size_t(ctx->nsteps + 1) * REC_BYTES;
+    const size_t total = sizeof(StateHeader) + 16 * 8 + rec_bytes + ctx->host_rec.size() * sizeof(trg_step_rec) +
+                         nd * 8;
+    *size = total;
+    if (!host_buf) return TRG_OK;
+    TRG_REQUIRE(cap >= total, "state buffer too small");
+    StateHeader h{};
+    std::memcpy(h.magic, STATE_MAGIC, 8);
+    h.version = STATE_VERSION;
+    h.impure = ctx->cfg.impure;
+    h.d = ctx->d;
+    h.method = ctx->cfg.method;
+    h.precision = ctx->cfg.precision;
+    h.dcut = ctx->cfg.dcut;
+    h.rsvd_p = ctx->cfg.rsvd_p;
+    h.rsvd_q = ctx->cfg.rsvd_q;
+    h.fp64_steps = ctx->cfg.fp64_steps;
+    h.nsteps = ctx->nsteps;
+    h.nimp = ctx->nimp;
+    h.r = ctx->r;
+    h.force_side = ctx->force_side;
+    for (int j = 0; j < 2; ++j) {
+      h.imp_kind[j] = ctx->imp_kind[j];
+      h.imp_r[j] = ctx->imp_r[j];
+    }
+    for (int a = 0; a < 4; ++a) h.dims[a] = ctx->dims[a];
+    h.seed = ctx->cfg.seed;
+    h.rec_bytes = rec_bytes;
+    h.nhost = ctx->host_rec.size();
+    h.ndoubles = nd;
+    char *p = static_cast<char *>(host_buf);
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    TRG_HIP_CHECK(hipMemcpy(p, ctx->dev_scalars.ptr, 16 * 8, hipMemcpyDeviceToHost));
+    p += 16 * 8;
+    TRG_HIP_CHECK(hipMemcpy(p, ctx->dev_rec.ptr, rec_bytes, hipMemcpyDeviceToHost));
+    p += rec_bytes;
+    if (!ctx->host_rec.empty()) std::memcpy(p, ctx->host_rec.data(), ctx->host_rec.size() * sizeof(trg_step_rec));
+    p += ctx->host_rec.size() * sizeof(trg_step_rec);
+    for (const auto &t : ten) {
+      TRG_HIP_CHECK(hipMemcpy(p, t.first, t.second * 8, hipMemcpyDeviceToHost));
+      p += t.second * 8;
+    }
+    return TRG_OK;
+  });
+}
+
+int trg_import_state(trg_ctx **out, const void *host_buf, size_t size, const trg_config *cfg) {
+  if (!out || !host_buf) return fail(nullptr, TRG_EINVAL, "NULL argument");
+  *out = nullptr;
+  trg_ctx *c = nullptr;
+  int rc = guarded(nullptr, [&]() -> int {
+    TRG_REQUIRE(size >= sizeof(StateHeader), "state blob too short");
+    StateHeader h{};
+    std::memcpy(&h, host_buf, sizeof h);
+    TRG_REQUIRE(std::memcmp(h.magic, STATE_MAGIC, 8) == 0, "not a state blob (bad magic)");
+    TRG_REQUIRE(h.version == STATE_VERSION, "unsupported state blob version");
+    TRG_REQUIRE(h.d >= 2 && h.d <= 4 && h.nsteps >= 0 && h.nimp >= 0 && h.nimp <= 2, "corrupt state header");
+    TRG_REQUIRE(h.rec_bytes == size_t(h.nsteps + 1) * REC_BYTES, "corrupt state header (records)");
+    for (int a = 0; a < h.d; ++a) TRG_REQUIRE(h.dims[a] >= 1 && h.dims[a] <= 1024, "corrupt state header (dims)");
+    const size_t need = sizeof(StateHeader) + 16 * 8 + h.rec_bytes + h.nhost * sizeof(trg_step_rec) + h.ndoubles * 8;
+    TRG_REQUIRE(size == need, "state blob size does not match its header");
+    // the blob fixes the numerics; cfg may bring the stream, allocator and
+    // workspace budget
+    trg_config k = cfg ? *cfg : trg_config{};
+    k.method = h.method;
+    k.precision = h.precision;
+    k.dcut = h.dcut;
+    k.impure = h.impure;
+    k.rsvd_p = h.rsvd_p;
+    k.rsvd_q = h.rsvd_q;
+    k.fp64_steps = h.fp64_steps;
+    k.seed = h.seed;
+    validate_cfg(&k, h.d);
+    c = new_ctx(h.d, &k);
+    for (int a = 0; a < h.d; ++a) c->dims[a] = h.dims[a];
+    c->nsteps = h.nsteps;
+    c->nimp = h.nimp;
+    c->r = h.r;
+    c->force_side = h.force_side;
+    for (int j = 0; j < 2; ++j) {
+      c->imp_kind[j] = h.imp_kind[j];
+      c->imp_r[j] = h.imp_r[j];
+    }
+    for (int j = 0; j < c->nimp; ++j) {
+      TRG_REQUIRE(c->imp_kind[j] == 0 || c->imp_kind[j] == 1, "corrupt state header (impurity)");
+      c->has_e = c->has_e || c->imp_kind[j] == 0;
+      c->has_m = c->has_m || c->imp_kind[j] == 1;
+    }
+    init_common(*c);
+    ensure_records(*c, h.nsteps + 2);
+    auto ten = [&]() {
+      std::vector<size_t> v;
+      int64_t n = 1, tot = 1;
+      for (int a = 0; a < h.d; ++a) {
+        n *= h.dims[a];
+        tot *= int64_t(h.dims[a]) * h.dims[a];
+      }
+      if (h.method == TRG_ATRG) {
+        v.push_back(size_t(n) * h.r);
+        v.push_back(size_t(n) * h.r);
+        for (int j = 0; j < h.nimp; ++j) {
+          v.push_back(size_t(n) * h.imp_r[j]);
+          v.push_back(size_t(n) * h.imp_r[j]);
+        }
+      } else {
+        for (int j = 0; j <= h.nimp; ++j) v.push_back(size_t(tot));
+      }
+      return v;
+    }();
+    size_t nd = 0;
+    for (size_t x : ten) nd += x;
+    TRG_REQUIRE(nd == h.ndoubles, "state blob tensor sizes do not match its header");
+    if (h.method == TRG_ATRG) {
+      c->ensure(c->G, ten[0] * 8);
+      c->ensure(c->H, ten[1] * 8);
+      for (int j = 0; j < c->nimp; ++j) {
+        c->ensure(c->S[j], ten[2 + 2 * j] * 8);
+        c->ensure(c->Sn[j], ten[3 + 2 * j] * 8);
+      }
+    } else {
+      c->ensure(c->T, ten[0] * 8);
+      for (int j = 0; j < c->nimp; ++j) c->ensure(c->S[j], ten[1 + j] * 8);
+    }
+    // the zero fills and allocations above are queued on the context's stream
+    TRG_HIP_CHECK(hipStreamSynchronize(c->st));
+    const char *p = static_cast<const char *>(host_buf) + sizeof h;
+    TRG_HIP_CHECK(hipMemcpy(c->dev_scalars.ptr, p, 16 * 8, hipMemcpyHostToDevice));
+    p += 16 * 8;
+    TRG_HIP_CHECK(hipMemcpy(c->dev_rec.ptr, p, h.rec_bytes, hipMemcpyHostToDevice));
+    p += h.rec_bytes;
+    c->host_rec.resize(h.nhost);
+    if (h.nhost) std::memcpy(c->host_rec.data(), p, h.nhost * sizeof(trg_step_rec));
+    p += h.nhost * sizeof(trg_step_rec);
+    for (const auto &t : state_tensors(*c)) {
+      TRG_HIP_CHECK(hipMemcpy(t.first, p, t.second * 8, hipMemcpyHostToDevice));
+      p += t.second * 8;
+    }
+    return TRG_OK;
+  });
+  if (rc != TRG_OK) {
+    if (c) trg_free(c);
+    return rc;
+  }
+  *out = c;
+  return TRG_OK;
+}
+
 int trg_step_log(trg_ctx *ctx, trg_step_rec *out, int cap, int *n) {
   if (!ctx || !n) return fail(ctx, TRG_EINVAL, "NULL argument");
   return guarded(ctx, [&]() -> int {

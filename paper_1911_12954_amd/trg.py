@@ -123,6 +123,14 @@ class Context:
     def free_energy(self) -> float:
         return self._dbl(_lib().trg_free_energy)
 
+    def export_state(self) -> bytes:
+        """Checkpoint blob of the current state (trg_export_state)."""
+        n = C.c_size_t()
+        _err(_lib().trg_export_state(self.handle, None, 0, C.byref(n)), self.handle)
+        buf = C.create_string_buffer(n.value)
+        _err(_lib().trg_export_state(self.handle, buf, n.value, C.byref(n)), self.handle)
+        return buf.raw[:n.value]
+
     def impure_energy(self) -> float:
         return self._dbl(_lib().trg_impure_energy)
 
@@ -241,6 +249,24 @@ def trg_init_tensor(T: np.ndarray, **cfg) -> Context:
     ctx = Context(h_, keep + [conf], d)
     ctx._initial_dims = tuple(T.shape[2 * a] for a in range(d))
     return ctx
+
+
+def trg_export_state(ctx: Context) -> bytes:
+    return ctx.export_state()
+
+
+def trg_import_state(blob: bytes, **cfg) -> Context:
+    """Context from a checkpoint blob; cfg contributes the stream, allocator
+    and workspace budget (the blob fixes the numerics)."""
+    import struct
+    if len(blob) < 20:
+        raise TrgError(L.TRG_EINVAL, "state blob too short")
+    d = struct.unpack_from("<i", blob, 16)[0]
+    conf, keep = make_config(**cfg)
+    h_ = C.c_void_p()
+    buf = C.create_string_buffer(blob, len(blob))
+    _err(_lib().trg_import_state(C.byref(h_), buf, len(blob), C.byref(conf)))
+    return Context(h_, keep + [conf], d)
 
 
 def trg_init_factors(G: np.ndarray, H: np.ndarray, **cfg) -> Context:

@@ -91,6 +91,12 @@ def test_more_argument_checks_on_the_host(lib):
     cfg.method, cfg.impure = L.TRG_ATRG, L.TRG_IMPURE_E
     assert lib.trg_init_ising(C.byref(h), 0.0, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
     assert b"beta > 0" in lib.trg_last_error(None)
+    # checkpoint blobs are validated before any device work
+    assert lib.trg_import_state(C.byref(h), None, 0, None) == L.TRG_EINVAL
+    junk = C.create_string_buffer(b"NOTSTATE" + bytes(200))
+    assert lib.trg_import_state(C.byref(h), junk, 208, None) == L.TRG_EINVAL
+    assert b"magic" in lib.trg_last_error(None)
+    assert lib.trg_import_state(C.byref(h), junk, 4, None) == L.TRG_EINVAL
     cfg = L.TrgConfig()
     cfg.dcut = 2000
     assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
