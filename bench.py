@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--compare", default="fp64,fp32",
                    help="other join precisions timed for one step each (comma list, '' = none)")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    p.add_argument("--impure", action="store_true",
+                   help="time the step with the impure E and M tensors (five joins per step)")
     p.add_argument("--cpu-sample-blocks", type=int, default=1)
     p.add_argument("--method", default="hotrg", choices=["hotrg", "atrg"],
                    help="atrg: time steady-state ATRG steps (default Dcut 24 there) instead of HOTRG")
@@ -254,11 +256,11 @@ def progress(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def time_steps(precision, dcut, beta, warmup, steps):
+def time_steps(precision, dcut, beta, warmup, steps, impure=False):
     import torch
     from paper_1911_12954_amd import trg_init_ising
     d = 4
-    ctx = trg_init_ising(beta, 0.0, d, dcut=dcut, precision=precision)
+    ctx = trg_init_ising(beta, 0.0, d, dcut=dcut, precision=precision, impure=("E", "M") if impure else ())
     n = 0
     # ramp: legs grow 2 -> 4 -> ... -> dcut
     while min(ctx.dims()[0]) < dcut or n < d:
@@ -495,14 +497,17 @@ def main():
                          "gemm_share_of_step": ms * 1e-3 / el}}), flush=True)
         return
     D = a.dcut
-    elapsed, join_ms, launches, lnz = time_steps(a.precision, D, a.beta, a.warmup, a.steps)
+    elapsed, join_ms, launches, lnz = time_steps(a.precision, D, a.beta, a.warmup, a.steps, a.impure)
     steps_per_s = a.steps / elapsed
-    alg_flops_step = 2.0 * D ** 15
+    # each impure tensor adds the joins C(S, T) and C(T, S)
+    joins_per_step = 5 if a.impure else 1
+    alg_flops_step = 2.0 * D ** 15 * joins_per_step
     mult = 3.0 if a.precision == "bf16x3" else 1.0   # BF16 MFMA products per multiply-add
     achieved = alg_flops_step * a.steps / (join_ms * 1e-3) / 1e12 if join_ms > 0 else None
     peak = PEAK_TFLOPS[a.precision]
     out = {
-        "metric": "4D HOTRG RG-steps/s at Dcut=%d (steady-state step, 1 GPU)" % D,
+        "metric": "4D HOTRG RG-steps/s at Dcut=%d (steady-state step%s, 1 GPU)" % (
+            D, ", impure E and M" if a.impure else ""),
         "value": steps_per_s,
         "unit": "RG-steps/s",
         "n_gpus": 1,
@@ -515,8 +520,9 @@ def main():
         "dtype": {"bf16x3": "bf16x3 (bf16 MFMA, fp32 accumulate; fp64 Gram/eigh/norm)",
                   "fp32": "fp32 (fp32 MFMA; fp64 Gram/eigh/norm)", "fp64": "fp64"}[a.precision],
         "data": "synthetic (closed-form 4D Ising tensor, beta=%.4f, h=0)" % a.beta,
-        "config": {"workload": "4D Ising HOTRG, Dcut=%d, steady-state coarse-graining step, beta=%.4f, h=0, "
-                               "join precision %s" % (D, a.beta, a.precision),
+        "config": {"workload": "4D Ising HOTRG, Dcut=%d, steady-state coarse-graining step%s, beta=%.4f, h=0, "
+                               "join precision %s" % (D, " with impure E and M (5 joins)" if a.impure else "",
+                                                      a.beta, a.precision),
                    "dcut": D, "join_precision": a.precision, "lnZ_per_site_after_run": lnz},
         "roofline": {
             "bound": "mfma",
@@ -525,8 +531,9 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": (achieved / peak) if achieved else None,
-            "traffic": JOIN_TRAFFIC.get((a.precision, D), {}).get("bytes_per_launch"),
-            "traffic_algorithmic": JOIN_TRAFFIC.get((a.precision, D), {}).get("algorithmic_bytes_per_launch"),
+            "traffic": None if a.impure else JOIN_TRAFFIC.get((a.precision, D), {}).get("bytes_per_launch"),
+            "traffic_algorithmic": None if a.impure else
+            JOIN_TRAFFIC.get((a.precision, D), {}).get("algorithmic_bytes_per_launch"),
             "join_launches": launches,
             "join_ms_per_step": join_ms / a.steps,
             "join_share_of_step": (join_ms * 1e-3) / elapsed,
@@ -536,7 +543,7 @@ def main():
     }
     others = {}
     for prec in [x for x in a.compare.split(",") if x in PEAK_TFLOPS and x != a.precision]:
-        e, jm, nl, _ = time_steps(prec, D, a.beta, 0, 1)
+        e, jm, nl, _ = time_steps(prec, D, a.beta, 0, 1, a.impure)
         ach = alg_flops_step / (jm * 1e-3) / 1e12
         others[prec] = {"rg_steps_per_s": 1.0 / e, "join_tflops": ach, "frac_of_peak": ach / PEAK_TFLOPS[prec]}
     if others:
