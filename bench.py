@@ -82,8 +82,8 @@ def parse():
                         "of the Dcut = 10 step): the BF16x3 join kernel against one plain BF16 torch.matmul "
                         "(hipBLASLt) of the same shape, in MFMA TFLOP/s issued")
     p.add_argument("--accuracy", default=None,
-                   help="instead of timing: run 'dcut,L,beta,h' in FP64, FP32 and BF16x3 with impure E and M "
-                        "and print the relative errors of f, E, M against the FP64 path")
+                   help="instead of timing: run 'dcut,L,beta,h[,pure]' in FP64, FP32 and BF16x3 with impure E "
+                        "and M (not with 'pure') and print the relative errors of f, E, M against the FP64 path")
     p.add_argument("--accuracy-variants", default="fp32:0,bf16x3:0",
                    help="precision:fp64_steps pairs compared with the FP64 path")
     return p.parse_args()
@@ -147,22 +147,25 @@ def accuracy(spec, variants):
     number of leading steps joined in FP64 (fp64_steps)."""
     import torch
     from paper_1911_12954_amd import trg_init_ising
-    dcut, L, beta, h = spec.split(",")
-    dcut, L, beta, h = int(dcut), int(L), float(beta), float(h)
+    fields = spec.split(",")
+    pure = len(fields) > 4 and fields[4] == "pure"
+    dcut, L, beta, h = int(fields[0]), int(fields[1]), float(fields[2]), float(fields[3])
     runs = [("fp64", 0)] + [(v.split(":")[0], int(v.split(":")[1])) for v in variants.split(",") if v]
     res = {}
     for prec, n64 in runs:
         key = prec if n64 == 0 else f"{prec}+fp64x{n64}"
         t0 = time.perf_counter()
-        ctx = trg_init_ising(beta, h, 4, dcut=dcut, precision=prec, impure=("E", "M"), fp64_steps=n64)
+        ctx = trg_init_ising(beta, h, 4, dcut=dcut, precision=prec, impure=() if pure else ("E", "M"),
+                             fp64_steps=n64)
         m = L.bit_length() - 1
         for n in range(1, 4 * m + 1):
             ctx.hotrg_step((n - 1) % 4, dcut)
-            if n % 4 == 0:
+            if n % 2 == 0:
                 ctx.sync()
                 progress(f"accuracy {key}: step {n}/{4 * m} at {time.perf_counter() - t0:.1f} s")
         log = ctx.step_log()
-        res[key] = {"f": ctx.free_energy(), "E": ctx.impure_energy(), "M": ctx.impure_magnetization(),
+        res[key] = {"f": ctx.free_energy(), "E": float("nan") if pure else ctx.impure_energy(),
+                    "M": float("nan") if pure else ctx.impure_magnetization(),
                     "seconds": time.perf_counter() - t0,
                     "fp64_join_steps": sum(r.join_precision == "fp64" for r in log),
                     "degenerate_cuts": sum(sum(r.degenerate_cut) for r in log)}
@@ -170,7 +173,8 @@ def accuracy(spec, variants):
         torch.cuda.empty_cache()
         progress(f"accuracy {key}: {res[key]}")
     ref = res["fp64"]
-    out = {"workload": f"4D Ising HOTRG Dcut={dcut} L={L} beta={beta} h={h}, impure E and M", "runs": res}
+    out = {"workload": f"4D Ising HOTRG Dcut={dcut} L={L} beta={beta} h={h}, "
+                       + ("ln Z/V only" if pure else "impure E and M"), "runs": res}
     for key in res:
         if key == "fp64":
             continue
