@@ -74,6 +74,10 @@ def parse():
     p.add_argument("--copy-cal", type=float, default=0.0,
                    help="only copy this many GiB device to device three times (calibration of the "
                         "FETCH_SIZE / WRITE_SIZE counters)")
+    p.add_argument("--atrg-scan", default=None,
+                   help="instead of timing: 'dcut;L;beta0,dbeta,n;precisions' (e.g. '24;1024;0.1490,0.0001,4;"
+                        "fp64,fp32'): ATRG ln Z/V over a beta scan in each contraction precision, with the "
+                        "FP32 - FP64 differences")
     p.add_argument("--atrg-impure", default=None,
                    help="instead of timing: 'd;T;h;L;dcuts;hotrg_dcut' (e.g. '4;6.64;0;1024;8,12,16;8'): E and M "
                         "by ATRG impure tensors for each Dcut next to HOTRG's at hotrg_dcut (0: none) (FP64)")
@@ -180,6 +184,38 @@ def accuracy(spec, variants):
             continue
         out[f"rel_err_{key}"] = {k: abs(res[key][k] - ref[k]) / max(abs(ref[k]), 1e-300) for k in ("f", "E", "M")}
         out[f"abs_err_{key}"] = {k: abs(res[key][k] - ref[k]) for k in ("f", "E", "M")}
+    return out
+
+
+def atrg_scan(spec):
+    """ATRG free energy over a beta scan (h = 0, p = 4 Dcut, q = 2 Dcut) for
+    each contraction precision, run after run on one GPU."""
+    import torch
+    from paper_1911_12954_amd import trg_init_ising
+    dcut, L, betas, precs = spec.split(";")
+    dcut, L = int(dcut), int(L)
+    b0, db, nb = betas.split(",")
+    betas = [float(b0) + i * float(db) for i in range(int(nb))]
+    precs = precs.split(",")
+    out = {"workload": f"4D Ising ATRG Dcut={dcut} L={L} h=0, beta scan", "runs": []}
+    for beta in betas:
+        row = {"beta": beta}
+        for prec in precs:
+            t0 = time.perf_counter()
+            ctx = trg_init_ising(beta, 0.0, 4, dcut=dcut, precision=prec, method="atrg")
+            m = L.bit_length() - 1
+            for n in range(1, 4 * m + 1):
+                ctx.atrg_step((n - 1) % 4, dcut)
+                if n % 8 == 0:
+                    progress(f"atrg-scan: beta {beta:.5f} {prec} step {n}/{4 * m} lnZ/V {ctx.free_energy():.12f} "
+                             f"at {time.perf_counter() - t0:.1f} s")
+            row[prec] = ctx.free_energy()
+            row[prec + "_seconds"] = time.perf_counter() - t0
+            ctx.close()
+            torch.cuda.empty_cache()
+        if "fp64" in row and "fp32" in row:
+            row["rel_diff_fp32"] = abs(row["fp32"] - row["fp64"]) / abs(row["fp64"])
+        out["runs"].append(row)
     return out
 
 
@@ -395,6 +431,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
+        return
+    if a.atrg_scan:
+        print(json.dumps(atrg_scan(a.atrg_scan)), flush=True)
         return
     if a.atrg_impure:
         print(json.dumps(atrg_impure(a.atrg_impure)), flush=True)
