@@ -1,5 +1,5 @@
-"""Write oracle_values.json: HOTRG results of the FP64 oracle for small,
-fully specified runs, used as stored expected values by the GPU tests.
+"""Write oracle_values.json: HOTRG and ATRG results of the FP64 oracle for
+small, fully specified runs, used as stored expected values by the GPU tests.
 
 Run from the repository root:  python tests/golden/make_golden.py
 Calls nothing but `oracle/`."""
@@ -10,7 +10,7 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import hotrg  # noqa: E402
+from oracle import atrg, hotrg  # noqa: E402
 
 CASES = [
     # (name, beta, h, d, dcut, L)
@@ -21,11 +21,25 @@ CASES = [
 ]
 
 
+ATRG_CASES = [
+    # (name, beta, h, d, dcut, L, seed); p = 4 dcut, q = 2 dcut
+    ("atrg_4d_dcut4_L4_h1e-3", 0.1497, 1e-3, 4, 4, 4, 5),
+    ("atrg_2d_dcut8_L64_h1e-2", 0.4000, 1e-2, 2, 8, 64, 1),
+]
+
+
 def main():
-    out = {"source": "oracle/hotrg.py run(beta, h, d, dcut, L, impure=True), FP64", "cases": {}}
+    out = {"source": "oracle/hotrg.py run(beta, h, d, dcut, L, impure=True) and oracle/atrg.py "
+                     "run(beta, h, d, dcut, L, seed=seed, impure=True), FP64", "cases": {}}
     for name, beta, h, d, dcut, L in CASES:
         r = hotrg.run(beta, h, d, dcut, L, impure=True)
         out["cases"][name] = {"beta": beta, "h": h, "d": d, "dcut": dcut, "L": L,
+                              "ln_z_per_site": repr(r.ln_z_per_site), "energy": repr(r.energy),
+                              "magnetization": repr(r.magnetization)}
+        print(name, out["cases"][name], flush=True)
+    for name, beta, h, d, dcut, L, seed in ATRG_CASES:
+        r = atrg.run(beta, h, d, dcut, L, seed=seed, impure=True)
+        out["cases"][name] = {"method": "atrg", "beta": beta, "h": h, "d": d, "dcut": dcut, "L": L, "seed": seed,
                               "ln_z_per_site": repr(r.ln_z_per_site), "energy": repr(r.energy),
                               "magnetization": repr(r.magnetization)}
         print(name, out["cases"][name], flush=True)

@@ -7,7 +7,7 @@ import os
 
 import pytest
 
-from oracle import hotrg
+from oracle import atrg, hotrg
 
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
@@ -23,6 +23,15 @@ def test_stored_oracle_values_are_reproduced(name):
     r = hotrg.run(c["beta"], c["h"], c["d"], c["dcut"], c["L"], impure=True)
     assert r.ln_z_per_site == pytest.approx(float(c["ln_z_per_site"]), rel=1e-13, abs=0)
     assert r.energy == pytest.approx(float(c["energy"]), rel=1e-12, abs=0)
+    assert r.magnetization == pytest.approx(float(c["magnetization"]), rel=1e-10, abs=1e-13)
+
+
+@pytest.mark.parametrize("name", ["atrg_4d_dcut4_L4_h1e-3", "atrg_2d_dcut8_L64_h1e-2"])
+def test_stored_atrg_oracle_values_are_reproduced(name):
+    c = _oracle_values()[name]
+    r = atrg.run(c["beta"], c["h"], c["d"], c["dcut"], c["L"], seed=c["seed"], impure=True)
+    assert r.ln_z_per_site == pytest.approx(float(c["ln_z_per_site"]), rel=1e-12, abs=0)
+    assert r.energy == pytest.approx(float(c["energy"]), rel=1e-10, abs=0)
     assert r.magnetization == pytest.approx(float(c["magnetization"]), rel=1e-10, abs=1e-13)
 
 

@@ -138,3 +138,19 @@ def test_impurities_leave_the_pure_atrg_run_unchanged():
     a = _gpu_run(0.1497, 1e-3, 4, 4, 4, seed=5)
     b = _gpu_impure(0.1497, 1e-3, 4, 4, 4, seed=5)
     assert a["f"] == b["f"]
+
+
+@pytest.mark.parametrize("name", ["atrg_4d_dcut4_L4_h1e-3", "atrg_2d_dcut8_L64_h1e-2"])
+def test_impure_matches_stored_oracle_values(name):
+    """The GPU path against the stored oracle values of tests/golden
+    (written by the oracle alone)."""
+    import json
+    import os
+    need_gpu()
+    announce("atrg golden", name)
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_values.json")) as f:
+        c = json.load(f)["cases"][name]
+    g = _gpu_impure(c["beta"], c["h"], c["d"], c["dcut"], c["L"], seed=c["seed"])
+    assert abs(g["f"] - float(c["ln_z_per_site"])) <= 1e-10 * abs(float(c["ln_z_per_site"]))
+    assert abs(g["E"] - float(c["energy"])) <= 1e-9 * abs(float(c["energy"]))
+    assert abs(g["M"] - float(c["magnetization"])) <= 1e-9 * abs(float(c["magnetization"]))
