@@ -162,9 +162,12 @@ int trg_init_factors(trg_ctx **out, int d, const int *dims, int r, const double 
 /* Singular values (descending, *n of them) of the latest ATRG swap. */
 int trg_atrg_spectrum(trg_ctx *ctx, double *out, int cap, int *n);
 
-/* Coarse-grain the periodic lattice L^d (L = 2^m, m >= 1): d*m steps along
- * axis (n-1) mod d with cfg->dcut, using the context's method.  Synchronises
- * once at the end and returns TRG_ENUMERIC if a step failed. */
+/* Coarse-grain the periodic lattice L^d (L = 2^m, m >= 1): steps n along
+ * axis (n-1) mod d with cfg->dcut, using the context's method, from the
+ * context's next step up to n = d*m (all d*m steps for a fresh context; a
+ * context imported from a checkpoint finishes the lattice).  TRG_EINVAL if
+ * the context is already past d*m steps.  Synchronises once at the end and
+ * returns TRG_ENUMERIC if a step failed. */
 int trg_run(trg_ctx *ctx, long long L);
 
 /* ln Z / V of the periodic lattice whose single block is the current tensor:

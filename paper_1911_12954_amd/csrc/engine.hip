@@ -793,7 +793,9 @@ int trg_run(trg_ctx *ctx, long long L) {
     TRG_REQUIRE(L >= 2 && (L & (L - 1)) == 0, "L must be a power of two >= 2");
     int m = 0;
     while ((1LL << m) < L) ++m;
-    for (int n = 1; n <= ctx->d * m; ++n) {
+    TRG_REQUIRE(ctx->nsteps <= ctx->d * m, "the context has already taken more steps than this lattice needs");
+    // continues from the current step (a resumed checkpoint finishes its lattice)
+    for (int n = ctx->nsteps + 1; n <= ctx->d * m; ++n) {
       if (ctx->cfg.method == TRG_ATRG)
         atrg_step_impl(*ctx, (n - 1) % ctx->d, ctx->cfg.dcut);
       else

@@ -58,3 +58,22 @@ def test_export_size_query_and_short_buffer():
     assert lib.trg_export_state(a.handle, buf, n.value - 1, C.byref(n)) == L.TRG_EINVAL
     assert len(a.export_state()) == n.value
     a.close()
+
+
+def test_run_continues_an_imported_checkpoint():
+    """trg_run on an imported context takes the remaining steps of the
+    lattice and ends on the bits of the uninterrupted run."""
+    need_gpu()
+    from paper_1911_12954_amd import trg_import_state, trg_init_ising
+    announce("checkpoint run")
+    a = trg_init_ising(0.1497, 1e-4, 4, dcut=4, impure=("E", "M"))
+    a.run(8)
+    straight = _observables(a)
+    a.close()
+    b = trg_init_ising(0.1497, 1e-4, 4, dcut=4, impure=("E", "M"))
+    _steps(b, "hotrg", 4, 4, 0, 7)
+    c = trg_import_state(b.export_state())
+    b.close()
+    c.run(8)
+    assert _observables(c) == straight
+    c.close()
