@@ -117,3 +117,57 @@ def test_jacobi_eigh(n):
         assert np.all(np.diff(w[b]) <= 0)
         assert np.allclose(V[b].T @ V[b], np.eye(n), atol=1e-13)
         assert np.allclose(V[b] @ np.diag(w[b]) @ V[b].T, A[b], atol=1e-13 * nrm)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_gemm_empty_products(precision):
+    """K = 0: C is zeroed (or left as it was when accumulating); M = 0 or
+    N = 0: nothing is written."""
+    torch = need_gpu()
+    from paper_1911_12954_amd import trg_gemm, trg_gemm_tile
+    announce("gemm empty", precision)
+    tm, tn, _ = trg_gemm_tile(precision)
+    ct = torch.float64 if precision == "fp64" else torch.float32
+    st = torch.cuda.current_stream().cuda_stream
+    dummy = torch.zeros(16, dtype=torch.float64, device="cuda")
+    C = torch.full((tm, tn), 3.0, dtype=ct, device="cuda")
+    trg_gemm(precision, dummy.data_ptr(), dummy.data_ptr(), C.data_ptr(), tm, tn, 0, 16, 16, tn, True, st)
+    torch.cuda.synchronize()
+    assert bool((C == 3.0).all())
+    trg_gemm(precision, dummy.data_ptr(), dummy.data_ptr(), C.data_ptr(), tm, tn, 0, 16, 16, tn, False, st)
+    torch.cuda.synchronize()
+    assert bool((C == 0.0).all())
+    C.fill_(5.0)
+    trg_gemm(precision, dummy.data_ptr(), dummy.data_ptr(), C.data_ptr(), 0, tn, 32, 32, 32, tn, False, st)
+    trg_gemm(precision, dummy.data_ptr(), dummy.data_ptr(), C.data_ptr(), tm, 0, 32, 32, 32, tn, False, st)
+    torch.cuda.synchronize()
+    assert bool((C == 5.0).all())
+
+
+@pytest.mark.parametrize("n", [16, 200])
+def test_eigh_degenerate_and_zero_matrices(n):
+    """Exactly repeated eigenvalues (any orthonormal basis of the eigenspace
+    is correct: check the eigenvalues, orthonormality and reconstruction)
+    and the zero matrix, on both solver paths."""
+    torch = need_gpu()
+    from paper_1911_12954_amd import trg_eigh
+    announce("eigh degenerate", n)
+    rng = np.random.default_rng(n)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.repeat(np.array([3.0, 1.0, -2.0, 0.5]), n // 4)
+    A = np.stack([Q @ np.diag(lam) @ Q.T, np.eye(n), np.zeros((n, n))])
+    A = 0.5 * (A + A.transpose(0, 2, 1))
+    dA = torch.from_numpy(A.copy()).cuda()
+    dw = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    dV = torch.empty((3, n, n), dtype=torch.float64, device="cuda")
+    ds = torch.empty(3, dtype=torch.int32, device="cuda")
+    trg_eigh(dA.data_ptr(), dw.data_ptr(), dV.data_ptr(), ds.data_ptr(), n, 3,
+             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    w, V = dw.cpu().numpy(), dV.cpu().numpy()
+    for b in range(3):
+        ref = np.sort(np.linalg.eigvalsh(A[b]))[::-1]
+        scale = max(np.linalg.norm(A[b]), 1.0)
+        assert np.max(np.abs(w[b] - ref)) < 1e-13 * scale
+        assert np.allclose(V[b].T @ V[b], np.eye(n), atol=1e-13)
+        assert np.allclose(V[b] @ np.diag(w[b]) @ V[b].T, A[b], atol=1e-13 * scale)
