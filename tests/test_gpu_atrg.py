@@ -154,3 +154,15 @@ def test_impure_matches_stored_oracle_values(name):
     assert abs(g["f"] - float(c["ln_z_per_site"])) <= 1e-10 * abs(float(c["ln_z_per_site"]))
     assert abs(g["E"] - float(c["energy"])) <= 1e-9 * abs(float(c["energy"]))
     assert abs(g["M"] - float(c["magnetization"])) <= 1e-9 * abs(float(c["magnetization"]))
+
+
+def test_impure_fp32_contraction_error():
+    """ATRG impurities with the contraction GEMMs in FP32 against FP64 (4D,
+    Dcut 6, 16 steps, h = 1e-3)."""
+    need_gpu()
+    announce("atrg impure fp32 contraction")
+    a = _gpu_impure(0.1497, 1e-3, 4, 6, 16)
+    b = _gpu_impure(0.1497, 1e-3, 4, 6, 16, precision="fp32")
+    err = {k: abs(a[k] - b[k]) / abs(a[k]) for k in ("f", "E", "M")}
+    print(f"[atrg impure fp32] rel err {err}", flush=True)
+    assert err["f"] < 1e-6 and err["E"] < 1e-4 and err["M"] < 1e-3
