@@ -312,10 +312,16 @@ def _pieces(F: Factors, X, sig, Y, mu: int):
     return G, H
 
 
-def isometries(G: np.ndarray, H: np.ndarray, mu: int, d: int, dcut: int):
-    """HOSVD isometries P_nu from the Gram matrices of sum_l G H over the
-    backward pair (b^A_nu, b^B_nu) (legs of G) and the forward pair (f^A_nu,
-    f^B_nu) (legs of H); same selection rule as HOTRG."""
+def grams(G: np.ndarray, H: np.ndarray, mu: int, d: int):
+    """Gram matrices of the two-site tensor sum_l G[.., l] H[l, ..] (HOSVD of
+    two adjacent decomposed tensors, Sec. 2, Fig. 2B), for every transverse
+    axis nu in axis order: (backward, forward), each (d_nu^2) x (d_nu^2).
+
+    Backward pair (b^A_nu, b^B_nu), legs of G: the other legs of G are summed
+    directly, and H enters through its own Gram Wf[l, l'] = sum_f H[l, f]
+    H[l', f].  Forward pair (f^A_nu, f^B_nu), legs of H: likewise with
+    Wb[l, l'] = sum_b G[b, l] G[b, l'].  Both are exact regroupings of
+    M M^T for the two-site tensor M with that pair as its row index."""
     perp = [a for a in range(d) if a != mu]
     # leg positions: G = [bA_0..bA_{d-1}, bB_perp..., l]; H = [l, fA_perp..., fB_0..fB_{d-1}]
     Wf = np.tensordot(H, H, axes=(list(range(1, H.ndim)), list(range(1, H.ndim))))   # [l, l']
@@ -324,14 +330,12 @@ def isometries(G: np.ndarray, H: np.ndarray, mu: int, d: int, dcut: int):
     L = string.ascii_letters
     for j, nu in enumerate(perp):
         dn = G.shape[nu]
-        grams = []
         # backward pair: G legs nu (site A) and d + j (site B)
         sub1 = list(L[: G.ndim])
         sub2 = list(sub1)
         sub2[nu], sub2[d + j], sub2[-1] = "W", "X", "Y"
         gb = np.einsum("".join(sub1) + "," + "".join(sub2) + "," + sub1[-1] + "Y" + "->" +
                        sub1[nu] + sub1[d + j] + "WX", G, G, Wf, optimize=True)
-        grams.append(gb.reshape(dn * dn, dn * dn))
         # forward pair: H legs 1 + j (site A) and 1 + (d - 1) + nu (site B)
         a_pos, b_pos = 1 + j, d + nu
         sub1 = list(L[: H.ndim])
@@ -339,11 +343,22 @@ def isometries(G: np.ndarray, H: np.ndarray, mu: int, d: int, dcut: int):
         sub2[a_pos], sub2[b_pos], sub2[0] = "W", "X", "Y"
         gf = np.einsum(sub1[0] + "Y" + "," + "".join(sub1) + "," + "".join(sub2) + "->" +
                        sub1[a_pos] + sub1[b_pos] + "WX", Wb, H, H, optimize=True)
-        grams.append(gf.reshape(dn * dn, dn * dn))
+        out.append((gb.reshape(dn * dn, dn * dn), gf.reshape(dn * dn, dn * dn)))
+    return out
+
+
+def isometries(G: np.ndarray, H: np.ndarray, mu: int, d: int, dcut: int):
+    """HOSVD isometries P_nu from the Gram matrices of sum_l G H over the
+    backward pair (b^A_nu, b^B_nu) (legs of G) and the forward pair (f^A_nu,
+    f^B_nu) (legs of H); same selection rule as HOTRG."""
+    perp = [a for a in range(d) if a != mu]
+    out = []
+    for nu, pair in zip(perp, grams(G, H, mu, d)):
+        dn = G.shape[nu]
         n = dn * dn
         k = min(n, dcut)
         res = []
-        for g in grams:
+        for g in pair:
             w, v = hotrg._eig_desc(g)
             res.append((w, v, float(np.sum(np.maximum(w[k:], 0.0)))))
         eps_b, eps_f = res[0][2], res[1][2]

@@ -22,17 +22,16 @@ Readings of details the paper leaves to its references (listed in the design doc):
   eps^s = sum of the discarded max(lambda, 0).  The forward side is used
   unless eps^- < (1 - 1e-10) eps^+.
 * The sign of each eigenvector and the basis of each degenerate eigenspace
-  (neighbouring eigenvalues within 1e-6 lambda_max) are fixed canonically:
+  (neighbouring eigenvalues within 1e-10 lambda_max) are fixed canonically:
   the basis is built from the eigenspace's projector P by taking P e_r /
   sqrt(P_rr) for the first coordinate r of largest remaining weight (ties
   within a relative 1e-9 go to the lowest index), then deflating.  Inside the
   kept space this is gauge freedom (f, E, M and ln c_n do not depend on it);
   when the cut splits a degenerate eigenspace it decides which vectors are
-  kept, and fixing it makes that choice reproducible.  The 1e-6 window is
-  wider than the perturbation that FP32 rounding of the join leaves on the
-  Gram spectrum (about 1e-7 lambda_max), so rounding does not decide which
-  vector of a degenerate pair survives a cut; merging a genuine gap below
-  1e-6 lambda_max changes the truncation error by less than that gap.
+  kept, and fixing it makes that choice reproducible.  The window only has
+  to hold the degeneracies that a symmetry makes exact, which FP64 rounding
+  leaves as gaps of about 1e-17 lambda_max; every gap above it is resolved
+  by plain truncated HOSVD (the leading k eigenvectors).
 * The same U_nu[a, b, k] (a from site 1, b from site 2) compresses both the
   backward pair and the forward pair of legs along nu.
 * Normalisation c_n = Frobenius norm; ln Z/V = sum_{n=0}^{N} 2^{-n} ln c_n
@@ -54,7 +53,7 @@ SIDE_FORWARD = 1
 TIE_REL = 1e-10          # side-rule tie window
 SIGN_REL = 1e-9          # sign-fix tie window
 DEGEN_REL = 1e-8         # degenerate-cut flag
-CLUSTER_REL = 1e-6       # eigenvalues closer than this * lambda_max are degenerate
+CLUSTER_REL = 1e-10      # eigenvalues closer than this * lambda_max are degenerate
 
 
 def transverse_axes(d: int, mu: int):

@@ -186,3 +186,50 @@ def test_indicator_phases_2d(K, expect):
     components), deep in the disordered phase X -> 1."""
     r = atrg.run(K, 0.0, 2, 8, 2 ** 8, p=16, q=4)
     assert abs(atrg.indicator_x(r.G, r.H, 0) - expect) < 1e-6
+
+
+def _explicit_two_site_gram(G, H, mu, d, j, nu, side):
+    """Gram of one leg pair of the dense two-site tensor M = sum_l G H, built
+    by one plain einsum and a reshape (no regrouping): M has the legs
+    (bA_0..bA_{d-1}, bB_perp..., fA_perp..., fB_0..fB_{d-1})."""
+    M = np.tensordot(G, H, axes=([G.ndim - 1], [0]))
+    if side == 0:
+        pos = (nu, d + j)                          # bA_nu, bB_nu
+    else:
+        pos = (2 * d - 1 + j, 3 * d - 2 + nu)      # fA_nu, fB_nu
+    Mm = np.moveaxis(M, pos, (0, 1))
+    n = Mm.shape[0] * Mm.shape[1]
+    Mm = Mm.reshape(n, -1)
+    return Mm @ Mm.T
+
+
+@pytest.mark.parametrize("d,dims,mu,r", [(2, (3, 2), 0, 3), (2, (2, 3), 1, 4), (3, (2, 3, 2), 1, 3),
+                                         (3, (3, 2, 2), 0, 2), (4, (2, 3, 2, 2), 2, 3), (4, (2, 2, 3, 2), 0, 2)])
+def test_hosvd_grams_equal_explicit_two_site_gram(d, dims, mu, r):
+    """HOSVD of two adjacent decomposed tensors (Sec. 2, Fig. 2B): the
+    factored Grams of both leg pairs equal M M^T of the explicit two-site
+    tensor, and the selected isometry spans the leading eigenvectors of the
+    explicit Gram (with the truncation error computed from it)."""
+    rng = np.random.default_rng(17 + d)
+    perp = [a for a in range(d) if a != mu]
+    G = rng.standard_normal(tuple(dims) + tuple(dims[a] for a in perp) + (r,))
+    H = rng.standard_normal((r,) + tuple(dims[a] for a in perp) + tuple(dims))
+    got = atrg.grams(G, H, mu, d)
+    dcut = 3
+    choices = atrg.isometries(G, H, mu, d, dcut)
+    for j, nu in enumerate(perp):
+        ref = [_explicit_two_site_gram(G, H, mu, d, j, nu, s) for s in (0, 1)]
+        for s in (0, 1):
+            assert np.allclose(got[j][s], ref[s], rtol=0, atol=1e-12 * np.abs(ref[s]).max())
+        ch = choices[j]
+        n = dims[nu] ** 2
+        k = min(n, dcut)
+        spectra = [np.sort(np.linalg.eigvalsh(g))[::-1] for g in ref]
+        for s in (0, 1):
+            assert abs(ch.eps[s] - np.sum(np.maximum(spectra[s][k:], 0.0))) <= 1e-10 * spectra[s][0]
+        w, v = np.linalg.eigh(ref[ch.side])
+        lead = v[:, np.argsort(-w)[:k]]
+        w_sorted = np.sort(w)[::-1]
+        assert k == n or w_sorted[k - 1] - w_sorted[k] > 1e-6 * w_sorted[0]
+        U = ch.U.reshape(n, k)
+        assert np.allclose(U @ U.T, lead @ lead.T, atol=1e-10)
