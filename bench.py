@@ -26,7 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
+# BF16 MFMA products per multiply-add of the split joins
+SPLIT_PRODUCTS = {"bf16x3": 3.0, "bf16x6": 6.0}
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per join launch of the steady Dcut 10 step (three full x0 slices
 # and one of a single x0 value per step, averaged), from rocprofv3 FETCH_SIZE
@@ -42,7 +44,7 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--dcut", type=int, default=10)
-    p.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    p.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     p.add_argument("--beta", type=float, default=0.1497)
     p.add_argument("--compare", default="fp64,fp32",
                    help="other join precisions timed for one step each (comma list, '' = none)")
@@ -61,7 +63,7 @@ def parse():
     p.add_argument("--serve-window", type=float, default=60.0)
     p.add_argument("--serve-dcuts", default="6,8,10")
     p.add_argument("--serve-k", default="4,10", help="L = 2^k, k uniform in [kmin, kmax]")
-    p.add_argument("--serve-precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    p.add_argument("--serve-precision", default="fp32", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     p.add_argument("--serve-methods", default="hotrg", help="methods of the request stream, e.g. hotrg,atrg")
     p.add_argument("--serve-budget-gb", type=float, default=200.0)
     p.add_argument("--tc-bisect", default=None,
@@ -82,9 +84,9 @@ def parse():
                    help="instead of timing: 'd;T;h;L;dcuts;hotrg_dcut' (e.g. '4;6.64;0;1024;8,12,16;8'): E and M "
                         "by ATRG impure tensors for each Dcut next to HOTRG's at hotrg_dcut (0: none) (FP64)")
     p.add_argument("--vendor-gemm", default=None,
-                   help="instead of timing the step: 'M,N,K' (e.g. '30208,100096,100000', the full-slice join "
-                        "of the Dcut = 10 step): the BF16x3 join kernel against one plain BF16 torch.matmul "
-                        "(hipBLASLt) of the same shape, in MFMA TFLOP/s issued")
+                   help="instead of timing the step: 'M,N,K[,precision]' (e.g. '30208,100096,100000', the "
+                        "full-slice join of the Dcut = 10 step): the BF16x3 (or bf16x6) join kernel against one "
+                        "plain BF16 torch.matmul (hipBLASLt) of the same shape, in MFMA TFLOP/s issued")
     p.add_argument("--accuracy", default=None,
                    help="instead of timing: run 'dcut,L,beta,h[,pure]' in FP64, FP32 and BF16x3 with impure E "
                         "and M (not with 'pure') and print the relative errors of f, E, M against the FP64 path")
@@ -94,35 +96,41 @@ def parse():
 
 
 def vendor_gemm(spec):
-    """Issue rate of the BF16x3 join kernel (three BF16 products per
+    """Issue rate of a split-BF16 join kernel (three or six BF16 products per
     multiply-add) next to a plain BF16 GEMM of the vendor library at one
     shape: both run the same MFMA instruction class, so the two TFLOP/s
-    figures say how close the hand-written kernel comes to the library."""
+    figures say how close the hand-written kernel comes to the library.
+    spec: 'M,N,K[,precision]' (precision bf16x3, the default, or bf16x6)."""
     import torch
     from paper_1911_12954_amd import trg_gemm, trg_gemm_tile
-    M, N, K = (int(x) for x in spec.split(","))
-    tm, tn, tk = trg_gemm_tile("bf16x3")
+    fields = spec.split(",")
+    M, N, K = (int(x) for x in fields[:3])
+    prec = fields[3] if len(fields) > 3 else "bf16x3"
+    planes, mult = {"bf16x3": (2, 3.0), "bf16x6": (3, 6.0)}[prec]
+    tm, tn, tk = trg_gemm_tile(prec)
     assert M % tm == 0 and N % tn == 0 and K % tk == 0, "M, N, K must be multiples of the join tile"
-    out = {"metric": "BF16 MFMA issue rate at the join shape", "M": M, "N": N, "K": K, "unit": "TFLOP/s"}
+    out = {"metric": "BF16 MFMA issue rate at the join shape", "M": M, "N": N, "K": K, "unit": "TFLOP/s",
+           "join_precision": prec}
     g = torch.Generator(device="cuda")
     g.manual_seed(1)
-    # two bf16 planes (hi, lo) per operand, values in [1, 2)
-    A = torch.randint(0x3F80, 0x4000, (2, M, K), dtype=torch.int16, device="cuda", generator=g)
-    Bt = torch.randint(0x3F80, 0x4000, (2, N, K), dtype=torch.int16, device="cuda", generator=g)
+    # bf16 planes per operand, values in [1, 2)
+    A = torch.randint(0x3F80, 0x4000, (planes, M, K), dtype=torch.int16, device="cuda", generator=g)
+    Bt = torch.randint(0x3F80, 0x4000, (planes, N, K), dtype=torch.int16, device="cuda", generator=g)
     Cm = torch.empty(M, N, dtype=torch.float32, device="cuda")
     ms = []
     for _ in range(3):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record()
-        trg_gemm("bf16x3", A.data_ptr(), Bt.data_ptr(), Cm.data_ptr(), M, N, K, K, K, N)
+        trg_gemm(prec, A.data_ptr(), Bt.data_ptr(), Cm.data_ptr(), M, N, K, K, K, N)
         e1.record()
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
     t = min(ms)
-    out["join_bf16x3_ms"] = t
-    out["join_bf16x3_issued_tflops"] = 3 * 2.0 * M * N * K / (t * 1e-3) / 1e12
-    progress(f"vendor-gemm: join kernel {t:.1f} ms")
+    out["join_ms"] = t
+    out["join_issued_tflops"] = mult * 2.0 * M * N * K / (t * 1e-3) / 1e12
+    out["join_algorithmic_tflops"] = 2.0 * M * N * K / (t * 1e-3) / 1e12
+    progress(f"vendor-gemm: {prec} join kernel {t:.1f} ms")
     del A, Bt, Cm
     torch.cuda.empty_cache()
     x = torch.randn(M, K, dtype=torch.bfloat16, device="cuda", generator=g)
@@ -140,7 +148,7 @@ def vendor_gemm(spec):
     t = min(ms)
     out["torch_matmul_bf16_ms"] = t
     out["torch_matmul_bf16_tflops"] = 2.0 * M * N * K / (t * 1e-3) / 1e12
-    out["join_vs_library"] = out["join_bf16x3_issued_tflops"] / out["torch_matmul_bf16_tflops"]
+    out["join_vs_library"] = out["join_issued_tflops"] / out["torch_matmul_bf16_tflops"]
     out["peak"] = 2500.0
     return out
 
@@ -545,7 +553,7 @@ def main():
     # each impure tensor adds the joins C(S, T) and C(T, S)
     joins_per_step = 5 if a.impure else 1
     alg_flops_step = 2.0 * D ** 15 * joins_per_step
-    mult = 3.0 if a.precision == "bf16x3" else 1.0   # BF16 MFMA products per multiply-add
+    mult = SPLIT_PRODUCTS.get(a.precision, 1.0)   # BF16 MFMA products per multiply-add
     achieved = alg_flops_step * a.steps / (join_ms * 1e-3) / 1e12 if join_ms > 0 else None
     peak = PEAK_TFLOPS[a.precision]
     out = {
@@ -561,6 +569,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"bf16x3": "bf16x3 (bf16 MFMA, fp32 accumulate; fp64 Gram/eigh/norm)",
+                  "bf16x6": "bf16x6 (bf16 MFMA, fp32 groups of 128 summed in fp64; fp64 Gram/eigh/norm)",
                   "fp32": "fp32 (fp32 MFMA; fp64 Gram/eigh/norm)", "fp64": "fp64"}[a.precision],
         "data": "synthetic (closed-form 4D Ising tensor, beta=%.4f, h=0)" % a.beta,
         "config": {"workload": "4D Ising HOTRG, Dcut=%d, steady-state coarse-graining step%s, beta=%.4f, h=0, "

@@ -49,8 +49,13 @@ enum {
 enum {
   TRG_FP64 = 0,     /* FP64 operands, FP64 MFMA, FP64 result */
   TRG_FP32 = 1,     /* operands rounded to FP32, FP32 MFMA, FP32 result */
-  TRG_BF16X3 = 2    /* operands split a = hi + lo (two BF16), hi*hi + hi*lo +
+  TRG_BF16X3 = 2,   /* operands split a = hi + lo (two BF16), hi*hi + hi*lo +
                        lo*hi on BF16 MFMA with FP32 accumulation */
+  TRG_BF16X6 = 3    /* operands rounded to FP32 and split exactly into three
+                       BF16 planes, fl32(a) = hi + mid + lo; the six products
+                       hi*hi + hi*mid + mid*hi + mid*mid + hi*lo + lo*hi on
+                       BF16 MFMA, summed in FP32 over groups of 128 K elements
+                       and the groups in FP64; FP32 result */
 };
 
 enum { TRG_HOTRG = 0, TRG_ATRG = 1 };
@@ -59,7 +64,8 @@ enum { TRG_HOTRG = 0, TRG_ATRG = 1 };
 enum { TRG_IMPURE_E = 1u, TRG_IMPURE_M = 2u };
 
 typedef struct trg_config {
-  int precision;          /* TRG_FP64 (default), TRG_FP32, TRG_BF16X3 */
+  int precision;          /* TRG_FP64 (default), TRG_FP32, TRG_BF16X3, TRG_BF16X6
+                             (HOTRG; ATRG takes TRG_FP64 or TRG_FP32) */
   int method;             /* TRG_HOTRG (default) or TRG_ATRG */
   int dcut;               /* bond dimension used by trg_run; > 0 */
   unsigned impure;        /* TRG_IMPURE_E | TRG_IMPURE_M, or 0 */
@@ -95,7 +101,7 @@ typedef struct trg_step_rec {
   int kept[4];            /* kept columns k_nu; 0 on the coarse-grained axis */
   int degenerate_cut[4];  /* 1 if the cut splits a degenerate eigenspace */
   int sweeps[4];          /* Jacobi sweeps used (chosen side) */
-  int join_precision;     /* TRG_FP64 / TRG_FP32 / TRG_BF16X3 of this step's join */
+  int join_precision;     /* TRG_FP64 / TRG_FP32 / TRG_BF16X3 / TRG_BF16X6 of this step's join */
   double ln_c;            /* ln of the Frobenius norm c_n of the new tensor */
   double eps[4][2];       /* discarded eigenvalue sum, [axis][backward, forward] */
   double seconds;         /* host wall time between launch of the step and the
@@ -127,9 +133,18 @@ int trg_init_tensor(trg_ctx **out, int d, const int *dims, const double *host_te
  * c_n.  Asynchronous.  Errors: TRG_EINVAL, TRG_ESTATE, TRG_ENOMEM, TRG_EHIP. */
 int trg_hotrg_step(trg_ctx *ctx, int axis, int dcut);
 
-/* The same step for n contexts that share d, precision and current dims and
- * the same stream: every kernel of the step is launched once for all n
- * (batched launches).  Results are identical to n separate calls. */
+/* The same step for n distinct contexts that share d, join precision,
+ * current dims and the stream.  The Gram eigendecompositions of all n
+ * contexts (every transverse axis, both sides) run in one batched launch;
+ * the Gram products, the operand builds, the joins, the post-join maps and
+ * the normalisations are then enqueued context by context on the shared
+ * stream (through the shared workspace when trg_share_workspace was used).
+ * Results are bit-identical to n separate trg_hotrg_step calls.
+ * Errors: TRG_EINVAL (NULL or duplicate context, mismatched contexts, bad
+ * axis or dcut) and TRG_ESTATE (a poisoned context) leave every context
+ * unchanged.  TRG_EHIP or TRG_ENUMERIC poisons every context of the batch.
+ * TRG_ENOMEM during the contraction can leave the first contexts stepped and
+ * the rest not; trg_get_dims' step count tells which. */
 int trg_hotrg_step_batch(trg_ctx *const *ctxs, int n, int axis, int dcut);
 
 /* ATRG step along `axis` (Sec. 2, Fig. 2) with bond dimension `dcut`
@@ -264,11 +279,13 @@ const char *trg_last_error(const trg_ctx *ctx);
 /* C[m][n] (+)= sum_k A[m][k] * Bt[n][k] for the join GEMM (Sec. 2: the
  * D^{4d-1} contraction).  A is M x K with row stride lda, Bt is N x K with row
  * stride ldb, C is M x N with row stride ldc.  M, N must be multiples of the
- * tile (trg_gemm_tile), K a multiple of 16 (FP64/FP32) or 32 (BF16X3); the
+ * tile (trg_gemm_tile), K a multiple of trg_gemm_tile's K granule; the
  * caller zero-pads.  precision selects the element types: FP64 (double in,
  * double out), FP32 (float in, float out), BF16X3 (A = A_hi, A + M*lda
- * elements = A_lo, likewise for Bt; bf16 in, float out).  accumulate != 0 adds
- * to C.  Returns TRG_EINVAL on shape violations. */
+ * elements = A_lo, likewise for Bt; bf16 in, float out), BF16X6 (three
+ * planes M*lda elements apart: A_hi, A_mid, A_lo; likewise for Bt; bf16 in,
+ * float out).  accumulate != 0 adds to C.  Returns TRG_EINVAL on shape
+ * violations. */
 int trg_gemm(int precision, const void *A, const void *Bt, void *C, long long M, long long N,
              long long K, long long lda, long long ldb, long long ldc, int accumulate,
              void *stream);

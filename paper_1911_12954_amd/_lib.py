@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtrg.so")
 
 TRG_OK, TRG_EINVAL, TRG_ENOMEM, TRG_EHIP, TRG_ESTATE, TRG_ENUMERIC = 0, -1, -2, -3, -4, -5
-TRG_FP64, TRG_FP32, TRG_BF16X3 = 0, 1, 2
+TRG_FP64, TRG_FP32, TRG_BF16X3, TRG_BF16X6 = 0, 1, 2, 3
 TRG_HOTRG, TRG_ATRG = 0, 1
 TRG_IMPURE_E, TRG_IMPURE_M = 1, 2
 

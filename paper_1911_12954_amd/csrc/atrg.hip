@@ -1196,7 +1196,7 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
     c.Uk[nu] = kn;
     SelectOut so{static_cast<double *>(c.U[nu].ptr), rd + 1 + 2 * nu, ri + 4 * nu,
                  static_cast<double *>(c.spec[nu].ptr)};
-    select_isometry(Wv, Vv, sw, nn, kn, c.force_side, so, st);
+    select_isometry(Wv, Vv, sw, nn, kn, c.force_side, degeneracy_window(producer_precision(c)), so, st);
   }
 
   dbg(c, "Wf", Wf, int64_t(dc) * dc);

@@ -205,6 +205,16 @@ inline int join_precision(const trg_ctx &c) {
   return c.nsteps < c.cfg.fp64_steps ? int(TRG_FP64) : c.cfg.precision;
 }
 
+// arithmetic of the contraction that produced the current tensor: FP64 for
+// the initial (or imported, or host-given) tensor of step 0 and for the steps
+// joined in FP64, else the configured precision (HOTRG join or ATRG
+// contraction GEMMs)
+inline int producer_precision(const trg_ctx &c) {
+  if (c.nsteps == 0) return TRG_FP64;
+  if (c.cfg.method == TRG_ATRG) return c.cfg.precision == TRG_FP32 ? int(TRG_FP32) : int(TRG_FP64);
+  return c.nsteps - 1 < c.cfg.fp64_steps ? int(TRG_FP64) : c.cfg.precision;
+}
+
 // C(out_names, contiguous) = sum over the legs shared by A and B of A * B,
 // through packed, padded operands and the MFMA GEMM (prec FP64 or FP32).
 void einsum2(trg_ctx &c, const double *A, const View &va, const double *B, const View &vb, double *C,

@@ -387,7 +387,6 @@ constexpr int SEL_THREADS = 256;
 constexpr double TIE_REL = 1e-10;      // side rule: backward only if clearly better
 constexpr double SIGN_REL = 1e-9;      // "largest" coordinate within this relative window
 constexpr double DEGEN_REL = 1e-8;     // degenerate-cut flag
-constexpr double CLUSTER_REL = 1e-6;   // eigenvalue gaps below this * lambda_max are degenerate
 
 __device__ inline double sel_reduce(double v, double *sh, bool is_max) {
   const int t = threadIdx.x;
@@ -418,7 +417,7 @@ __device__ inline int sel_min_index(int v, int *sh) {
 // w2/V2: the two sides' sorted eigensystems (side 0 backward, 1 forward).
 __global__ void __launch_bounds__(SEL_THREADS)
 select_kernel(const double *w2, const double *V2, const int *sweeps2, int n, int k, int force_side,
-              double *U, double *rec_eps, int *rec_int, double *spectrum) {
+              double cluster_rel, double *U, double *rec_eps, int *rec_int, double *spectrum) {
   __shared__ double sh[SEL_THREADS];
   __shared__ int shi[SEL_THREADS];
   __shared__ double diag[MAX_N];
@@ -437,7 +436,10 @@ select_kernel(const double *w2, const double *V2, const int *sweeps2, int n, int
   const double *V = V2 + size_t(side) * n * n;
   for (int j = t; j < n; j += SEL_THREADS) spectrum[j] = w[j];
 
-  const double tol = CLUSTER_REL * fmax(w[0], 0.0);
+  // neighbouring eigenvalues within cluster_rel lambda_max form one
+  // eigenspace, kept in its canonical basis; every larger gap is resolved by
+  // the leading eigenvectors (plain truncated HOSVD)
+  const double tol = cluster_rel * fmax(w[0], 0.0);
   int a = 0;
   while (a < k) {
     int bnd = a + 1;
@@ -499,10 +501,11 @@ void eigh_batched(double *A, double *w, double *V, int *sweeps, int n, int batch
 }
 
 void select_isometry(const double *w2, const double *V2, const int *sweeps2, int n, int k,
-                     int force_side, SelectOut out, hipStream_t st) {
+                     int force_side, double cluster_rel, SelectOut out, hipStream_t st) {
   TRG_REQUIRE(n >= 1 && n <= MAX_N && k >= 1 && k <= n, "select: bad sizes");
+  TRG_REQUIRE(cluster_rel >= 0.0 && cluster_rel < 1.0, "select: bad degeneracy window");
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(SEL_THREADS), 0, st, w2, V2, sweeps2, n, k, force_side,
-                     out.U, out.rec_eps, out.rec_int, out.spectrum);
+                     cluster_rel, out.U, out.rec_eps, out.rec_int, out.spectrum);
   TRG_HIP_CHECK(hipGetLastError());
 }
 

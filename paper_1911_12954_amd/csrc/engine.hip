@@ -190,7 +190,10 @@ void build_operand(trg_ctx &c, const StepShape &sh, const double *X, bool site1,
   finalv.insert(finalv.end(), colv.begin(), colv.end());
   const int64_t M = view_count(rowv);
 
-  const int out_kind = sh.prec == TRG_FP64 ? OUT_F64 : (sh.prec == TRG_FP32 ? OUT_F32 : OUT_BF16X2);
+  const int out_kind = sh.prec == TRG_FP64   ? OUT_F64
+                       : sh.prec == TRG_FP32 ? OUT_F32
+                       : sh.prec == TRG_BF16X3 ? OUT_BF16X2
+                                               : OUT_BF16X3;
   const int esz = sh.prec == TRG_FP64 ? 8 : (sh.prec == TRG_FP32 ? 4 : 2);
   const int64_t lo_plane = Mpad * sh.Kpad;
 
@@ -233,7 +236,7 @@ void build_operand(trg_ctx &c, const StepShape &sh, const double *X, bool site1,
       curv = tv;
     }
   }
-  zero_pad(out, M, Mpad, sh.Kdim, sh.Kpad, esz, out_kind == OUT_BF16X2 ? 2 : 1, lo_plane, c.st);
+  zero_pad(out, M, Mpad, sh.Kdim, sh.Kpad, esz, operand_planes(sh.prec), lo_plane, c.st);
 }
 
 // Compress the post-axis pairs of a join block E (rows x0-block, cols
@@ -408,7 +411,7 @@ void isometries_batch(std::vector<trg_ctx *> &cs, std::vector<StepPrep> &ps, int
       SelectOut so{static_cast<double *>(c.U[ax].ptr), ps[i].rd + 1 + 2 * ax, ps[i].ri + 4 * ax,
                    static_cast<double *>(c.spec[ax].ptr)};
       select_isometry(W + wbase(a) + m * n, V + gbase(a) + m * n * n, sw + size_t(a) * per_ax + m, n, k,
-                      c.force_side, so, c.st);
+                      c.force_side, degeneracy_window(producer_precision(c)), so, c.st);
     }
   }
 }
@@ -426,7 +429,7 @@ void contract_step(trg_ctx &c, StepPrep &prep, int mu) {
   sh.Kdim = c.dims[mu];
   for (int s : sh.pre) sh.Kdim *= int64_t(c.dims[s]) * c.dims[s];
   sh.Kpad = int64_t(round_up(sh.Kdim, tile.k));
-  const int esz = sh.prec == TRG_FP64 ? 8 : 4;  // per element incl. both bf16 planes
+  const int esz = operand_bytes(sh.prec);  // per element, all planes
   const int esE = sh.prec == TRG_FP64 ? 8 : 4;
   const int nt = 1 + c.nimp;
   const int dmu = c.dims[mu];
@@ -602,7 +605,7 @@ void init_common(trg_ctx &c) {
 void validate_cfg(const trg_config *cfg, int d) {
   TRG_REQUIRE(d >= 2 && d <= 4, "d must be 2, 3 or 4");
   if (!cfg) return;
-  TRG_REQUIRE(cfg->precision >= TRG_FP64 && cfg->precision <= TRG_BF16X3, "unknown precision");
+  TRG_REQUIRE(cfg->precision >= TRG_FP64 && cfg->precision <= TRG_BF16X6, "unknown precision");
   TRG_REQUIRE(cfg->method == TRG_HOTRG || cfg->method == TRG_ATRG, "unknown method");
   TRG_REQUIRE(cfg->dcut >= 0 && cfg->dcut <= 1024, "dcut out of range");
   TRG_REQUIRE((cfg->impure & ~3u) == 0, "unknown impurity bits");
@@ -638,7 +641,7 @@ int trg_init_ising(trg_ctx **out, double beta, double h, int d, const trg_config
     const unsigned imp = cfg ? cfg->impure : 0u;
     TRG_REQUIRE(!(imp & TRG_IMPURE_E) || beta > 0.0, "the energy impurity needs beta > 0");
     const bool atrg = cfg && cfg->method == TRG_ATRG;
-    TRG_REQUIRE(!atrg || cfg->precision != TRG_BF16X3, "ATRG supports FP64 and FP32 contractions");
+    TRG_REQUIRE(!atrg || cfg->precision <= TRG_FP32, "ATRG supports FP64 and FP32 contractions");
     c = new_ctx(d, cfg);
     for (int a = 0; a < d; ++a) c->dims[a] = 2;
     c->has_e = imp & TRG_IMPURE_E;
@@ -708,10 +711,15 @@ int trg_hotrg_step(trg_ctx *ctx, int axis, int dcut) {
 
 int trg_hotrg_step_batch(trg_ctx *const *ctxs, int n, int axis, int dcut) {
   if (!ctxs || n < 1) return fail(nullptr, TRG_EINVAL, "empty batch");
+  // pointers first (no context is read before they are all distinct)
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i]) return fail(nullptr, TRG_EINVAL, "NULL context in batch");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(nullptr, TRG_EINVAL, "a context appears twice in the batch");
+  }
+  for (int i = 0; i < n; ++i) {
     if (ctxs[i]->d != ctxs[0]->d || join_precision(*ctxs[i]) != join_precision(*ctxs[0]) ||
-        ctxs[i]->st != ctxs[0]->st)
+        producer_precision(*ctxs[i]) != producer_precision(*ctxs[0]) || ctxs[i]->st != ctxs[0]->st)
       return fail(nullptr, TRG_EINVAL, "batch contexts differ in d, join precision or stream");
     for (int a = 0; a < ctxs[0]->d; ++a)
       if (ctxs[i]->dims[a] != ctxs[0]->dims[a]) return fail(nullptr, TRG_EINVAL, "batch contexts differ in dims");
@@ -721,11 +729,21 @@ int trg_hotrg_step_batch(trg_ctx *const *ctxs, int n, int axis, int dcut) {
   if (axis < 0 || axis >= ctxs[0]->d || dcut < 1 || dcut > 1024) return fail(nullptr, TRG_EINVAL, "bad axis or dcut");
   for (int i = 0; i < n; ++i)
     if (ctxs[i]->cfg.method != TRG_HOTRG) return fail(nullptr, TRG_EINVAL, "batch contexts must be HOTRG");
-  return guarded(nullptr, [&]() -> int {
+  const int rc = guarded(nullptr, [&]() -> int {
     std::vector<trg_ctx *> cs(ctxs, ctxs + n);
     hotrg_step_batch_impl(cs, axis, dcut);
     return TRG_OK;
   });
+  if (rc == TRG_EHIP || rc == TRG_ENUMERIC) {
+    // the device state of every context of the batch is unknown
+    for (int i = 0; i < n; ++i) {
+      ctxs[i]->poisoned = true;
+      ctxs[i]->err = g_thread_error;
+    }
+  } else if (rc != TRG_OK) {
+    for (int i = 0; i < n; ++i) ctxs[i]->err = g_thread_error;
+  }
+  return rc;
 }
 
 int trg_atrg_step(trg_ctx *ctx, int axis, int dcut) {
@@ -747,7 +765,7 @@ int trg_init_factors(trg_ctx **out, int d, const int *dims, int r, const double 
   int rc = guarded(nullptr, [&]() -> int {
     validate_cfg(cfg, d);
     TRG_REQUIRE(cfg && cfg->method == TRG_ATRG, "factors need method TRG_ATRG");
-    TRG_REQUIRE(cfg->impure == 0 && cfg->precision != TRG_BF16X3, "unsupported ATRG configuration");
+    TRG_REQUIRE(cfg->impure == 0 && cfg->precision <= TRG_FP32, "unsupported ATRG configuration");
     TRG_REQUIRE(r >= 1 && r <= 512, "rank out of range");
     int64_t n = 1;
     for (int a = 0; a < d; ++a) {
@@ -1195,12 +1213,13 @@ size_t trg_workspace_bytes(int d, int dcut, int precision, int method, unsigned 
   const double K = std::pow(D, 1 + 2 * pre);
   const GemmTile tile = gemm_tile(precision);
   const double Kpad = double(round_up(size_t(K), tile.k));
-  const double esz = precision == TRG_FP64 ? 8.0 : 4.0;
+  const double esz = operand_bytes(precision);
+  const double esE = precision == TRG_FP64 ? 8.0 : 4.0;
   const double c0 = std::max(1.0, std::min(D, std::floor(double(JOIN_ROWS) / Mr)));
   const double Mp = double(round_up(size_t(c0 * Mr), tile.m)), Np = double(round_up(size_t(D * Mr), tile.n));
   double b = nt * (Mp + Np) * Kpad * esz;                 // operands
   b += D * std::pow(D, 2 * d - 1) * D * 8.0;              // operand build temporary
-  b += Mp * Np * esz;                                     // join result
+  b += Mp * Np * esE;                                     // join result
   if (post) b += c0 * D * std::pow(D, 2 * post + 2 * pre + post) * 8.0;  // post-join temporary
   b += 12.0 * std::pow(D, 2 * d) * 8.0 / 1.0;             // Gram packing, partials, eigensystems (bound)
   return size_t(b);

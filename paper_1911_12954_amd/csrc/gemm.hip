@@ -15,6 +15,12 @@
 //   BF16X3 v_mfma_f32_16x16x32_bf16 256 x 256 tile, eight 128 x 64 waves,
 //          RB 64 (32 bf16 per plane, 1 k-step, three products hi*hi +
 //          hi*lo + lo*hi into one FP32 accumulator), two swizzled stages
+//   BF16X6 v_mfma_f32_16x16x32_bf16 128 x 128 tile, eight 64 x 32 waves,
+//          RB 64, three planes (fl32(a) = hi + mid + lo exactly), six
+//          products hi*hi + hi*mid + mid*hi + mid*mid + hi*lo + lo*hi; the
+//          MFMA sums BF6_FLUSH K tiles in FP32, the groups are summed in
+//          FP64 (FP32-accurate operands and FP64-grade accumulation), two
+//          swizzled stages
 //
 // With two stages the next tile's global loads are in flight while the
 // current tile feeds the MFMAs (one barrier per tile); with one stage two
@@ -24,6 +30,8 @@
 // the 8 XCDs) works on one contiguous range of tiles, walked in groups of
 // GROUP_M tile-rows: neighbouring tiles on one XCD share A and Bt rows in
 // that XCD's L2.
+#include <type_traits>
+
 #include "common.h"
 #include "internal.h"
 
@@ -56,6 +64,18 @@ constexpr int GROUP_M = TRG_GROUP_M;
 #ifndef TRG_F32_WN
 #define TRG_F32_WN 4
 #endif
+// BF16X6 join: K tiles (32 elements each) per FP32 group, and LDS stages
+#ifndef TRG_BF6_FLUSH
+#define TRG_BF6_FLUSH 4
+#endif
+#ifndef TRG_BF6_STAGES
+#define TRG_BF6_STAGES 2
+#endif
+// BF16X6 join: global -> LDS prefetch distance in K tiles (1 or 2)
+#ifndef TRG_BF6_PF
+#define TRG_BF6_PF 2
+#endif
+constexpr uint32_t BF6_FLUSH = TRG_BF6_FLUSH;
 
 template <int PREC> struct Prec;
 template <> struct Prec<0> {  // FP64
@@ -80,6 +100,14 @@ template <> struct Prec<2> {  // BF16 x3
   using acc_t = v4f;
   using frag_t = bf16x8;
   static constexpr int planes = 2;
+  static constexpr int elem = 2;
+};
+template <> struct Prec<3> {  // BF16 x6
+  using in_t = uint16_t;
+  using out_t = float;
+  using acc_t = v4f;
+  using frag_t = bf16x8;
+  static constexpr int planes = 3;
   static constexpr int elem = 2;
 };
 
@@ -120,7 +148,7 @@ constexpr int lds_stride() { return SWZ ? RB : RB + 16; }
 
 // BM x BN tile per workgroup, WM x WN waves of 64 lanes, K in tiles of RB
 // bytes per row.
-template <int PREC, int BM, int BN, int WM, int WN, int STAGES, int RB, int SWZ, bool ACCUM>
+template <int PREC, int BM, int BN, int WM, int WN, int STAGES, int RB, int SWZ, int PF, bool ACCUM>
 __global__ void __launch_bounds__(64 * WM * WN)
 gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
                const typename Prec<PREC>::in_t *__restrict__ Bt,
@@ -164,25 +192,28 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
   const uint64_t ldaB = lda * P::elem, ldbB = ldb * P::elem;
   const uint64_t plA = planeA * P::elem, plB = planeB * P::elem;
 
-  u32x4 ra[PL][LA], rb[PL][LB];
+  // PF register sets for the global -> LDS staging: with PF = 2 the loads
+  // of tile t are issued two compute phases before tile t is stored to LDS
+  static_assert(PF == 1 || (PF == 2 && STAGES == 2), "prefetch distance 2 needs two LDS stages");
+  u32x4 ra[PF][PL][LA], rb[PF][PL][LB];
 
-  auto gload = [&](uint32_t kt) {
+  auto gload = [&](uint32_t kt, int set) {
     const uint64_t kb = uint64_t(kt) * RB;
 #pragma unroll
     for (int p = 0; p < PL; ++p) {
 #pragma unroll
       for (int i = 0; i < LA; ++i) {
         const int c = tid + i * NT, row = c / CPR, col = c % CPR;
-        ra[p][i] = *reinterpret_cast<const u32x4 *>(gA + p * plA + row * ldaB + kb + col * 16);
+        ra[set][p][i] = *reinterpret_cast<const u32x4 *>(gA + p * plA + row * ldaB + kb + col * 16);
       }
 #pragma unroll
       for (int i = 0; i < LB; ++i) {
         const int c = tid + i * NT, row = c / CPR, col = c % CPR;
-        rb[p][i] = *reinterpret_cast<const u32x4 *>(gB + p * plB + row * ldbB + kb + col * 16);
+        rb[set][p][i] = *reinterpret_cast<const u32x4 *>(gB + p * plB + row * ldbB + kb + col * 16);
       }
     }
   };
-  auto sstore = [&](int stage) {
+  auto sstore = [&](int stage, int set) {
     unsigned char *base = smem + stage * STAGE;
 #pragma unroll
     for (int p = 0; p < PL; ++p) {
@@ -191,12 +222,12 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
 #pragma unroll
       for (int i = 0; i < LA; ++i) {
         const int c = tid + i * NT, row = c / CPR, col = c % CPR;
-        *reinterpret_cast<u32x4 *>(sA + lds_off<RB, SWZ>(row, col)) = ra[p][i];
+        *reinterpret_cast<u32x4 *>(sA + lds_off<RB, SWZ>(row, col)) = ra[set][p][i];
       }
 #pragma unroll
       for (int i = 0; i < LB; ++i) {
         const int c = tid + i * NT, row = c / CPR, col = c % CPR;
-        *reinterpret_cast<u32x4 *>(sB + lds_off<RB, SWZ>(row, col)) = rb[p][i];
+        *reinterpret_cast<u32x4 *>(sB + lds_off<RB, SWZ>(row, col)) = rb[set][p][i];
       }
     }
   };
@@ -206,10 +237,11 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{};
-  // FP32 products: the MFMA accumulates one group of F32_FLUSH K tiles in
+  // FP32 and BF16X6 products: the MFMA accumulates one group of K tiles in
   // FP32, the groups are summed in FP64, so the rounding of the sum no longer
   // grows with the full length of K
-  constexpr bool F64SUM = PREC == 1;
+  constexpr bool F64SUM = PREC == 1 || PREC == 3;
+  constexpr uint32_t FLUSH = PREC == 3 ? BF6_FLUSH : F32_FLUSH;
   v4d acc64[F64SUM ? FM : 1][F64SUM ? FN : 1];
   if constexpr (F64SUM) {
 #pragma unroll
@@ -218,23 +250,9 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
       for (int j = 0; j < FN; ++j) acc64[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
   }
 
-  gload(0);
-  if constexpr (STAGES == 2) {
-    sstore(0);
-    __syncthreads();
-  }
-
-  for (uint32_t kt = 0; kt < ktiles; ++kt) {
-    // two stages: compute stage kt&1 while tile kt+1 is loaded, one barrier;
-    // one stage: store, barrier, load the next tile into registers, compute,
-    // barrier (two workgroups per CU then overlap each other's waits)
-    const int cur = STAGES == 2 ? (kt & 1) : 0;
-    if constexpr (STAGES == 1) {
-      sstore(0);
-      __syncthreads();
-    }
-    if (kt + 1 < ktiles) gload(kt + 1);
-
+  // MFMAs of the tile in LDS stage `cur`, then the FP64 fold of a finished
+  // group (K tile kt is the last of its group, or the last one)
+  auto compute = [&](int cur, uint32_t kt) {
     const unsigned char *base = smem + cur * STAGE;
     // fragments: lane group g owns chunks [g NF, g NF + NF) of every row
     using frag_t = typename P::frag_t;
@@ -273,6 +291,18 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
           for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[0][i][s >> 2][s & 3],
                                                               fb[0][j][s >> 2][s & 3], acc[i][j], 0, 0, 0);
+    } else if constexpr (PREC == 3) {
+      static_assert(NF == 1, "BF16X6 uses one 32-element k-step per K tile");
+      // the six products of each block, the small ones first; each term
+      // sweeps all accumulators so consecutive MFMAs are independent
+      constexpr int TA[6] = {2, 0, 1, 1, 0, 0}, TB[6] = {0, 2, 1, 0, 1, 0};  // lo*hi, hi*lo, mid*mid, mid*hi, hi*mid, hi*hi
+#pragma unroll
+      for (int term = 0; term < 6; ++term)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[TA[term]][i][0], fb[TB[term]][j][0], acc[i][j], 0, 0, 0);
     } else {
 #pragma unroll
       // the three products of a block are spread over all accumulators so
@@ -290,7 +320,7 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
     }
 
     if constexpr (F64SUM) {
-      if ((kt + 1) % F32_FLUSH == 0 || kt + 1 == ktiles) {
+      if ((kt + 1) % FLUSH == 0 || kt + 1 == ktiles) {
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -301,10 +331,72 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
           }
       }
     }
-    if constexpr (STAGES == 2) {
-      if (kt + 1 < ktiles) sstore(cur ^ 1);
-    }
+  };
+
+  if constexpr (PF == 2) {
+    // tile t: registers set t % 2, LDS stage t % 2.  Iteration t issues the
+    // loads of tile t + 2 into the set that tile t has left, computes stage
+    // t % 2, then stores tile t + 1 (loaded during iteration t - 1) into the
+    // stage that iteration t - 1 computed; one barrier per tile.  The main
+    // loop has no conditional loads or stores, so the wait before a store
+    // leaves the six loads issued after it in flight; the last one to three
+    // tiles run in a tail with the bounds checks.
+    gload(0, 0);
+    sstore(0, 0);
+    if (ktiles > 1) gload(1, 1);
     __syncthreads();
+    auto body = [&](uint32_t kt, auto half) {
+      constexpr int h = decltype(half)::value;
+      gload(kt + 2, h);
+      // keep the loads ahead of the MFMAs: the compiler would otherwise sink
+      // them towards their use and shorten the prefetch distance to one tile
+      // (the empty asm with a memory clobber stops sinking in the IR, the
+      // scheduling barrier reordering in the machine scheduler)
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+      compute(h, kt);
+      sstore(h ^ 1, h ^ 1);
+      __syncthreads();
+    };
+    auto tail = [&](uint32_t kt, auto half) {
+      constexpr int h = decltype(half)::value;
+      if (kt + 2 < ktiles) gload(kt + 2, h);
+      compute(h, kt);
+      if (kt + 1 < ktiles) sstore(h ^ 1, h ^ 1);
+      __syncthreads();
+    };
+    uint32_t kt = 0;
+    for (; kt + 3 < ktiles; kt += 2) {
+      body(kt, std::integral_constant<int, 0>{});
+      body(kt + 1, std::integral_constant<int, 1>{});
+    }
+    // kt is even here and 1 to 3 tiles remain
+    tail(kt, std::integral_constant<int, 0>{});
+    if (kt + 1 < ktiles) tail(kt + 1, std::integral_constant<int, 1>{});
+    if (kt + 2 < ktiles) tail(kt + 2, std::integral_constant<int, 0>{});
+  } else {
+    gload(0, 0);
+    if constexpr (STAGES == 2) {
+      sstore(0, 0);
+      __syncthreads();
+    }
+
+    for (uint32_t kt = 0; kt < ktiles; ++kt) {
+      // two stages: compute stage kt&1 while tile kt+1 is loaded, one barrier;
+      // one stage: store, barrier, load the next tile into registers, compute,
+      // barrier (two workgroups per CU then overlap each other's waits)
+      const int cur = STAGES == 2 ? (kt & 1) : 0;
+      if constexpr (STAGES == 1) {
+        sstore(0, 0);
+        __syncthreads();
+      }
+      if (kt + 1 < ktiles) gload(kt + 1, 0);
+      compute(cur, kt);
+      if constexpr (STAGES == 2) {
+        if (kt + 1 < ktiles) sstore(cur ^ 1, 0);
+      }
+      __syncthreads();
+    }
   }
 
   // epilogue: register e of lane (g, r16) holds column r16 of each 16x16
@@ -334,7 +426,7 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
       }
 }
 
-template <int PREC, int BM, int BN, int WM, int WN, int STAGES = 2, int RB = 128, int SWZ = 0>
+template <int PREC, int BM, int BN, int WM, int WN, int STAGES = 2, int RB = 128, int SWZ = 0, int PF = 1>
 void launch_gemm(const void *A, const void *Bt, void *C, uint64_t M, uint64_t N, uint64_t K,
                  uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st,
                  uint32_t splits = 1, uint64_t c_split_stride = 0) {
@@ -365,17 +457,17 @@ void launch_gemm(const void *A, const void *Bt, void *C, uint64_t M, uint64_t N,
   // dynamic LDS above 64 KB must be allowed per kernel (once per instantiation)
   static bool attr_set = false;
   if (!attr_set) {
-    TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, RB, SWZ, true>),
+    TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, RB, SWZ, PF, true>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-    TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, RB, SWZ, false>),
+    TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, RB, SWZ, PF, false>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     attr_set = true;
   }
   if (accum)
-    hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, RB, SWZ, true>), grid, block, lds, st, a, b, c,
+    hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, RB, SWZ, PF, true>), grid, block, lds, st, a, b, c,
                        uint32_t(tiles_m), uint32_t(tiles_n), kt, lda, ldb, ldc, plA, plB, c_split_stride);
   else
-    hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, RB, SWZ, false>), grid, block, lds, st, a, b, c,
+    hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, RB, SWZ, PF, false>), grid, block, lds, st, a, b, c,
                        uint32_t(tiles_m), uint32_t(tiles_n), kt, lda, ldb, ldc, plA, plB, c_split_stride);
   TRG_HIP_CHECK(hipGetLastError());
 }
@@ -389,12 +481,21 @@ void launch_gemm(const void *A, const void *Bt, void *C, uint64_t M, uint64_t N,
 struct BF {
   static constexpr int BM = 256, BN = 256, WM = 2, WN = 4, S = 2, RB = 64, SWZ = 1;
 };
+// BF16x6 join: 128 x 128 workgroup tile, eight waves of 64 x 32 (two per
+// SIMD: 32 FP32 accumulators, 64 FP64 group sums, 18 operand fragments of
+// 16 bytes per lane), 64-byte K rows of three planes, swizzled LDS stages of
+// 48 KB.  Six products per three planes read from LDS: per MFMA it reads a
+// third less LDS than the BF16x3 join's two-plane, three-product blocks.
+struct BF6 {
+  static constexpr int BM = 128, BN = 128, WM = 2, WN = 4, S = TRG_BF6_STAGES, RB = 64, SWZ = 1, PF = TRG_BF6_PF;
+};
 
 GemmTile gemm_tile(int prec) {
   switch (prec) {
     case 0: return {128, 128, 16};
     case 1: return {128, 128, 32};
     case 2: return {BF::BM, BF::BN, BF::RB / 2};
+    case 3: return {BF6::BM, BF6::BN, BF6::RB / 2};
   }
   throw Error(-1, "gemm: unknown precision");
 }
@@ -406,6 +507,10 @@ void gemm_nt(int prec, const void *A, const void *Bt, void *C, uint64_t M, uint6
     case 1: launch_gemm<1, 128, 128, 2, TRG_F32_WN, TRG_F32_STAGES>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
     case 2:
       launch_gemm<2, BF::BM, BF::BN, BF::WM, BF::WN, BF::S, BF::RB, BF::SWZ>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st);
+      return;
+    case 3:
+      launch_gemm<3, BF6::BM, BF6::BN, BF6::WM, BF6::WN, BF6::S, BF6::RB, BF6::SWZ, BF6::PF>(A, Bt, C, M, N, K, lda, ldb,
+                                                                                          ldc, accum, st);
       return;
   }
   throw Error(-1, "gemm: unknown precision");

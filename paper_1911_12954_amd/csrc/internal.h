@@ -9,6 +9,10 @@ namespace trg {
 struct GemmTile {
   int m, n, k;
 };
+// join operand planes and bytes per element over all planes, per precision
+// (FP64, FP32, BF16X3 = hi + lo, BF16X6 = hi + mid + lo)
+inline int operand_planes(int prec) { return prec == 2 ? 2 : (prec == 3 ? 3 : 1); }
+inline int operand_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2 * operand_planes(prec)); }
 GemmTile gemm_tile(int prec);
 void gemm_nt(int prec, const void *A, const void *Bt, void *C, uint64_t M, uint64_t N, uint64_t K,
              uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st);
@@ -22,7 +26,8 @@ void gemm_nt_splitk_f64(const double *A, const double *Bt, double *Cpart, uint64
 //                                U[sum_i o_i su_i + sum_j s_j ssu_j]
 // over the iteration space o (dims listed outermost first).  With nsum = 0
 // and U == nullptr it is a strided copy.  Output kinds: FP64, FP32 or a BF16
-// split (hi at out, lo at out + lo_plane elements).
+// split of fl32(v) into planes lo_plane elements apart: two planes (hi, lo)
+// or three (hi, mid, lo, which sum to fl32(v) exactly).
 constexpr int MAP_MAXD = 12;
 struct MapDim {
   int64_t size, so, si, su;
@@ -30,7 +35,7 @@ struct MapDim {
 struct MapSum {
   int64_t size, si, su;
 };
-enum OutKind { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16X2 = 2 };
+enum OutKind { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16X2 = 2, OUT_BF16X3 = 3 };
 enum InKind { IN_F64 = 0, IN_F32 = 1 };
 
 void tensor_map(const void *in, int in_kind, const double *U, void *out, int out_kind,
@@ -84,7 +89,22 @@ struct SelectOut {
   int *rec_int;     // [side, k, degenerate, sweeps]
   double *spectrum; // n (chosen side)
 };
+// Degenerate eigenspaces: neighbouring eigenvalues within cluster_rel
+// lambda_max (see degeneracy_window) are expressed in a canonical basis.
 void select_isometry(const double *w2, const double *V2, const int *sweeps2, int n, int k,
-                     int force_side, SelectOut out, hipStream_t st);
+                     int force_side, double cluster_rel, SelectOut out, hipStream_t st);
+
+// Window of select_isometry for a Gram built from a tensor that an FP64
+// contraction produced: FP64 rounding leaves the degeneracies that a symmetry
+// makes exact as gaps of ~1e-17 lambda_max, and every gap above the window is
+// resolved by the leading eigenvectors.  A tensor from an FP32 or split-BF16
+// contraction carries ~1e-7 lambda_max of rounding on its Gram spectrum, so its
+// window is 1e-6: rounding then does not pick the member of a degenerate pair
+// that survives a cut.
+constexpr double CLUSTER_REL_FP64 = 1e-10;
+constexpr double CLUSTER_REL_MIXED = 1e-6;
+inline double degeneracy_window(int producer_precision) {
+  return producer_precision == 0 ? CLUSTER_REL_FP64 : CLUSTER_REL_MIXED;
+}
 
 }  // namespace trg

@@ -38,13 +38,24 @@ __device__ inline void map_store(void *out, int64_t o, int64_t lo_plane, double 
     static_cast<double *>(out)[o] = v;
   } else if constexpr (OUT == OUT_F32) {
     static_cast<float *>(out)[o] = float(v);
-  } else {
+  } else if constexpr (OUT == OUT_BF16X2) {
     // v = hi + lo with hi = bf16(fl32(v)), lo = bf16(fl32(v) - hi)
     const float a = float(v);
     const uint16_t hi = f32_to_bf16_rne(a);
     const uint16_t lo = f32_to_bf16_rne(a - bf16_to_f32(hi));
     static_cast<uint16_t *>(out)[o] = hi;
     static_cast<uint16_t *>(out)[o + lo_plane] = lo;
+  } else {
+    // fl32(v) = hi + mid + lo exactly: each residual is exact in FP32
+    // (Sterbenz) and the last one has at most 8 significant bits
+    const float a = float(v);
+    const uint16_t hi = f32_to_bf16_rne(a);
+    const float r1 = a - bf16_to_f32(hi);
+    const uint16_t mid = f32_to_bf16_rne(r1);
+    const uint16_t lo = f32_to_bf16_rne(r1 - bf16_to_f32(mid));
+    static_cast<uint16_t *>(out)[o] = hi;
+    static_cast<uint16_t *>(out)[o + lo_plane] = mid;
+    static_cast<uint16_t *>(out)[o + 2 * lo_plane] = lo;
   }
 }
 
@@ -133,6 +144,7 @@ void launch_map(const InT *in, const double *U, void *out, int out_kind, MapPara
     case OUT_F64: hipLaunchKernelGGL((map_kernel<InT, OUT_F64>), grid, block, lds, st, in, U, out, p); break;
     case OUT_F32: hipLaunchKernelGGL((map_kernel<InT, OUT_F32>), grid, block, lds, st, in, U, out, p); break;
     case OUT_BF16X2: hipLaunchKernelGGL((map_kernel<InT, OUT_BF16X2>), grid, block, lds, st, in, U, out, p); break;
+    case OUT_BF16X3: hipLaunchKernelGGL((map_kernel<InT, OUT_BF16X3>), grid, block, lds, st, in, U, out, p); break;
     default: throw Error(-1, "tensor_map: bad output kind");
   }
   TRG_HIP_CHECK(hipGetLastError());

@@ -11,7 +11,7 @@ import numpy as np
 
 from . import _lib as L
 
-PRECISIONS = {"fp64": L.TRG_FP64, "fp32": L.TRG_FP32, "bf16x3": L.TRG_BF16X3}
+PRECISIONS = {"fp64": L.TRG_FP64, "fp32": L.TRG_FP32, "bf16x3": L.TRG_BF16X3, "bf16x6": L.TRG_BF16X6}
 METHODS = {"hotrg": L.TRG_HOTRG, "atrg": L.TRG_ATRG}
 
 

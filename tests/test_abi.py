@@ -55,7 +55,8 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
 
 def test_gemm_tile_and_footprint(lib):
     m, n, k = C.c_int(), C.c_int(), C.c_int()
-    for prec, tile in ((L.TRG_FP64, (128, 128, 16)), (L.TRG_FP32, (128, 128, 32)), (L.TRG_BF16X3, (256, 256, 32))):
+    for prec, tile in ((L.TRG_FP64, (128, 128, 16)), (L.TRG_FP32, (128, 128, 32)), (L.TRG_BF16X3, (256, 256, 32)),
+                       (L.TRG_BF16X6, (128, 128, 32))):
         assert lib.trg_gemm_tile(prec, C.byref(m), C.byref(n), C.byref(k)) == 0
         assert (m.value, n.value, k.value) == tile
     f8 = lib.trg_footprint_bytes(4, 8, L.TRG_FP64, L.TRG_HOTRG, 0)
@@ -66,7 +67,8 @@ def test_gemm_tile_and_footprint(lib):
     assert f10 > 2 * 10 ** 8 * 8
     assert lib.trg_footprint_bytes(5, 8, 0, 0, 0) == 0
     for args in ((4, 10, L.TRG_FP64, L.TRG_HOTRG, 0), (4, 6, L.TRG_FP32, L.TRG_HOTRG, 3),
-                 (3, 12, L.TRG_BF16X3, L.TRG_HOTRG, 1), (4, 24, L.TRG_FP64, L.TRG_ATRG, 0)):
+                 (3, 12, L.TRG_BF16X3, L.TRG_HOTRG, 1), (4, 10, L.TRG_BF16X6, L.TRG_HOTRG, 3),
+                 (4, 24, L.TRG_FP64, L.TRG_ATRG, 0)):
         res, ws = lib.trg_resident_bytes(*args), lib.trg_workspace_bytes(*args)
         assert res > 0 and ws > 0 and lib.trg_footprint_bytes(*args) == res + ws
     # resident: T, S_E, S_M and their next-step buffers, D^8 doubles each
@@ -84,8 +86,12 @@ def test_more_argument_checks_on_the_host(lib):
     cfg.fp64_steps = -1
     assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
     assert b"fp64_steps" in lib.trg_last_error(None)
+    for prec in (L.TRG_BF16X3, L.TRG_BF16X6):
+        cfg = L.TrgConfig()
+        cfg.method, cfg.precision = L.TRG_ATRG, prec
+        assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
     cfg = L.TrgConfig()
-    cfg.method, cfg.precision = L.TRG_ATRG, L.TRG_BF16X3
+    cfg.precision = 4
     assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
     cfg = L.TrgConfig()
     cfg.method, cfg.impure = L.TRG_ATRG, L.TRG_IMPURE_E
@@ -113,6 +119,12 @@ def test_more_argument_checks_on_the_host(lib):
     arr = (C.c_void_p * 2)(None, None)
     assert lib.trg_hotrg_step_batch(arr, 0, 0, 4) == L.TRG_EINVAL
     assert lib.trg_hotrg_step_batch(arr, 2, 0, 4) == L.TRG_EINVAL
+    # the same context twice is rejected before any context is read (the
+    # pointer names a host buffer, never dereferenced)
+    fake = C.create_string_buffer(64)
+    dup = (C.c_void_p * 3)(C.addressof(fake), C.addressof(fake) + 16, C.addressof(fake))
+    assert lib.trg_hotrg_step_batch(dup, 3, 0, 4) == L.TRG_EINVAL
+    assert b"twice" in lib.trg_last_error(None)
     assert lib.trg_share_workspace(None, None) == L.TRG_EINVAL
     assert lib.trg_atrg_step(None, 0, 4) == L.TRG_EINVAL
     assert lib.trg_free_energy(None, None) == L.TRG_EINVAL

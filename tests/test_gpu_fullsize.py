@@ -38,7 +38,7 @@ def problem():
     return T, choices, blocks
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 2e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 2e-4), ("bf16x6", 1e-5)])
 def test_dcut10_step_on_sampled_blocks(problem, precision, tol):
     need_gpu()
     from paper_1911_12954_amd import trg_init_tensor

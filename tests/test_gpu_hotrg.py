@@ -169,6 +169,7 @@ def test_field_reversal_symmetry():
 
 
 @pytest.mark.parametrize("precision,n64,tol_f,tol_E,tol_M", [("fp32", 0, 1e-6, 1e-6, 1e-3),
+                                                           ("bf16x6", 0, 1e-6, 1e-6, 1e-3),
                                                            ("bf16x3", 0, 2e-5, 1e-3, 1e-1),
                                                            ("bf16x3", 8, 1e-6, 1e-3, 1e-1)])
 def test_mixed_precision_error_dcut8(precision, n64, tol_f, tol_E, tol_M):
@@ -193,7 +194,7 @@ def test_mixed_precision_error_dcut8(precision, n64, tol_f, tol_E, tol_M):
     assert eE < tol_E and eM < tol_M
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6", "bf16x3"])
 def test_mixed_precision_dcut4_degenerate_case(precision):
     """Config of the smoke case (Dcut = 4, L = 16): its truncation at step 3
     goes through a degenerate pair, and gaps near the degeneracy window let
@@ -218,7 +219,7 @@ def test_fp64_steps_schedule():
     announce("fp64_steps schedule")
     ref = trg_init_ising(0.1497, 1e-5, 4, dcut=5, precision="fp64", impure=("E", "M"))
     ref.run(8)
-    for prec in ("fp32", "bf16x3"):
+    for prec in ("fp32", "bf16x3", "bf16x6"):
         a = trg_init_ising(0.1497, 1e-5, 4, dcut=5, precision=prec, impure=("E", "M"), fp64_steps=12)
         a.run(8)
         assert [r.join_precision for r in a.step_log()] == ["fp64"] * 12

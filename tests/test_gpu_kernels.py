@@ -1,4 +1,4 @@
-"""GPU kernels against plain references: the join GEMM in its three
+"""GPU kernels against plain references: the join GEMM in its four
 precisions and the Jacobi eigensolver."""
 import numpy as np
 import pytest
@@ -90,6 +90,56 @@ def test_gemm_bf16x3(M, N, K, accumulate):
     assert err < 4 * 2.0 ** -24 * np.sqrt(K) + 1e-7
     # and the split product is within ~2^-16 of the exact one
     assert np.max(np.abs(dC.cpu().numpy() - exact) / scale) < 2.0 ** -14
+
+
+def _split3(X):
+    """fl32(X) = hi + mid + lo exactly (three bfloat16 planes, round to
+    nearest even at each stage), as torch tensors."""
+    import torch
+    x32 = torch.from_numpy(X).float()
+    hi = x32.to(torch.bfloat16)
+    r1 = x32 - hi.float()
+    mid = r1.to(torch.bfloat16)
+    lo = (r1 - mid.float()).to(torch.bfloat16)
+    return hi, mid, lo
+
+
+@pytest.mark.parametrize("M,N,K,accumulate", [(128, 128, 32, False), (384, 256, 1056, False),
+                                              (256, 640, 4128, False), (256, 384, 1056, True)])
+def test_gemm_bf16x6(M, N, K, accumulate):
+    """Three-plane split join: the six products reproduce the product of the
+    FP32-rounded operands to FP32 accuracy (the dropped mid*lo, lo*mid and
+    lo*lo terms are below 2^-24 of each product), with FP64 sums of the
+    FP32 groups (K = 4128: 32 groups and a ragged last one)."""
+    torch = need_gpu()
+    from paper_1911_12954_amd import trg_gemm, trg_gemm_tile
+    announce("gemm bf16x6", M, N, K, accumulate)
+    tm, tn, tk = trg_gemm_tile("bf16x6")
+    assert M % tm == 0 and N % tn == 0 and K % tk == 0
+    A = random_matrix(M, K, 16)
+    B = random_matrix(N, K, 17)
+    pa, pb = _split3(A), _split3(B)
+    # the split is exact on the host side too
+    f = lambda t: t.double().numpy()
+    A32, B32 = A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
+    assert np.array_equal(f(pa[0]) + f(pa[1]) + f(pa[2]), A32)
+    dA = torch.stack(list(pa)).cuda().contiguous()
+    dB = torch.stack(list(pb)).cuda().contiguous()
+    C0 = random_matrix(M, N, 18).astype(np.float32)
+    dC = torch.from_numpy(C0).cuda()
+    trg_gemm("bf16x6", dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), M, N, K, K, K, N, accumulate,
+             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    ref = A32 @ B32.T
+    scale = np.abs(A) @ np.abs(B).T
+    if accumulate:
+        c0 = C0.astype(np.float64)
+        ref, scale = ref + c0, scale + np.abs(c0)
+    err = np.max(np.abs(dC.cpu().numpy() - ref) / scale)
+    print(f"[gemm bf16x6] max err / scale {err:.3e}", flush=True)
+    # FP32 output rounding (2^-24 of |C|) plus the dropped terms and the
+    # FP32 group sums; no sqrt(K) growth beyond the group length
+    assert err < 12 * 2.0 ** -24
 
 
 @pytest.mark.parametrize("n", [1, 2, 4, 7, 16, 33, 100, 144, 161, 200, 333, 576])
