@@ -203,6 +203,21 @@ int trg_free_energy(trg_ctx *ctx, double *lnz_per_site);
  * trace). */
 int trg_indicator_x(trg_ctx *ctx, int axis, double *X);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): X of
+ * trg_indicator_x for a HOTRG context, computed by the same kernels with the
+ * partial-trace matrix and the two traces in a static device array of
+ * 512 KiB + 256 bytes that the library holds on each GPU until the process
+ * ends, instead of the context's workspace.  It allocates nothing: no
+ * hipMalloc, hipFree or allocator callback.  Limit: dims[axis] <= 256.
+ * Every call on one GPU uses that GPU's array and leaves its contents
+ * behind (the kernels overwrite every entry they read); calls that overlap
+ * on one GPU (from several threads or streams) race and give undefined
+ * results.  Synchronises the context's stream.  Errors: TRG_EINVAL (NULL,
+ * bad axis, dims[axis] > 256, ATRG context), TRG_ENUMERIC (vanishing
+ * two-site trace). */
+int trg_indicator_x_noalloc(trg_ctx *ctx, int axis, double *X);
+
 /* E = <H>/V = -Tr S_E / Tr T and M = <s> = Tr S_M / Tr T (impure-tensor
  * method, Sec. 3.1; HOTRG and ATRG contexts).  Synchronises.  TRG_ESTATE if
  * that impurity was not enabled. */

@@ -75,6 +75,7 @@ SIGNATURES = {
     "trg_export_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "trg_import_state": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.POINTER(TrgConfig)]),
     "trg_indicator_x": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double)]),
+    "trg_indicator_x_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double)]),
     "trg_footprint_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint]),
     "trg_resident_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint]),
     "trg_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint]),

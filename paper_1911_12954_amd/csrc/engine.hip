@@ -627,6 +627,38 @@ void normalise_initial(trg_ctx &c) {
 
 }  // namespace trg
 
+// ------------------------------------------------ allocation-free scratch ---
+// Device scratch of trg_indicator_x_noalloc: the partial-trace matrix M
+// (up to NOALLOC_MAX_N^2 doubles) followed by the two traces.  Each GPU the
+// library runs on holds its own copy until the process ends.  Host code uses
+// the address hipGetSymbolAddress returns for the current device, never the
+// array's name (which is a host-side stand-in).
+constexpr int NOALLOC_MAX_N = 256;
+constexpr size_t NOALLOC_M_BYTES = size_t(NOALLOC_MAX_N) * NOALLOC_MAX_N * 8;
+constexpr size_t NOALLOC_SCRATCH_BYTES = NOALLOC_M_BYTES + 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device (looked up once per device)
+void *scratch_on_current_device() {
+  int dev = -1;
+  TRG_HIP_CHECK(hipGetDevice(&dev));
+  TRG_REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    TRG_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    TRG_REQUIRE(ptr != nullptr, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
 // =================================================================== C-ABI ==
 extern "C" {
 
@@ -866,6 +898,27 @@ int trg_indicator_x(trg_ctx *ctx, int axis, double *X) {
       atrg_indicator_traces(*ctx, axis, M, out);
     else
       indicator_traces(static_cast<const double *>(ctx->T.ptr), ctx->dims, ctx->d, axis, M, out, ctx->st);
+    sync_check(*ctx);
+    double t[2];
+    TRG_HIP_CHECK(hipMemcpy(t, out, 2 * 8, hipMemcpyDeviceToHost));
+    if (!(t[1] > 0.0) || !std::isfinite(t[0])) throw Error(TRG_ENUMERIC, "indicator: vanishing two-site trace");
+    *X = t[0] * t[0] / t[1];
+    return TRG_OK;
+  });
+}
+
+int trg_indicator_x_noalloc(trg_ctx *ctx, int axis, double *X) {
+  if (!ctx || !X) return fail(ctx, TRG_EINVAL, "NULL argument");
+  return guarded(ctx, [&]() -> int {
+    TRG_REQUIRE(axis >= 0 && axis < ctx->d, "axis out of range");
+    TRG_REQUIRE(ctx->cfg.method == TRG_HOTRG, "the allocation-free indicator takes HOTRG contexts");
+    const int n = ctx->dims[axis];
+    TRG_REQUIRE(n >= 1 && n <= NOALLOC_MAX_N, "leg dim of the axis exceeds the static scratch (at most 256)");
+    char *base = static_cast<char *>(scratch_on_current_device());
+    double *M = reinterpret_cast<double *>(base);
+    double *out = reinterpret_cast<double *>(base + NOALLOC_M_BYTES);
+    // both kernels overwrite every scratch entry they later read
+    indicator_traces(static_cast<const double *>(ctx->T.ptr), ctx->dims, ctx->d, axis, M, out, ctx->st);
     sync_check(*ctx);
     double t[2];
     TRG_HIP_CHECK(hipMemcpy(t, out, 2 * 8, hipMemcpyDeviceToHost));

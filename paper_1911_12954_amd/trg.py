@@ -142,6 +142,12 @@ class Context:
         _err(_lib().trg_indicator_x(self.handle, int(axis), C.byref(out)), self.handle)
         return out.value
 
+    def indicator_x_noalloc(self, axis: int = 0) -> float:
+        """trg_indicator_x_noalloc: the same X without any device allocation."""
+        out = C.c_double()
+        _err(_lib().trg_indicator_x_noalloc(self.handle, int(axis), C.byref(out)), self.handle)
+        return out.value
+
     def accumulator(self) -> float:
         return self._dbl(_lib().trg_accumulator)
 
