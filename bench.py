@@ -4,13 +4,20 @@ A step is one steady-state HOTRG coarse-graining step (Gram matrices, FP64
 eigendecomposition and isometries, block-spin contraction, post-join
 compression, FP64 normalisation) of the 4D Ising tensor at beta = 0.1497,
 h = 0, with every leg at Dcut = 10; inputs are resident in HBM.  The first
-three steps (leg dims 2 -> 4 -> 10) and `--warmup` steady steps are untimed;
-then `--steps` steps are timed between two stream synchronisations.
+four steps (leg dims 2 -> 4 -> 10) and `--warmup` steady steps are untimed;
+then `--steps` steps are timed between two stream synchronisations.  The
+headline join precision is BF16x6 (FP32-accurate operands, FP64 sums of
+128-element groups), the mixed path that meets 1e-6 on f and E against the
+FP64 path; FP64 and BF16x3 are timed beside it (warm, several steps) and
+every precision's ln Z/V after the same step is compared with the FP64 one.
 
 The join GEMM (the D^15 contraction) is timed with HIP events on the
-library's stream; its algorithmic flops per step are 2 D^15 (3 x 2 D^15
-BF16 MFMA flops for the BF16x3 split).  The oracle (FP64 NumPy) is timed on
-a bounded sample of the same step on the host cores.
+library's stream; its algorithmic flops per step are 2 D^15 (6 x or 3 x
+2 D^15 BF16 MFMA flops for the BF16x6 / BF16x3 splits).  The oracle (FP64
+NumPy) is timed on a bounded sample of the same step on the host cores, in a
+child process while the GPU runs the FP64 comparison.  A time-boxed window
+of the serving stream (Poisson arrivals of HOTRG solves, Dcut 6/8/10,
+L = 2^4 .. 2^10) reports served solves/s and latency.
 
 Prints one JSON line.
 """
@@ -30,12 +37,31 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
 # BF16 MFMA products per multiply-add of the split joins
 SPLIT_PRODUCTS = {"bf16x3": 3.0, "bf16x6": 6.0}
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per join launch of the steady Dcut 10 step (three full x0 slices
-# and one of a single x0 value per step, averaged), from rocprofv3 FETCH_SIZE
-# (x 2.0) and WRITE_SIZE (x 1.0) of the current BF16x3 join kernel; the
-# factors are what the two counters read for a device copy of 4 GiB.  Valid
-# for this kernel and workload only (null elsewhere).
-JOIN_TRAFFIC = {("bf16x3", 10): {"bytes_per_launch": 1.7127e12, "algorithmic_bytes_per_launch": 6.02e10}}
+# HBM bytes per join launch of the steady Dcut 10 step (three full x0
+# slices and one of a single x0 value per step, averaged), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE of the join kernel, each scaled by what the
+# counter reads for a device-to-device copy of 4 GiB (FETCH x 2.0, WRITE x
+# 1.0).  Each entry names the SHA-256 of the kernel source it was taken on;
+# the figure is reported only while csrc/gemm.hip still has that hash.
+JOIN_TRAFFIC = {
+    ("bf16x6", 10): {"bytes_per_launch": 4.657e12, "algorithmic_bytes_per_launch": 8.51e10,
+                     "gemm_sha16": "992e4c6c9aa3ae35",
+                     "source": "profiles/join_gemm_hotrg_dcut10_bf16x6.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"},
+}
+GEMM_SRC = os.path.join(ROOT, "paper_1911_12954_amd", "csrc", "gemm.hip")
+
+
+def gemm_source_hash():
+    import hashlib
+    with open(GEMM_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def join_traffic(precision, dcut):
+    t = JOIN_TRAFFIC.get((precision, dcut))
+    if not t or t.get("gemm_sha16") != gemm_source_hash():
+        return None
+    return t
 
 
 def parse():
@@ -44,11 +70,16 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--dcut", type=int, default=10)
-    p.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
+    p.add_argument("--precision", default="bf16x6", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     p.add_argument("--beta", type=float, default=0.1497)
-    p.add_argument("--compare", default="fp64,fp32",
-                   help="other join precisions timed for one step each (comma list, '' = none)")
+    p.add_argument("--compare", default="fp64,bf16x3",
+                   help="other join precisions timed beside the headline (comma list, '' = none)")
+    p.add_argument("--compare-warmup", type=int, default=1)
+    p.add_argument("--compare-steps", type=int, default=2)
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    p.add_argument("--cpu-only", action="store_true",
+                   help="only the oracle baseline (run as a child process by the benchmark)")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving window")
     p.add_argument("--impure", action="store_true",
                    help="time the step with the impure E and M tensors (five joins per step)")
     p.add_argument("--cpu-sample-blocks", type=int, default=1)
@@ -61,9 +92,13 @@ def parse():
                    help="arrivals per second; 0 = 0.8 of the capacity measured by a calibration pass; "
                         "<0 = every request arrives at the start (saturation)")
     p.add_argument("--serve-window", type=float, default=60.0)
+    p.add_argument("--window-rate", type=float, default=0.5,
+                   help="arrival rate of the serving window of the default run (requests/s)")
+    p.add_argument("--window-seconds", type=float, default=35.0,
+                   help="length of the serving window of the default run")
     p.add_argument("--serve-dcuts", default="6,8,10")
     p.add_argument("--serve-k", default="4,10", help="L = 2^k, k uniform in [kmin, kmax]")
-    p.add_argument("--serve-precision", default="fp32", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
+    p.add_argument("--serve-precision", default="bf16x6", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     p.add_argument("--serve-methods", default="hotrg", help="methods of the request stream, e.g. hotrg,atrg")
     p.add_argument("--serve-budget-gb", type=float, default=200.0)
     p.add_argument("--tc-bisect", default=None,
@@ -304,16 +339,26 @@ def progress(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def time_steps(precision, dcut, beta, warmup, steps, impure=False):
+def time_steps(precision, dcut, beta, warmup, steps, impure=False, probe_step=0):
+    """Ramp to every leg at dcut, `warmup` untimed steps, then `steps` timed
+    steps.  ln Z/V of the periodic block after step `probe_step` is read if
+    that step is untimed (ramp or warm-up; the read synchronises)."""
     import torch
     from paper_1911_12954_amd import trg_init_ising
     d = 4
     ctx = trg_init_ising(beta, 0.0, d, dcut=dcut, precision=precision, impure=("E", "M") if impure else ())
     n = 0
+    probe = None
+
+    def after_step():
+        nonlocal probe
+        if n == probe_step:
+            probe = ctx.free_energy()
     # ramp: legs grow 2 -> 4 -> ... -> dcut
     while min(ctx.dims()[0]) < dcut or n < d:
         ctx.hotrg_step(n % d, dcut)
         n += 1
+        after_step()
         if n > 3 * d:
             break
     ctx.sync()
@@ -324,6 +369,7 @@ def time_steps(precision, dcut, beta, warmup, steps, impure=False):
         n += 1
         ctx.sync()
         progress(f"{precision}: warmup step {n} took {time.perf_counter() - tw:.3f} s")
+        after_step()
     ctx.sync()
     torch.cuda.synchronize()
     ctx.set_profiling(True)
@@ -342,7 +388,8 @@ def time_steps(precision, dcut, beta, warmup, steps, impure=False):
     lnz = ctx.free_energy()
     ctx.close()
     torch.cuda.empty_cache()
-    return elapsed, ms, launches, lnz
+    return {"elapsed": elapsed, "join_ms": ms, "launches": launches, "lnz": lnz, "steps_total": n,
+            "probe": probe}
 
 
 def time_atrg(precision, dcut, beta, warmup, steps):
@@ -386,40 +433,99 @@ def cpu_baseline(dcut, blocks):
     """Time the oracle on a bounded sample of one steady-state step: the six
     isometries (all Gram matrices and eigendecompositions) plus `blocks`
     blocks T'[x0, x2, Y, Y', :, :, :, :] of the block-spin contraction, each
-    1/D^4 of the join, then scale the join part to the whole step."""
+    1/D^4 of the join, then scale the join part to the whole step; once with
+    every host thread the BLAS pool has and once with one thread."""
     import numpy as np
     from oracle import hotrg
     from trg_inputs import random_site_tensor
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     D = dcut
     T = random_site_tensor((D,) * 4, seed=0, positive_bias=True)
     T /= np.sqrt(np.sum(T * T))
     mu = 0
-    t0 = time.perf_counter()
-    choices = [hotrg.isometry(T, mu, nu, D) for nu in (1, 2, 3)]
-    t_iso = time.perf_counter() - t0
-    U = {ch.nu: ch.U for ch in choices}
-    t0 = time.perf_counter()
-    for b in range(blocks):
-        # one (x0, x2) pair and one kept column Y of the first pre-join axis
-        Ub = dict(U)
-        Ub[1] = U[1][:, :, b % D: b % D + 1]
-        hotrg.coarse_grain(T, T, Ub, mu, x0s=[b % D], x2s=[(b + 1) % D])
-    t_blk = (time.perf_counter() - t0) / blocks
-    # whole step: D^2 (x0, x2) pairs x D^2 (Y, Y') pairs of such blocks
-    t_step = t_iso + t_blk * D ** 4
+
+    def sample():
+        t0 = time.perf_counter()
+        choices = [hotrg.isometry(T, mu, nu, D) for nu in (1, 2, 3)]
+        t_iso = time.perf_counter() - t0
+        U = {ch.nu: ch.U for ch in choices}
+        t0 = time.perf_counter()
+        for b in range(blocks):
+            # one (x0, x2) pair and one kept column Y of the first pre-join axis
+            Ub = dict(U)
+            Ub[1] = U[1][:, :, b % D: b % D + 1]
+            hotrg.coarse_grain(T, T, Ub, mu, x0s=[b % D], x2s=[(b + 1) % D])
+        t_blk = (time.perf_counter() - t0) / blocks
+        # whole step: D^2 (x0, x2) pairs x D^2 (Y, Y') pairs of such blocks
+        return t_iso, t_blk, t_iso + t_blk * D ** 4
+
+    t_iso, t_blk, t_step = sample()
+    with threadpool_limits(limits=1):
+        t_iso1, t_blk1, t_step1 = sample()
     return {
         "value": 1.0 / t_step,
         "unit": "RG-steps/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"oracle FP64 NumPy, seeded random D={D} 4D tensor: the 6 HOSVD isometries of one step "
-                   f"({t_iso:.2f} s) plus {blocks} block(s) T'[x0,x2,Y,Y',:,:,:,:] of the block-spin "
-                   f"contraction ({t_blk:.2f} s each, 1/D^4 of the join), join scaled by D^4 = {D ** 4}"),
+        "extrapolated": True,
+        "sample": (f"oracle FP64 NumPy, seeded random D={D} 4D tensor (the shape of the Dcut={D} step): the 6 "
+                   f"HOSVD isometries of one step ({t_iso:.2f} s) plus {blocks} block(s) "
+                   f"T'[x0,x2,Y,Y',:,:,:,:] of the block-spin contraction ({t_blk:.2f} s each, 1/D^4 of the "
+                   f"join), join scaled by D^4 = {D ** 4}"),
+        "one_core": {"value": 1.0 / t_step1, "unit": "RG-steps/s", "cores": 1, "extrapolated": True,
+                     "isometries_s": t_iso1, "block_s": t_blk1},
+    }
+
+
+def start_cpu_baseline(dcut, blocks):
+    """The oracle baseline in a child process, so that it runs on the host
+    cores while the GPU runs the comparison precisions."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-only", "--dcut", str(dcut),
+           "--cpu-sample-blocks", str(blocks)]
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def finish_cpu_baseline(proc):
+    out, err = proc.communicate(timeout=600)
+    if proc.returncode != 0:
+        progress(f"cpu baseline failed: {err[-2000:]}")
+        return None
+    return json.loads(out.strip().splitlines()[-1])
+
+
+def serving_window(precision, rate, window, budget_gb=200.0):
+    """A time-boxed window of the serving stream: the first arrivals of a
+    Poisson stream of HOTRG solves (beta ~ U[0.1490, 0.1505], h uniform on
+    {0, 1e-6, 1e-5}, Dcut uniform on {6, 8, 10}, L = 2^k with k ~ U{4..10})
+    at `rate` per second, served by continuous batching for `window`
+    seconds; unfinished solves are censored and counted."""
+    from paper_1911_12954_amd.serve import Server, TrgBackend
+    from trg_inputs import serving_requests
+    n = max(1, int(rate * window * 2) + 8)
+    reqs = [r for r in serving_requests(n, rate, seed=0, dcuts=(6, 8, 10), kmin=4, kmax=10)
+            if r["arrival"] < window]
+    srv = Server(TrgBackend(precision), int(budget_gb * 2 ** 30))
+    progress(f"serving window: {len(reqs)} arrivals in {window:.0f} s")
+    summ = srv.serve(reqs, window=window)
+    waiting = len(reqs) - summ["completed"] - summ["censored_active"]
+    done_by = {}
+    for r in srv.results:
+        done_by.setdefault(str(r["dcut"]), []).append(r["latency"])
+    srv.close()
+    arrived_by = {}
+    for r in reqs:
+        arrived_by[str(r["dcut"])] = arrived_by.get(str(r["dcut"]), 0) + 1
+    return {
+        "solves_per_s": summ["solves_per_s"], "p50_latency_s": summ["p50_latency_s"],
+        "p99_latency_s": summ["p99_latency_s"], "join_precision": precision,
+        "window_s": window, "arrival_rate_per_s": rate, "arrived": len(reqs), "completed": summ["completed"],
+        "censored_running": summ["censored_active"], "censored_waiting": waiting,
+        "arrived_by_dcut": arrived_by, "completed_by_dcut": {k: len(v) for k, v in sorted(done_by.items())},
+        "mean_runs_per_step_call": summ["mean_runs_per_call"],
+        "stream": "Poisson, seed 0: beta~U[0.1490,0.1505], h in {0,1e-6,1e-5}, Dcut in {6,8,10}, L=2^k, "
+                  "k~U{4..10}; first arrivals within the window",
     }
 
 
@@ -429,6 +535,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only (the multi-GPU sharding of the "
                                    "step is a design, not built); use --gpus 1"}))
         sys.exit(2)
+    if a.cpu_only:
+        print(json.dumps(cpu_baseline(a.dcut, a.cpu_sample_blocks)), flush=True)
+        return
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.copy_cal > 0:
@@ -531,7 +640,7 @@ def main():
         return
     if a.method == "atrg":
         D = a.dcut if a.dcut != 10 else 24
-        prec = a.precision if a.precision != "bf16x3" else "fp64"
+        prec = a.precision if a.precision in ("fp64", "fp32") else "fp64"
         el, ms, nl, fl, lnz = time_atrg(prec, D, a.beta, a.warmup, a.steps)
         ach = fl / (ms * 1e-3) / 1e12 if ms > 0 else None
         print(json.dumps({
@@ -548,7 +657,12 @@ def main():
                          "gemm_share_of_step": ms * 1e-3 / el}}), flush=True)
         return
     D = a.dcut
-    elapsed, join_ms, launches, lnz = time_steps(a.precision, D, a.beta, a.warmup, a.steps, a.impure)
+    compare = [x for x in a.compare.split(",") if x in PEAK_TFLOPS and x != a.precision]
+    # ln Z/V of every precision is compared after the last step of the
+    # comparison runs (ramp of 4 steps, warm-up, timed steps)
+    probe_step = 4 + a.compare_warmup + a.compare_steps
+    head = time_steps(a.precision, D, a.beta, a.warmup, a.steps, a.impure, probe_step=probe_step)
+    elapsed, join_ms, launches = head["elapsed"], head["join_ms"], head["launches"]
     steps_per_s = a.steps / elapsed
     # each impure tensor adds the joins C(S, T) and C(T, S)
     joins_per_step = 5 if a.impure else 1
@@ -556,6 +670,7 @@ def main():
     mult = SPLIT_PRODUCTS.get(a.precision, 1.0)   # BF16 MFMA products per multiply-add
     achieved = alg_flops_step * a.steps / (join_ms * 1e-3) / 1e12 if join_ms > 0 else None
     peak = PEAK_TFLOPS[a.precision]
+    traffic = None if a.impure else join_traffic(a.precision, D)
     out = {
         "metric": "4D HOTRG RG-steps/s at Dcut=%d (steady-state step%s, 1 GPU)" % (
             D, ", impure E and M" if a.impure else ""),
@@ -575,7 +690,8 @@ def main():
         "config": {"workload": "4D Ising HOTRG, Dcut=%d, steady-state coarse-graining step%s, beta=%.4f, h=0, "
                                "join precision %s" % (D, " with impure E and M (5 joins)" if a.impure else "",
                                                       a.beta, a.precision),
-                   "dcut": D, "join_precision": a.precision, "lnZ_per_site_after_run": lnz},
+                   "dcut": D, "join_precision": a.precision, "lnZ_per_site_after_run": head["lnz"],
+                   "steps_in_run": head["steps_total"]},
         "roofline": {
             "bound": "mfma",
             "kernel": "gemm_nt_kernel (join, D^15 block-spin contraction)",
@@ -583,27 +699,47 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": (achieved / peak) if achieved else None,
-            "traffic": None if a.impure else JOIN_TRAFFIC.get((a.precision, D), {}).get("bytes_per_launch"),
-            "traffic_algorithmic": None if a.impure else
-            JOIN_TRAFFIC.get((a.precision, D), {}).get("algorithmic_bytes_per_launch"),
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "traffic_algorithmic": traffic["algorithmic_bytes_per_launch"] if traffic else None,
+            "traffic_counters": traffic["source"] if traffic else None,
             "join_launches": launches,
             "join_ms_per_step": join_ms / a.steps,
             "join_share_of_step": (join_ms * 1e-3) / elapsed,
             "mfma_issued_tflops": mult * achieved if achieved else None,
             "mfma_issued_frac": (mult * achieved / peak) if achieved else None,
+            "achieved_over_fp32_mfma_peak": (achieved / PEAK_TFLOPS["fp32"]) if achieved else None,
         },
     }
+    cpu_proc = None
+    if not a.no_cpu:
+        cpu_proc = start_cpu_baseline(D, a.cpu_sample_blocks)
     others = {}
-    for prec in [x for x in a.compare.split(",") if x in PEAK_TFLOPS and x != a.precision]:
-        e, jm, nl, _ = time_steps(prec, D, a.beta, 0, 1, a.impure)
-        ach = alg_flops_step / (jm * 1e-3) / 1e12
-        others[prec] = {"rg_steps_per_s": 1.0 / e, "join_tflops": ach, "frac_of_peak": ach / PEAK_TFLOPS[prec]}
+    for prec in compare:
+        r = time_steps(prec, D, a.beta, a.compare_warmup, a.compare_steps, a.impure, probe_step=probe_step)
+        ach = alg_flops_step * a.compare_steps / (r["join_ms"] * 1e-3) / 1e12
+        others[prec] = {"rg_steps_per_s": a.compare_steps / r["elapsed"], "warmup": a.compare_warmup,
+                        "steps": a.compare_steps, "join_tflops": ach, "frac_of_peak": ach / PEAK_TFLOPS[prec],
+                        "lnZ_per_site_after_step_%d" % probe_step: r["lnz"] if r["steps_total"] == probe_step
+                        else None}
     if others:
         out["other_precisions"] = others
         if "fp64" in others:
+            ref = others["fp64"]["lnZ_per_site_after_step_%d" % probe_step]
             out["speedup_vs_fp64_path"] = steps_per_s / others["fp64"]["rg_steps_per_s"]
-    if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(D, a.cpu_sample_blocks)
+            rel = lambda x: abs(x - ref) / abs(ref) if x is not None and ref is not None else None
+            errs = {a.precision: rel(head["probe"])}
+            for prec in others:
+                if prec != "fp64":
+                    errs[prec] = rel(others[prec]["lnZ_per_site_after_step_%d" % probe_step])
+            out["f_rel_err_vs_fp64_path"] = {"after_step": probe_step, **errs}
+            out["accuracy_records"] = ("f, E, M of whole runs against the FP64 path (4D Dcut 8, L = 1024, "
+                                       "h = 1e-5, and the other configurations): bench.py --accuracy")
+    if cpu_proc is not None:
+        cb = finish_cpu_baseline(cpu_proc)
+        if cb is not None:
+            out["cpu_baseline"] = cb
+    if not a.no_serve and a.method == "hotrg":
+        out["serving"] = serving_window(a.precision, a.window_rate, a.window_seconds)
     print(json.dumps(out), flush=True)
 
 

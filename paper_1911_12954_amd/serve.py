@@ -61,9 +61,9 @@ class TrgBackend:
         self.d = d
 
     def _precision(self, method):
-        """ATRG contracts in FP64 or FP32: a BF16x3 server runs its ATRG
-        requests with FP32 contractions."""
-        return "fp32" if method == "atrg" and self.precision == "bf16x3" else self.precision
+        """ATRG contracts in FP64 or FP32: a server with a split-BF16 join
+        (BF16x3 or BF16x6) runs its ATRG requests with FP32 contractions."""
+        return "fp32" if method == "atrg" and self.precision in ("bf16x3", "bf16x6") else self.precision
 
     def resident(self, req) -> int:
         from .trg import trg_resident_bytes
