@@ -109,7 +109,8 @@ typedef struct trg_step_rec {
 } trg_step_rec;
 
 /* Create a context holding the initial Ising site tensor T0 of the
- * d-dimensional model at inverse temperature beta >= 0 and field h (weight
+ * d-dimensional Ising model that the paper studies (Sec. 1; the 4D model of
+ * Sec. 3.1) at inverse temperature beta >= 0 and field h (weight
  * e^{-beta H}, H = -sum s_i s_j - h sum s_i), built from the bond split
  * W = [[sqrt(cosh b), sqrt(sinh b)], [sqrt(cosh b), -sqrt(sinh b)]] in closed
  * form, and the impure tensors requested by cfg->impure (S_E needs beta > 0).
@@ -177,7 +178,9 @@ int trg_init_factors(trg_ctx **out, int d, const int *dims, int r, const double 
 /* Singular values (descending, *n of them) of the latest ATRG swap. */
 int trg_atrg_spectrum(trg_ctx *ctx, double *out, int cap, int *n);
 
-/* Coarse-grain the periodic lattice L^d (L = 2^m, m >= 1): steps n along
+/* Coarse-grain the periodic lattice L^d (L = 2^m, m >= 1; each step halves
+ * the lattice, so the block volume reaches 2^n after n steps as in the
+ * caption of Fig. 5, Sec. 3.1, and 1024^4 takes 40 steps): steps n along
  * axis (n-1) mod d with cfg->dcut, using the context's method, from the
  * context's next step up to n = d*m (all d*m steps for a fresh context; a
  * context imported from a checkpoint finishes the lattice).  TRG_EINVAL if
@@ -187,7 +190,9 @@ int trg_run(trg_ctx *ctx, long long L);
 
 /* ln Z / V of the periodic lattice whose single block is the current tensor:
  * acc + 2^{-n} ln Tr T_n (Tr joins each backward leg to the forward leg of
- * the same axis).  Synchronises.  Caller owns *out. */
+ * the same axis).  This is the free energy per site up to the factor -1/beta
+ * that the paper compares between ATRG and HOTRG and over the bond
+ * dimension (Sec. 3.2, Figs. 7 and 8).  Synchronises.  Caller owns *out. */
 int trg_free_energy(trg_ctx *ctx, double *lnz_per_site);
 
 /* Degeneracy indicator of the current tensor T (the quantity the

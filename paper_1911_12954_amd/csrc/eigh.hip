@@ -162,7 +162,9 @@ jacobi_kernel(double *Aall, double *wall, double *Vall, int *sweeps_out, int n) 
 // CU thousands of times.  This solver reduces A to tridiagonal form with
 // Householder reflections (A <- H A H, H = I - 2 v v^T / v^T v, one column at
 // a time), accumulates Q = H_0 H_1 ..., then diagonalises the tridiagonal
-// matrix by implicit QL iterations with Wilkinson-type shifts.  Thread 0 runs
+// matrix by implicit QL iterations with Wilkinson-type shifts; the QL step
+// follows the order of the published tql2 procedure (Bowdler, Martin, Reinsch
+// and Wilkinson, Numer. Math. 11 (1968) 293-306).  Thread 0 runs
 // the scalar QL recurrence and records the Givens rotations of one sweep in
 // LDS; all threads then apply the sweep to their rows of the eigenvector
 // matrix.  Deterministic (fixed order everywhere).
