@@ -403,6 +403,191 @@ def contract(G: np.ndarray, H: np.ndarray, P: dict, mu: int, d: int):
     return Gn, Hn
 
 
+# -------------------------------------------------------------------- Z2 ---
+# The Ising tensor at h = 0 is invariant under the Z2 transformation that
+# acts on every leg index with (-1)^index in the W basis (index 0 even, 1
+# odd): its entries vanish unless the parities of all its legs add up to even.
+# In the "z2" mode every decomposition of the ATRG step is done sector by
+# sector, so the tensors stay exactly symmetric and the symmetric fixed point
+# of the ordered phase (X -> 2) survives (Sec. 3.2 follows X with ATRG;
+# reading: a trial matrix drawn across both sectors lets the randomized SVD
+# mix them, and over tens of steps in the ordered phase the mixture grows
+# until X -> 1).  Each leg index and each bond index carries a parity.
+
+
+def composite_parity(pars) -> np.ndarray:
+    """Parity of the row-major composite index of legs with the given
+    per-leg parity arrays (outermost first)."""
+    out = np.zeros(1, dtype=np.int64)
+    for p in pars:
+        out = ((out[:, None] + np.asarray(p, dtype=np.int64)[None, :]) % 2).reshape(-1)
+    return out
+
+
+def ising_factors_z2(beta: float, d: int):
+    """ising_factors at h = 0 with the bond rotated to definite parity:
+    u_e = (u_+ + u_-) / sqrt 2 (even |b|), u_o = (u_+ - u_-) / sqrt 2 (odd
+    |b|); likewise v.  Returns the factors, the leg parities [0, 1] of every
+    axis and the bond parities [0, 1]."""
+    F = ising_factors(beta, 0.0, d)
+    rot = np.array([[1.0, 1.0], [1.0, -1.0]]) / math.sqrt(2.0)
+    U = np.tensordot(F.U, rot, axes=([d], [0]))             # [b..., k]: k = e, o
+    V = np.tensordot(rot.T, F.V, axes=([1], [0]))           # [k, f...]
+    legs = [np.array([0, 1]) for _ in range(d)]
+    return Factors(U, np.ones(2), V), legs, np.array([0, 1])
+
+
+def _sectors(par):
+    return [np.nonzero(par == s)[0] for s in (0, 1)]
+
+
+def _qr_sectors(Y, rpar, csec):
+    """Orthonormal basis of the columns of Y, sector by sector (rows of
+    parity s, columns of sector s); columns beyond a sector's rank are 0."""
+    Q = np.zeros_like(Y)
+    for rows, cols in zip(_sectors(rpar), _sectors(csec)):
+        if len(rows) == 0 or len(cols) == 0:
+            continue
+        q, _ = np.linalg.qr(Y[np.ix_(rows, cols)])
+        Q[np.ix_(rows, cols[:q.shape[1]])] = q
+    return Q
+
+
+def _merge(parts, keep):
+    """parts: per sector (values descending, payload); returns the `keep`
+    largest values across sectors (even sector first on equal values) as
+    (value, sector, index in sector)."""
+    allv = [(-float(v), s, i) for s, vals in enumerate(parts) for i, v in enumerate(vals)]
+    allv.sort()
+    return [(-v, s, i) for v, s, i in allv[:keep]]
+
+
+def canonical_z2(G: np.ndarray, H: np.ndarray, dcut: int, legs, bond):
+    """canonical() sector by sector: the parity-s rows of G and columns of
+    H with the bonds of parity s; singular values of both sectors merged and
+    the largest dcut kept.  Returns the factors and the kept bonds' parities."""
+    d = G.ndim - 1
+    r = G.shape[-1]
+    Gm = G.reshape(-1, r)
+    Hm = H.reshape(r, -1)
+    rp = composite_parity(legs)
+    res = []
+    for rows, bonds in zip(_sectors(rp), _sectors(bond)):
+        if len(rows) == 0 or len(bonds) == 0:
+            res.append((np.zeros(0), None, None, rows))
+            continue
+        Qg, Rg = np.linalg.qr(Gm[np.ix_(rows, bonds)])
+        Qh, Rh = np.linalg.qr(Hm[np.ix_(bonds, rows)].T)
+        W, sv, Zt = np.linalg.svd(Rg @ Rh.T)
+        res.append((sv, Qg @ W, Zt @ Qh.T, rows))
+    nz = sum(int(np.count_nonzero(x[0] > 0)) for x in res)
+    k = min(dcut, nz or 1, sum(len(x[0]) for x in res))
+    kept = _merge([x[0] for x in res], k)
+    Um = np.zeros((Gm.shape[0], k))
+    Vm = np.zeros((k, Hm.shape[1]))
+    sv = np.zeros(k)
+    par = np.zeros(k, dtype=np.int64)
+    for j, (v, sec, i) in enumerate(kept):
+        _, Us, Vs, rows = res[sec]
+        Um[rows, j] = Us[:, i]
+        Vm[j, rows] = Vs[i]
+        sv[j] = v
+        par[j] = sec
+    for j in range(k):
+        col = np.abs(Um[:, j])
+        i = int(np.nonzero(col >= (1.0 - 1e-9) * col.max())[0][0])
+        if Um[i, j] < 0:
+            Um[:, j] = -Um[:, j]
+            Vm[j] = -Vm[j]
+    return Factors(Um.reshape(G.shape[:-1] + (k,)), sv, Vm.reshape((k,) + H.shape[1:])), par
+
+
+def rsvd_swap_z2(F: Factors, legs, bond, mu: int, dcut: int, p: int, q: int, step: int, seed: int):
+    """rsvd_swap with the swap matrix's two parity sectors kept apart: the
+    trial matrix keeps only the entries whose row parity (f_perp, k_B) equals
+    the sector of its column (column c in sector c mod 2), the QR
+    factorisations and the final SVD are done per sector, and the largest
+    dcut singular values of both sectors are kept.  Returns X, sigma, Y and
+    the parities of the new bond."""
+    d = F.d
+    Ut, Vt = _swap_operands(F, mu)
+    k = F.s.shape[0]
+    perp = [a for a in range(d) if a != mu]
+    nperp = int(np.prod(Ut.shape[1:-1]))
+    n = k * nperp
+    rpar = composite_parity([bond] + [legs[a] for a in perp])
+    cpar = composite_parity([legs[a] for a in perp] + [bond])
+    r = min(dcut + p, n)
+    csec = np.arange(r) % 2
+    Om = trial_matrix(n, r, step, seed) * (cpar[:, None] == csec[None, :])
+    Q = _qr_sectors(_apply(Ut, Vt, Om, False), rpar, csec)
+    for _ in range(q):
+        Z = _qr_sectors(_apply(Ut, Vt, Q, True), cpar, csec)
+        Q = _qr_sectors(_apply(Ut, Vt, Z, False), rpar, csec)
+    Bt = _apply(Ut, Vt, Q, True)                 # M^T Q, rows (f_perp, k_B)
+    res = []
+    for crows, cols in zip(_sectors(cpar), _sectors(csec)):
+        if len(crows) == 0 or len(cols) == 0:
+            res.append((np.zeros(0), None, None, crows, cols))
+            continue
+        Wb, sig, Zt = np.linalg.svd(Bt[np.ix_(crows, cols)].T, full_matrices=False)
+        res.append((sig, Wb, Zt, crows, cols))
+    keep = min(dcut, sum(len(x[0]) for x in res))
+    kept = _merge([x[0] for x in res], keep)
+    X = np.zeros((n, keep))
+    Y = np.zeros((keep, n))
+    sig = np.zeros(keep)
+    par = np.zeros(keep, dtype=np.int64)
+    for j, (v, sec, i) in enumerate(kept):
+        _, Wb, Zt, crows, cols = res[sec]
+        X[:, j] = Q[:, cols] @ Wb[:, i]
+        Y[j, crows] = Zt[i]
+        sig[j] = v
+        par[j] = sec
+    return X, sig, Y, par
+
+
+def isometries_z2(G: np.ndarray, H: np.ndarray, mu: int, d: int, dcut: int, legs):
+    """isometries() with each Gram's two pair-parity sectors diagonalised
+    apart and their spectra merged; returns the choices and the parities of
+    the new legs (those of the kept isometry columns)."""
+    perp = [a for a in range(d) if a != mu]
+    out, new_legs = [], {}
+    for nu, pair in zip(perp, grams(G, H, mu, d)):
+        dn = G.shape[nu]
+        n = dn * dn
+        k = min(n, dcut)
+        pp = composite_parity([legs[nu], legs[nu]])
+        res = []
+        for g in pair:
+            g = 0.5 * (g + g.T)
+            vals, vecs = [], []
+            for rows in _sectors(pp):
+                if len(rows) == 0:
+                    vals.append(np.zeros(0))
+                    vecs.append(None)
+                    continue
+                w, v = np.linalg.eigh(g[np.ix_(rows, rows)])
+                order = np.argsort(-w, kind="stable")
+                vals.append(w[order])
+                vecs.append((rows, v[:, order]))
+            merged = _merge(vals, n)
+            w = np.array([x[0] for x in merged])
+            V = np.zeros((n, n))
+            for j, (_, sec, i) in enumerate(merged):
+                rows, v = vecs[sec]
+                V[rows, j] = v[:, i]
+            res.append((w, V, float(np.sum(np.maximum(w[k:], 0.0)))))
+        eps_b, eps_f = res[0][2], res[1][2]
+        side = hotrg.SIDE_BACKWARD if eps_b < (1.0 - hotrg.TIE_REL) * eps_f else hotrg.SIDE_FORWARD
+        w, V, _ = res[side]
+        Pm = hotrg._kept_vectors(w, V, k)
+        new_legs[nu] = np.array([int(np.sum(Pm[pp == 1, j] ** 2) > np.sum(Pm[pp == 0, j] ** 2))
+                                 for j in range(k)])
+        out.append(hotrg.AxisChoice(nu, side, k, (eps_b, eps_f), w, False, Pm.reshape(dn, dn, k)))
+    return out, new_legs
+
+
 # ------------------------------------------------------------- step / run ---
 @dataclass
 class AtrgStep:
@@ -513,6 +698,32 @@ def atrg_step(F: Factors, mu: int, dcut: int, p: int, q: int, step: int, seed: i
     return Gn, Hn, c, rec, new_imps
 
 
+def atrg_step_z2(F: Factors, bond, legs, mu: int, dcut: int, p: int, q: int, step: int, seed: int, imps=None):
+    """atrg_step for the symmetric (h = 0) tensor with the swap and the HOSVD
+    done sector by sector.  `bond` and `legs` are the parities of F's bond
+    and of its legs; returns G', H' normalised, c, the record, the impurity
+    pairs (plain randomized SVDs: they do not feed back into the pure
+    tensor), the new legs' parities and the new bond's."""
+    d = F.d
+    X, sig, Y, lpar = rsvd_swap_z2(F, legs, bond, mu, dcut, p, q, step, seed)
+    G, H = _pieces(F, X, sig, Y, mu)
+    choices, new = isometries_z2(G, H, mu, d, dcut, legs)
+    P = {ch.nu: ch.U for ch in choices}
+    Gn, Hn = contract(G, H, P, mu, d)
+    r = Gn.shape[-1]
+    GtG = Gn.reshape(-1, r).T @ Gn.reshape(-1, r)
+    HHt = Hn.reshape(r, -1) @ Hn.reshape(r, -1).T
+    c = math.sqrt(float(np.sum(GtG * HHt)))
+    rec = AtrgStep(step, mu, math.log(c), sig, F.s, choices)
+    new_imps = []
+    for kind, (GS, HS) in enumerate(imps or []):
+        Gc, Hc = impurity_pieces_step(F, mu, GS, HS, kind, dcut, p, q, step, seed)
+        GSn, HSn = contract(Gc, Hc, P, mu, d)
+        new_imps.append((GSn / math.sqrt(c), HSn / math.sqrt(c)))
+    legs = [new.get(a, legs[a]) for a in range(d)]
+    return Gn / math.sqrt(c), Hn / math.sqrt(c), c, rec, new_imps, legs, lpar
+
+
 def periodic_trace(G: np.ndarray, H: np.ndarray) -> float:
     """Tr T for T = sum_l G[b..., l] H[l, f...] with each f_nu joined to b_nu."""
     r = G.shape[-1]
@@ -546,29 +757,46 @@ def indicator_x(G: np.ndarray, H: np.ndarray, axis: int = 0) -> float:
 
 
 def run(beta: float, h: float, d: int, dcut: int, L: int, p=None, q=None, seed: int = 0,
-        dense_swap: bool = False, impure: bool = False) -> AtrgResult:
+        dense_swap: bool = False, impure: bool = False, z2: bool = False) -> AtrgResult:
     """ATRG on the periodic L^d lattice: d*m steps along (n-1) mod d.  With
-    ``impure`` (beta > 0) also E = -Tr S_E / Tr T and M = Tr S_M / Tr T."""
+    ``impure`` (beta > 0) also E = -Tr S_E / Tr T and M = Tr S_M / Tr T.
+    ``z2`` (h = 0 only) keeps the pure tensor exactly Z2 symmetric."""
     m = int(round(math.log2(L)))
     if 2 ** m != L or m < 1:
         raise ValueError("L must be a power of two >= 2")
+    if z2 and (h != 0.0 or dense_swap):
+        raise ValueError("the Z2 mode needs h = 0 and the randomized swap")
     p = 4 * dcut if p is None else p
     q = 2 * dcut if q is None else q
-    F0 = ising_factors(beta, h, d)
+    if z2:
+        F0, legs, bond = ising_factors_z2(beta, d)
+    else:
+        F0 = ising_factors(beta, h, d)
     G, H = F0.U * 1.0, F0.V * 1.0
     r = G.shape[-1]
     c0 = math.sqrt(float(np.sum((G.reshape(-1, r).T @ G.reshape(-1, r)) * (H.reshape(r, -1) @ H.reshape(r, -1).T))))
     G, H = G / math.sqrt(c0), H / math.sqrt(c0)
-    imps = [(G.copy(), x / math.sqrt(c0)) for x in ising_impurity_pieces(beta, h, d)] if impure else None
+    imps = None
+    if impure:
+        pieces = ising_impurity_pieces(beta, h, d)
+        if z2:   # the impurity's bond rotated like the pure one
+            rot = np.array([[1.0, 1.0], [1.0, -1.0]]) / math.sqrt(2.0)
+            pieces = [np.tensordot(rot.T, x, axes=([1], [0])) for x in pieces]
+        imps = [(G.copy(), x / math.sqrt(c0)) for x in pieces]
     acc = math.log(c0)
     steps = []
     for n in range(1, d * m + 1):
         mu = (n - 1) % d
-        F = canonical(G, H, dcut)
-        if impure:
-            G, H, c, rec, imps = atrg_step(F, mu, dcut, p, q, n, seed, dense_swap, imps=imps)
+        if z2:
+            F, kpar = canonical_z2(G, H, dcut, legs, bond)
+            G, H, c, rec, imps2, legs, bond = atrg_step_z2(F, kpar, legs, mu, dcut, p, q, n, seed, imps)
+            imps = imps2 if impure else None
         else:
-            G, H, c, rec = atrg_step(F, mu, dcut, p, q, n, seed, dense_swap)
+            F = canonical(G, H, dcut)
+            if impure:
+                G, H, c, rec, imps = atrg_step(F, mu, dcut, p, q, n, seed, dense_swap, imps=imps)
+            else:
+                G, H, c, rec = atrg_step(F, mu, dcut, p, q, n, seed, dense_swap)
         acc += 2.0 ** (-n) * math.log(c)
         steps.append(rec)
     tr = periodic_trace(G, H)

@@ -233,3 +233,31 @@ def test_hosvd_grams_equal_explicit_two_site_gram(d, dims, mu, r):
         assert k == n or w_sorted[k - 1] - w_sorted[k] > 1e-6 * w_sorted[0]
         U = ch.U.reshape(n, k)
         assert np.allclose(U @ U.T, lead @ lead.T, atol=1e-10)
+
+
+@pytest.mark.parametrize("d,L,beta", [(2, 4, 0.3), (2, 4, 0.6), (3, 2, 0.25)])
+def test_z2_mode_untruncated_equals_brute_force(d, L, beta):
+    """The sector-by-sector ATRG of the symmetric (h = 0) tensor is exact
+    when nothing is truncated."""
+    r = atrg.run(beta, 0.0, d, 128, L, p=8, q=2, z2=True)
+    assert abs(r.ln_z_per_site - exact.brute_force(beta, 0.0, d, L)[0]) < 1e-12
+
+
+def test_z2_mode_keeps_the_symmetric_fixed_point_in_4d():
+    """4D, beta = 0.2 (deep in the ordered phase), h = 0, L = 1024, Dcut 6:
+    with the sectors kept apart the pure tensor stays exactly symmetric, so
+    M = 0 and the degeneracy indicator X = 2 (Sec. 3.1-3.2); the plain
+    randomized swap has already broken the symmetry at this bond dimension
+    (M ~ 3e-4, X below 2), while f agrees."""
+    z = atrg.run(0.2, 0.0, 4, 6, 1024, z2=True, impure=True)
+    plain = atrg.run(0.2, 0.0, 4, 6, 1024, impure=True)
+    assert abs(z.magnetization) < 1e-12
+    assert abs(atrg.indicator_x(z.G, z.H, 0) - 2.0) < 1e-10
+    assert abs(plain.magnetization) > 1e-6
+    assert abs(z.ln_z_per_site - plain.ln_z_per_site) < 1e-10 * abs(plain.ln_z_per_site)
+
+
+def test_z2_mode_disordered_phase_gives_x_one():
+    """4D, beta = 0.12 (disordered), h = 0: X -> 1 in the Z2 mode too."""
+    z = atrg.run(0.12, 0.0, 4, 4, 1024, z2=True)
+    assert abs(atrg.indicator_x(z.G, z.H, 0) - 1.0) < 1e-6
