@@ -136,11 +136,16 @@ int trg_hotrg_step(trg_ctx *ctx, int axis, int dcut);
 
 /* The same step for n distinct contexts that share d, join precision,
  * current dims and the stream.  The Gram eigendecompositions of all n
- * contexts (every transverse axis, both sides) run in one batched launch;
- * the Gram products, the operand builds, the joins, the post-join maps and
- * the normalisations are then enqueued context by context on the shared
- * stream (through the shared workspace when trg_share_workspace was used).
- * Results are bit-identical to n separate trg_hotrg_step calls.
+ * contexts (every transverse axis, both sides) run in one launch; the Gram
+ * products are formed context by context; then every kernel of the
+ * contraction and the normalisation -- operand builds, zero padding, the
+ * joins, the post-join maps, the norm and the scaling -- is launched once for
+ * all contexts with the same impurities (up to 64 per launch, each context
+ * in its own slot of the workspace of the first context of the batch).  The
+ * batch's workspace budget is the sum of its contexts' cfg.workspace_bytes
+ * (85 % of the free device memory if one of them is 0); contexts that do
+ * not fit in it together are stepped in consecutive groups.  Results are
+ * bit-identical to n separate trg_hotrg_step calls.
  * Errors: TRG_EINVAL (NULL or duplicate context, mismatched contexts, bad
  * axis or dcut) and TRG_ESTATE (a poisoned context) leave every context
  * unchanged.  TRG_EHIP or TRG_ENUMERIC poisons every context of the batch.

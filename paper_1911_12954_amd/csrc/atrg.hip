@@ -194,28 +194,29 @@ chol_inv_kernel(const double *C, int n, double shift_coef, double *R, double *Ri
   }
 }
 
-// The same factorisation for n <= 128 with both triangles packed in LDS
-// (row i of an upper triangle starts at i n - i (i - 1) / 2), right-looking:
-// after row j of R is formed, the trailing triangle is updated by all
-// threads at once (A[p][q] -= R[j][p] R[j][q]); the inverse likewise, from
-// the last row up (X[p][j] -= R[p][k] X[k][j] once row k of X is final).
-// Every element update is independent, so no thread runs a long chain; the
-// four waves take every fourth row of an update, the lanes its columns.
-constexpr int CHOL_PACK_MAX = 128;
-__device__ inline int tri(int i, int j, int n) { return i * n - (i * (i - 1)) / 2 + (j - i); }
-
+// The same factorisation for n <= 128 with the matrix in registers: a 16 x 16
+// grid of threads, thread (ti, tj) holding the 8 x 8 elements (ti + 16 a,
+// tj + 16 b).  Right-looking by columns, two barriers each: the owners of
+// row j scale it by the pivot and publish it in LDS, then every thread
+// updates its elements of the trailing triangle (A[p][q] -= R[j][p] R[j][q]);
+// the owner of the next diagonal element publishes it.  The inverse runs the
+// same way from the last row up (X[p][q] -= R[p][k] X[k][q] once row k of X
+// is final) with R read from LDS.  Each element sees the operations of the
+// column-by-column elimination in the same order as a one-thread-per-element
+// elimination would apply them.
+constexpr int CHOL_REG_MAX = 128;
 constexpr int CHOL_THREADS = 256;
 
 __global__ void __launch_bounds__(CHOL_THREADS)
-chol_inv_packed_kernel(const double *C, int n, double shift_coef, double *Rg, double *Rinv, int *err) {
-  extern __shared__ double lds[];
-  const int npk = n * (n + 1) / 2;
-  double *R = lds, *I = lds + npk;
+chol_inv_reg_kernel(const double *C, int n, double shift_coef, double *Rg, double *Rinv, int *err) {
+  extern __shared__ double Rl[];   // n x n: R for the inverse
   __shared__ double sh[CHOL_THREADS];
   __shared__ double shm[CHOL_THREADS];
-  __shared__ int dead[CHOL_PACK_MAX];
-  __shared__ double piv;
+  __shared__ int dead[CHOL_REG_MAX];
+  __shared__ double rowbuf[CHOL_REG_MAX];
+  __shared__ double diag;
   const int t = threadIdx.x;
+  const int ti = t >> 4, tj = t & 15;
   double tr = 0.0, mx = 0.0;
   for (int i = t; i < n; i += CHOL_THREADS) {
     tr += C[i * n + i];
@@ -233,75 +234,131 @@ chol_inv_packed_kernel(const double *C, int n, double shift_coef, double *Rg, do
   }
   const double shift = shift_coef * sh[0];
   const double tol = 1e-26 * (shm[0] + shift);
-  __syncthreads();
-  for (int idx = t; idx < n * n; idx += CHOL_THREADS) {
-    const int r = idx / n, c = idx % n;
-    if (r <= c) {
-      R[tri(r, c, n)] = C[idx] + (r == c ? shift : 0.0);
-      I[tri(r, c, n)] = r == c ? 1.0 : 0.0;
+  double A[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int r = ti + 16 * a, c = tj + 16 * b;
+      A[a][b] = (r <= c && c < n) ? C[r * n + c] + (r == c ? shift : 0.0) : 0.0;
     }
-  }
   for (int i = t; i < n; i += CHOL_THREADS) dead[i] = 0;
+  if (t == 0) diag = C[0] + shift;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    if (t == 0) {
-      double dj = R[tri(j, j, n)];   // all updates from the rows above applied
-      if (!(dj > tol)) {
-        if (!isfinite(dj)) *err |= 4;
-        dead[j] = 1;
-        dj = 1.0;
+    const int aj = j >> 4;
+    if (ti == (j & 15)) {
+      // row j: its diagonal has received the updates of every row above
+      double dj = diag;
+      const bool isdead = !(dj > tol);
+      if (isdead) dj = 1.0;
+      const double piv = sqrt(dj);
+      if (tj == (j & 15)) {
+        dead[j] = isdead ? 1 : 0;
+        if (isdead && !isfinite(diag)) *err |= 4;
       }
-      piv = sqrt(dj);
-      R[tri(j, j, n)] = piv;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int c = tj + 16 * b;
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+          if (a == aj) {
+            if (c == j) {
+              A[a][b] = piv;
+            } else if (c > j && c < n) {
+              const double v = isdead ? 0.0 : A[a][b] / piv;
+              A[a][b] = v;
+              rowbuf[c] = v;
+            }
+          }
+      }
     }
     __syncthreads();
-    const bool dj_dead = dead[j] != 0;
-    const double rjj = piv;
-    for (int i = j + 1 + t; i < n; i += CHOL_THREADS) {
-      const int o = tri(j, i, n);
-      R[o] = dj_dead ? 0.0 : R[o] / rjj;
+    // trailing triangle j < p <= q
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int p = ti + 16 * a;
+      if (p > j && p < n) {
+        const double rp = rowbuf[p];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int q = tj + 16 * b;
+          if (q >= p && q < n) A[a][b] -= rp * rowbuf[q];
+        }
+      }
     }
-    __syncthreads();
-    const int rowj = tri(j, 0, n);   // R[j][q] = R[rowj + q]
-    for (int p = j + 1 + (t >> 6); p < n; p += CHOL_THREADS / 64) {
-      const double rjp = R[rowj + p];
-      const int rowp = tri(p, 0, n);
-      for (int q = p + (t & 63); q < n; q += 64) R[rowp + q] -= rjp * R[rowj + q];
+    const int jn = j + 1;
+    if (jn < n && ti == (jn & 15) && tj == (jn & 15)) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (a == (jn >> 4)) diag = A[a][a];
     }
     __syncthreads();
   }
-  // inverse: rows of X = R^-1 from the bottom; dead rows of R are unit rows
+  // R to LDS (upper triangle; the lower one is never read), X = I in registers
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int r = ti + 16 * a, c = tj + 16 * b;
+      if (r <= c && c < n) Rl[r * n + c] = A[a][b];
+      A[a][b] = (r == c && c < n) ? 1.0 : 0.0;
+    }
+  __syncthreads();
   for (int k = n - 1; k >= 0; --k) {
-    const double inv = 1.0 / R[tri(k, k, n)];
-    for (int j = k + t; j < n; j += CHOL_THREADS) I[tri(k, j, n)] *= inv;
+    const int ak = k >> 4;
+    if (ti == (k & 15)) {
+      const double inv = 1.0 / Rl[k * n + k];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int c = tj + 16 * b;
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+          if (a == ak && c >= k && c < n) {
+            A[a][b] *= inv;
+            rowbuf[c] = A[a][b];
+          }
+      }
+    }
     __syncthreads();
-    const int rowk = tri(k, 0, n);
-    for (int p = t >> 6; p < k; p += CHOL_THREADS / 64) {
-      const int rowp = tri(p, 0, n);
-      const double rpk = R[rowp + k];
-      for (int jj = k + (t & 63); jj < n; jj += 64) I[rowp + jj] -= rpk * I[rowk + jj];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int p = ti + 16 * a;
+      if (p < k) {
+        const double rpk = Rl[p * n + k];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int q = tj + 16 * b;
+          if (q >= k && q < n) A[a][b] -= rpk * rowbuf[q];
+        }
+      }
     }
     __syncthreads();
   }
-  for (int idx = t; idx < n * n; idx += CHOL_THREADS) {
-    const int r = idx / n, c = idx % n;
-    Rinv[idx] = (r <= c && !dead[c]) ? I[tri(r, c, n)] : 0.0;
-    Rg[idx] = (r <= c && !dead[r]) ? R[tri(r, c, n)] : 0.0;
-  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int r = ti + 16 * a, c = tj + 16 * b;
+      if (r < n && c < n) {
+        Rinv[r * n + c] = (r <= c && !dead[c]) ? A[a][b] : 0.0;
+        Rg[r * n + c] = (r <= c && !dead[r]) ? Rl[r * n + c] : 0.0;
+      }
+    }
 }
 
 void launch_chol_inv(const double *C, int n, double shift, double *R, double *Rinv, int *err, hipStream_t st) {
   TRG_REQUIRE(n >= 1 && n <= 1024, "chol: bad order");
-  if (n <= CHOL_PACK_MAX) {
-    const size_t lds = size_t(n) * (n + 1) * 8;   // two packed triangles
+  if (n <= CHOL_REG_MAX) {
+    const size_t lds = size_t(n) * n * 8;   // R for the inverse
     static bool attr = false;
     if (!attr) {
-      TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&chol_inv_packed_kernel),
+      TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&chol_inv_reg_kernel),
                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        CHOL_PACK_MAX * (CHOL_PACK_MAX + 1) * 8));
+                                        CHOL_REG_MAX * CHOL_REG_MAX * 8));
       attr = true;
     }
-    hipLaunchKernelGGL(chol_inv_packed_kernel, dim3(1), dim3(CHOL_THREADS), lds, st, C, n, shift, R, Rinv, err);
+    hipLaunchKernelGGL(chol_inv_reg_kernel, dim3(1), dim3(CHOL_THREADS), lds, st, C, n, shift, R, Rinv, err);
   } else {
     hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, st, C, n, shift, R, Rinv, err);
   }

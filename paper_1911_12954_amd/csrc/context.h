@@ -58,6 +58,10 @@ inline View rename(View v, const std::map<std::string, std::string> &m) {
 void apply_map(const void *in, int in_kind, const View &inv, const double *U,
                const std::map<std::string, int64_t> &u_strides, const std::vector<std::string> &sums,
                void *out, int out_kind, int64_t lo_plane, const View &outv, hipStream_t st);
+// the same map for nb contexts in one launch (context i: ins[i], Us[i], outs[i])
+void apply_map_batch(const void *const *ins, int in_kind, const View &inv, const double *const *Us,
+                     const std::map<std::string, int64_t> &u_strides, const std::vector<std::string> &sums,
+                     void *const *outs, int nb, int out_kind, int64_t lo_plane, const View &outv, hipStream_t st);
 
 inline std::string nm(const char *p, int ax) { return std::string(p) + std::to_string(ax); }
 

@@ -39,6 +39,12 @@ namespace trg {
 void apply_map(const void *in, int in_kind, const View &inv, const double *U,
                const std::map<std::string, int64_t> &u_strides, const std::vector<std::string> &sums,
                void *out, int out_kind, int64_t lo_plane, const View &outv, hipStream_t st) {
+  apply_map_batch(&in, in_kind, inv, &U, u_strides, sums, &out, 1, out_kind, lo_plane, outv, st);
+}
+
+void apply_map_batch(const void *const *ins, int in_kind, const View &inv, const double *const *Us,
+                     const std::map<std::string, int64_t> &u_strides, const std::vector<std::string> &sums,
+                     void *const *outs, int nb, int out_kind, int64_t lo_plane, const View &outv, hipStream_t st) {
   std::vector<MapDim> dims;
   for (const auto &o : outv) {
     MapDim m{o.size, o.stride, 0, 0};
@@ -56,8 +62,8 @@ void apply_map(const void *in, int in_kind, const View &inv, const double *U,
     if (it == u_strides.end()) throw Error(-1, "internal: summed leg without U stride");
     ss.push_back(MapSum{l.size, l.stride, it->second});
   }
-  tensor_map(in, in_kind, U, out, out_kind, lo_plane, dims.data(), int(dims.size()), ss.data(),
-             int(ss.size()), st);
+  tensor_map_batch(ins, in_kind, Us, outs, nb, out_kind, lo_plane, dims.data(), int(dims.size()), ss.data(),
+                   int(ss.size()), st);
 }
 
 }  // namespace trg
@@ -151,9 +157,13 @@ struct StepShape {
 // Operand of site 1 (A) or site 2 (Bt) for outer-leg values [o0, o0 + cnt):
 // rows (outer, pair legs of post axes, compressed pre legs), columns
 // (i, b_s..., a'_s...).  Written with row stride Kpad, rows padded to Mpad,
-// in the join precision.
-void build_operand(trg_ctx &c, const StepShape &sh, const double *X, bool site1, int o0, int cnt,
-                   void *out, int64_t Mpad, const std::string &tmp_tag) {
+// in the join precision.  For the nb contexts of a batch at once: context b
+// reads Xs[b] with its own isometries and writes out + b * out_slot bytes
+// (temporaries in slots of tmp_slot bytes); every kernel is one launch.
+void build_operand(std::vector<trg_ctx *> &cs, const StepShape &sh, const double *const *Xs, bool site1, int o0,
+                   int cnt, char *out, size_t out_slot, int64_t Mpad, const std::string &tmp_tag) {
+  trg_ctx &c = *cs[0];
+  const int nb = int(cs.size());
   const int d = c.d, mu = sh.mu;
   auto st_ = canon_strides(c.dims, d);
   // view of X with names of the roles it plays
@@ -172,7 +182,8 @@ void build_operand(trg_ctx &c, const StepShape &sh, const double *X, bool site1,
       v.push_back(Leg{nm(site1 ? "ap" : "bp", ax), c.dims[ax], st_[2 * ax + 1]});
     }
   }
-  const double *src = X + int64_t(o0) * (site1 ? st_[2 * mu] : st_[2 * mu + 1]);
+  std::vector<const void *> cur(nb);
+  for (int b = 0; b < nb; ++b) cur[b] = Xs[b] + int64_t(o0) * (site1 ? st_[2 * mu] : st_[2 * mu + 1]);
   // final layout
   std::vector<std::pair<std::string, int64_t>> rows{{"o", cnt}}, cols{{"i", c.dims[mu]}};
   for (int r : sh.post) {
@@ -183,8 +194,6 @@ void build_operand(trg_ctx &c, const StepShape &sh, const double *X, bool site1,
   for (int s : sh.pre) cols.push_back({nm("b", s), c.dims[s]});
   for (int s : sh.pre) cols.push_back({nm("ap", s), c.dims[s]});
   View colv = contiguous(cols);
-  int64_t ncols = view_count(colv);
-  (void)ncols;
   View rowv = contiguous(rows, sh.Kpad);
   View finalv = rowv;
   finalv.insert(finalv.end(), colv.begin(), colv.end());
@@ -196,8 +205,9 @@ void build_operand(trg_ctx &c, const StepShape &sh, const double *X, bool site1,
                                                : OUT_BF16X3;
   const int esz = sh.prec == TRG_FP64 ? 8 : (sh.prec == TRG_FP32 ? 4 : 2);
   const int64_t lo_plane = Mpad * sh.Kpad;
+  std::vector<void *> outs(nb);
+  for (int b = 0; b < nb; ++b) outs[b] = out + size_t(b) * out_slot;
 
-  const double *cur = src;
   View curv = v;
   for (size_t j = 0; j < sh.pre.size(); ++j) {
     const int s = sh.pre[j];
@@ -217,9 +227,11 @@ void build_operand(trg_ctx &c, const StepShape &sh, const double *X, bool site1,
       produced = {{nm("ap", s), ds}, {nm("L", s), ks}};
     }
     const bool last = j + 1 == sh.pre.size();
-    const double *Us = static_cast<const double *>(c.U[s].ptr);
+    std::vector<const double *> Us(nb);
+    for (int b = 0; b < nb; ++b) Us[b] = static_cast<const double *>(cs[b]->U[s].ptr);
     if (last) {
-      apply_map(cur, IN_F64, curv, Us, us, {summed}, out, out_kind, lo_plane, finalv, c.st);
+      apply_map_batch(cur.data(), IN_F64, curv, Us.data(), us, {summed}, outs.data(), nb, out_kind, lo_plane, finalv,
+                      c.st);
     } else {
       std::vector<std::pair<std::string, int64_t>> legs;
       for (const auto &l : curv) {
@@ -230,19 +242,26 @@ void build_operand(trg_ctx &c, const StepShape &sh, const double *X, bool site1,
         }
       }
       View tv = contiguous(legs);
-      double *tmp = c.wsp<double>("op_tmp" + tmp_tag, size_t(view_count(tv)) * 8);
-      apply_map(cur, IN_F64, curv, Us, us, {summed}, tmp, OUT_F64, 0, tv, c.st);
-      cur = tmp;
+      const size_t slot = size_t(view_count(tv)) * 8;
+      char *tmp = c.wsp<char>("op_tmp" + tmp_tag, slot * nb);
+      std::vector<void *> tmps(nb);
+      for (int b = 0; b < nb; ++b) tmps[b] = tmp + size_t(b) * slot;
+      apply_map_batch(cur.data(), IN_F64, curv, Us.data(), us, {summed}, tmps.data(), nb, OUT_F64, 0, tv, c.st);
+      for (int b = 0; b < nb; ++b) cur[b] = tmps[b];
       curv = tv;
     }
   }
-  zero_pad(out, M, Mpad, sh.Kdim, sh.Kpad, esz, operand_planes(sh.prec), lo_plane, c.st);
+  zero_pad(out, M, Mpad, sh.Kdim, sh.Kpad, esz, operand_planes(sh.prec), lo_plane, c.st, nb,
+           int64_t(out_slot / esz));
 }
 
 // Compress the post-axis pairs of a join block E (rows x0-block, cols
-// x2-block) and write the new tensor's slab T'[x0a.., x2a..].
-void post_join(trg_ctx &c, const StepShape &sh, const void *E, int64_t ldc, int x0a, int c0, int x2a,
-               int c2, double *Tout) {
+// x2-block) and write the new tensor's slab T'[x0a.., x2a..]: context b of
+// the batch reads E + b * e_slot bytes and writes Touts[b].
+void post_join(std::vector<trg_ctx *> &cs, const StepShape &sh, const char *E, size_t e_slot, int64_t ldc, int x0a,
+               int c0, int x2a, int c2, double *const *Touts) {
+  trg_ctx &c = *cs[0];
+  const int nb = int(cs.size());
   const int d = c.d, mu = sh.mu;
   const int in_kind = sh.prec == TRG_FP64 ? IN_F64 : IN_F32;
   std::vector<std::pair<std::string, int64_t>> rows{{"o1", c0}}, cols{{"o2", c2}};
@@ -269,27 +288,41 @@ void post_join(trg_ctx &c, const StepShape &sh, const void *E, int64_t ldc, int 
       outv.push_back(Leg{nm("L", ax), sh.nd[ax], nst[2 * ax + 1]});
     }
   }
-  double *dst = Tout + int64_t(x0a) * nst[2 * mu] + int64_t(x2a) * nst[2 * mu + 1];
+  std::vector<const void *> ins(nb);
+  std::vector<void *> dsts(nb);
+  for (int b = 0; b < nb; ++b) {
+    ins[b] = E + size_t(b) * e_slot;
+    dsts[b] = Touts[b] + int64_t(x0a) * nst[2 * mu] + int64_t(x2a) * nst[2 * mu + 1];
+  }
   if (sh.post.empty()) {
-    apply_map(E, in_kind, ev, nullptr, {}, {}, dst, OUT_F64, 0, outv, c.st);
+    std::vector<const double *> none(nb, nullptr);
+    apply_map_batch(ins.data(), in_kind, ev, none.data(), {}, {}, dsts.data(), nb, OUT_F64, 0, outv, c.st);
     return;
   }
   if (sh.post.size() != 1) throw Error(-1, "internal: more than one post axis");
   const int r = sh.post[0];
   const int64_t dr = c.dims[r], kr = sh.nd[r];
-  const double *Ur = static_cast<const double *>(c.U[r].ptr);
+  std::vector<const double *> Us(nb);
+  for (int b = 0; b < nb; ++b) Us[b] = static_cast<const double *>(cs[b]->U[r].ptr);
   // (a_r, b_r) -> K_r into a contiguous temporary
   std::vector<std::pair<std::string, int64_t>> tl;
   for (const auto &l : ev)
     if (l.name != nm("a", r) && l.name != nm("b", r)) tl.push_back({l.name, l.size});
   tl.push_back({nm("K", r), kr});
   View tv = contiguous(tl);
-  double *tmp = c.wsp<double>("post_tmp", size_t(view_count(tv)) * 8);
-  apply_map(E, in_kind, ev, Ur, {{nm("a", r), dr * kr}, {nm("b", r), kr}, {nm("K", r), 1}},
-            {nm("a", r), nm("b", r)}, tmp, OUT_F64, 0, tv, c.st);
+  const size_t slot = size_t(view_count(tv)) * 8;
+  char *tmp = c.wsp<char>("post_tmp", slot * nb);
+  std::vector<void *> tmps(nb);
+  std::vector<const void *> tmpin(nb);
+  for (int b = 0; b < nb; ++b) {
+    tmps[b] = tmp + size_t(b) * slot;
+    tmpin[b] = tmps[b];
+  }
+  apply_map_batch(ins.data(), in_kind, ev, Us.data(), {{nm("a", r), dr * kr}, {nm("b", r), kr}, {nm("K", r), 1}},
+                  {nm("a", r), nm("b", r)}, tmps.data(), nb, OUT_F64, 0, tv, c.st);
   // (a'_r, b'_r) -> L_r into the new tensor
-  apply_map(tmp, IN_F64, tv, Ur, {{nm("ap", r), dr * kr}, {nm("bp", r), kr}, {nm("L", r), 1}},
-            {nm("ap", r), nm("bp", r)}, dst, OUT_F64, 0, outv, c.st);
+  apply_map_batch(tmpin.data(), IN_F64, tv, Us.data(), {{nm("ap", r), dr * kr}, {nm("bp", r), kr}, {nm("L", r), 1}},
+                  {nm("ap", r), nm("bp", r)}, dsts.data(), nb, OUT_F64, 0, outv, c.st);
 }
 
 void record_join(trg_ctx &c, hipEvent_t &a, hipEvent_t &b, bool begin) {
@@ -304,15 +337,20 @@ void record_join(trg_ctx &c, hipEvent_t &a, hipEvent_t &b, bool begin) {
   }
 }
 
-void join(trg_ctx &c, int prec, const void *A, const void *Bt, void *E, int64_t Mpad, int64_t Npad,
-          int64_t Kpad, bool accum) {
+// The join of nb contexts in one launch: product b reads A + b * a_slot and
+// Bt + b * b_slot and writes E + b * e_slot (bytes).  A batched launch is
+// timed and counted on the batch's first context.
+void join(trg_ctx &c, int prec, const char *A, size_t a_slot, const char *Bt, size_t b_slot, char *E, size_t e_slot,
+          int nb, int64_t Mpad, int64_t Npad, int64_t Kpad, bool accum) {
   hipEvent_t a{}, b{};
   record_join(c, a, b, true);
+  const int ein = prec == TRG_FP64 ? 8 : (prec == TRG_FP32 ? 4 : 2);   // bytes of one element of one plane
+  const int eout = prec == TRG_FP64 ? 8 : 4;
   gemm_nt(prec, A, Bt, E, uint64_t(Mpad), uint64_t(Npad), uint64_t(Kpad), uint64_t(Kpad), uint64_t(Kpad),
-          uint64_t(Npad), accum, c.st);
+          uint64_t(Npad), accum, c.st, uint32_t(nb), a_slot / ein, b_slot / ein, e_slot / eout);
   record_join(c, a, b, false);
   c.join_launches += 1;
-  c.join_flops_pending += 2.0 * double(Mpad) * double(Npad) * double(Kpad);
+  c.join_flops_pending += 2.0 * double(Mpad) * double(Npad) * double(Kpad) * nb;
 }
 
 struct StepPrep {
@@ -342,7 +380,6 @@ StepPrep prepare_step(trg_ctx &c, int mu, int dcut) {
   p.ri = rec_i(c, p.n_step);
   return p;
 }
-
 // Gram matrices of every context into one buffer, one batched Jacobi launch
 // for all of them, then each context's isometry selection.  Every matrix is
 // processed by its own workgroup, so a batch gives the same bits as single
@@ -416,11 +453,18 @@ void isometries_batch(std::vector<trg_ctx *> &cs, std::vector<StepPrep> &ps, int
   }
 }
 
-void contract_step(trg_ctx &c, StepPrep &prep, int mu) {
+// Block-spin contraction, normalisation and bookkeeping of one step for
+// contexts of equal shape (d, dims, join precision, impurities), every kernel
+// launched once for up to TRG_MAXB of them: the join plan (x0 slices of A,
+// x2 slices of Bt) is that of one context, and the batch is cut into chunks
+// whose join workspaces fit the budget together.  Context b of a chunk uses
+// slot b of each operand buffer; the results do not depend on the chunking.
+void contract_batch(std::vector<trg_ctx *> all, std::vector<StepPrep *> preps, int mu) {
+  trg_ctx &c = *all[0];
   const int d = c.d;
-  StepShape &sh = prep.sh;
-  const int n_step = prep.n_step;
-  double *rd = prep.rd;
+  // the contexts share the shape of the step, not its number: each keeps its
+  // own step count (accumulator weight 2^-n, records)
+  StepShape &sh = preps[0]->sh;
   // ---- 3: block-spin contraction, sliced over x0 (A) and x2 (Bt)
   const GemmTile tile = gemm_tile(sh.prec);
   sh.Mr = 1;
@@ -429,6 +473,11 @@ void contract_step(trg_ctx &c, StepPrep &prep, int mu) {
   sh.Kdim = c.dims[mu];
   for (int s : sh.pre) sh.Kdim *= int64_t(c.dims[s]) * c.dims[s];
   sh.Kpad = int64_t(round_up(sh.Kdim, tile.k));
+  for (auto *p : preps) {
+    p->sh.Mr = sh.Mr;
+    p->sh.Kdim = sh.Kdim;
+    p->sh.Kpad = sh.Kpad;
+  }
   const int esz = operand_bytes(sh.prec);  // per element, all planes
   const int esE = sh.prec == TRG_FP64 ? 8 : 4;
   const int nt = 1 + c.nimp;
@@ -447,94 +496,146 @@ void contract_step(trg_ctx &c, StepPrep &prep, int mu) {
     if (!sh.post.empty()) b += e1 * 8.0;
     return b;
   };
-  double budget = double(c.cfg.workspace_bytes);
-  if (budget <= 0) {
+  // budget of the batch: every context brings its cfg.workspace_bytes (the
+  // batched launches hold one slot per context); without a cap on some
+  // context, 85 % of the free device memory
+  double budget = 0.0;
+  bool capped = true;
+  for (auto *x : all) {
+    capped = capped && x->cfg.workspace_bytes > 0;
+    budget += double(x->cfg.workspace_bytes);
+  }
+  if (!capped) {
     size_t fr = 0, tot = 0;
     TRG_HIP_CHECK(hipMemGetInfo(&fr, &tot));
     budget = 0.85 * double(fr + c.ws_held()) - 2.0e9;
   }
-  // natural plan: Bt whole, A in slices of about JOIN_ROWS GEMM rows; the
-  // memory budget can only shrink it
+  // natural plan, sized to one context's share: Bt whole, A in slices of
+  // about JOIN_ROWS GEMM rows; the memory budget can only shrink it (the
+  // slicing does not change any result)
+  const double share = budget / double(all.size());
   int c2 = dmu;
-  while (c2 > 1 && bytes_for(1, c2) > budget) --c2;
-  if (bytes_for(1, c2) > budget) throw Error(TRG_ENOMEM, "join workspace does not fit the memory budget");
+  while (c2 > 1 && bytes_for(1, c2) > share) --c2;
+  if (bytes_for(1, c2) > share) throw Error(TRG_ENOMEM, "join workspace does not fit the memory budget");
   const int c0_max = int(std::max<int64_t>(1, std::min<int64_t>(dmu, JOIN_ROWS / sh.Mr)));
   int c0 = 1;
-  while (c0 < c0_max && bytes_for(c0 + 1, c2) <= budget) ++c0;
+  while (c0 < c0_max && bytes_for(c0 + 1, c2) <= share) ++c0;
+  // contexts per launch
+  const int fit = int(std::max(1.0, std::floor(budget / bytes_for(c0, c2))));
+  const int chunk = std::min({fit, TRG_MAXB, int(all.size())});
 
   const int64_t cap_tensor = [&] {
     int64_t n = 1;
     for (int ax = 0; ax < d; ++ax) n *= int64_t(sh.nd[ax]) * sh.nd[ax];
     return n;
   }();
-  c.ensure(c.Tn, size_t(cap_tensor) * 8);
-  for (int j = 0; j < c.nimp; ++j) c.ensure(c.Sn[j], size_t(cap_tensor) * 8);
+  const size_t a_slot = round_up(size_t(c0) * sh.Mr, tile.m) * size_t(sh.Kpad) * esz;
+  const size_t b_slot = round_up(size_t(c2) * sh.Mr, tile.n) * size_t(sh.Kpad) * esz;
+  const size_t e_slot = round_up(size_t(c0) * sh.Mr, tile.m) * round_up(size_t(c2) * sh.Mr, tile.n) * esE;
 
-  const double *src[3] = {static_cast<const double *>(c.T.ptr), nullptr, nullptr};
-  for (int j = 0; j < c.nimp; ++j) src[1 + j] = static_cast<const double *>(c.S[j].ptr);
-  double *dst[3] = {static_cast<double *>(c.Tn.ptr), nullptr, nullptr};
-  for (int j = 0; j < c.nimp; ++j) dst[1 + j] = static_cast<double *>(c.Sn[j].ptr);
-
-  for (int x2a = 0; x2a < dmu; x2a += c2) {
-    const int n2 = (dmu - x2a) < c2 ? (dmu - x2a) : c2;
-    const int64_t Npad = int64_t(round_up(size_t(n2) * sh.Mr, tile.n));
-    void *Bt[3];
-    for (int t = 0; t < nt; ++t) {
-      Bt[t] = c.wsp<char>("Bt" + std::to_string(t), size_t(round_up(size_t(c2) * sh.Mr, tile.n)) * sh.Kpad * esz);
-      build_operand(c, sh, src[t], false, x2a, n2, Bt[t], Npad, "B");
+  for (size_t first = 0; first < all.size(); first += chunk) {
+    std::vector<trg_ctx *> cs(all.begin() + first, all.begin() + std::min(all.size(), first + chunk));
+    const int nb = int(cs.size());
+    for (auto *x : cs) {
+      x->ensure(x->Tn, size_t(cap_tensor) * 8);
+      for (int j = 0; j < x->nimp; ++j) x->ensure(x->Sn[j], size_t(cap_tensor) * 8);
     }
-    for (int x0a = 0; x0a < dmu; x0a += c0) {
-      const int n0 = (dmu - x0a) < c0 ? (dmu - x0a) : c0;
-      const int64_t Mpad = int64_t(round_up(size_t(n0) * sh.Mr, tile.m));
-      void *A[3];
-      for (int t = 0; t < nt; ++t) {
-        A[t] = c.wsp<char>("A" + std::to_string(t), size_t(round_up(size_t(c0) * sh.Mr, tile.m)) * sh.Kpad * esz);
-        build_operand(c, sh, src[t], true, x0a, n0, A[t], Mpad, "A");
-      }
-      void *E = c.wsp<char>("E", size_t(round_up(size_t(c0) * sh.Mr, tile.m)) *
-                                     round_up(size_t(c2) * sh.Mr, tile.n) * esE);
-      // pure: E = A_T Bt_T
-      join(c, sh.prec, A[0], Bt[0], E, Mpad, Npad, sh.Kpad, false);
-      post_join(c, sh, E, Npad, x0a, n0, x2a, n2, dst[0]);
-      // impure: E = A_S Bt_T + A_T Bt_S
+    // sources and destinations per tensor kind t (pure, impurities) and context
+    std::vector<std::vector<const double *>> src(nt, std::vector<const double *>(nb));
+    std::vector<std::vector<double *>> dst(nt, std::vector<double *>(nb));
+    for (int b = 0; b < nb; ++b) {
+      src[0][b] = static_cast<const double *>(cs[b]->T.ptr);
+      dst[0][b] = static_cast<double *>(cs[b]->Tn.ptr);
       for (int j = 0; j < c.nimp; ++j) {
-        join(c, sh.prec, A[1 + j], Bt[0], E, Mpad, Npad, sh.Kpad, false);
-        join(c, sh.prec, A[0], Bt[1 + j], E, Mpad, Npad, sh.Kpad, true);
-        post_join(c, sh, E, Npad, x0a, n0, x2a, n2, dst[1 + j]);
+        src[1 + j][b] = static_cast<const double *>(cs[b]->S[j].ptr);
+        dst[1 + j][b] = static_cast<double *>(cs[b]->Sn[j].ptr);
       }
     }
-  }
+    for (int x2a = 0; x2a < dmu; x2a += c2) {
+      const int n2 = (dmu - x2a) < c2 ? (dmu - x2a) : c2;
+      const int64_t Npad = int64_t(round_up(size_t(n2) * sh.Mr, tile.n));
+      char *Bt[3];
+      for (int t = 0; t < nt; ++t) {
+        Bt[t] = c.wsp<char>("Bt" + std::to_string(t), b_slot * nb);
+        build_operand(cs, sh, src[t].data(), false, x2a, n2, Bt[t], b_slot, Npad, "B");
+      }
+      for (int x0a = 0; x0a < dmu; x0a += c0) {
+        const int n0 = (dmu - x0a) < c0 ? (dmu - x0a) : c0;
+        const int64_t Mpad = int64_t(round_up(size_t(n0) * sh.Mr, tile.m));
+        char *A[3];
+        for (int t = 0; t < nt; ++t) {
+          A[t] = c.wsp<char>("A" + std::to_string(t), a_slot * nb);
+          build_operand(cs, sh, src[t].data(), true, x0a, n0, A[t], a_slot, Mpad, "A");
+        }
+        char *E = c.wsp<char>("E", e_slot * nb);
+        // pure: E = A_T Bt_T
+        join(c, sh.prec, A[0], a_slot, Bt[0], b_slot, E, e_slot, nb, Mpad, Npad, sh.Kpad, false);
+        post_join(cs, sh, E, e_slot, Npad, x0a, n0, x2a, n2, dst[0].data());
+        // impure: E = A_S Bt_T + A_T Bt_S
+        for (int j = 0; j < c.nimp; ++j) {
+          join(c, sh.prec, A[1 + j], a_slot, Bt[0], b_slot, E, e_slot, nb, Mpad, Npad, sh.Kpad, false);
+          join(c, sh.prec, A[0], a_slot, Bt[1 + j], b_slot, E, e_slot, nb, Mpad, Npad, sh.Kpad, true);
+          post_join(cs, sh, E, e_slot, Npad, x0a, n0, x2a, n2, dst[1 + j].data());
+        }
+      }
+    }
 
-  // ---- 4: normalisation, accumulator, impure scaling
-  const int64_t newtotal = cap_tensor;
-  const int nb = norm_blocks();
-  double *partial = c.wsp<double>("norm_partial", size_t(nb) * 8);
-  norm_and_accumulate(dst[0], newtotal, partial, nb, c.scal(), c.scal() + 3, std::ldexp(1.0, -n_step),
-                      c.errp(), c.st);
-  scale_by_inverse(dst[0], newtotal, c.scal(), 1.0, c.st);
-  for (int j = 0; j < c.nimp; ++j) scale_by_inverse(dst[1 + j], newtotal, c.scal(), 0.5, c.st);
-  TRG_HIP_CHECK(hipMemcpyAsync(rd, c.scal() + 2, 8, hipMemcpyDeviceToDevice, c.st));
+    // ---- 4: normalisation (ln c_n also into each step record), accumulator,
+    // impure scaling
+    const int nblk = norm_blocks();
+    double *partial = c.wsp<double>("norm_partial", size_t(nblk) * nb * 8);
+    NormBatch nbt{};
+    std::vector<const double *> scals(nb);
+    for (int b = 0; b < nb; ++b) {
+      nbt.x[b] = dst[0][b];
+      nbt.scal[b] = cs[b]->scal();
+      nbt.err[b] = cs[b]->errp();
+      nbt.rec[b] = preps[first + b]->rd;
+      nbt.weight[b] = std::ldexp(1.0, -preps[first + b]->n_step);
+      scals[b] = cs[b]->scal();
+    }
+    norm_and_accumulate_batch(nbt, nb, cap_tensor, partial, nblk, c.st);
+    scale_by_inverse_batch(dst[0].data(), scals.data(), nb, cap_tensor, 1.0, c.st);
+    for (int j = 0; j < c.nimp; ++j) scale_by_inverse_batch(dst[1 + j].data(), scals.data(), nb, cap_tensor, 0.5, c.st);
 
-  std::swap(c.T, c.Tn);
-  for (int j = 0; j < c.nimp; ++j) std::swap(c.S[j], c.Sn[j]);
-  trg_step_rec hr{};
-  hr.n = n_step;
-  hr.axis = mu;
-  hr.join_precision = sh.prec;
-  for (int ax = 0; ax < 4; ++ax) {
-    hr.dims[ax] = ax < d ? sh.nd[ax] : 0;
-    hr.side[ax] = -1;
+    for (int b = 0; b < nb; ++b) {
+      trg_ctx &x = *cs[b];
+      const int n_step = preps[first + b]->n_step;
+      std::swap(x.T, x.Tn);
+      for (int j = 0; j < x.nimp; ++j) std::swap(x.S[j], x.Sn[j]);
+      trg_step_rec hr{};
+      hr.n = n_step;
+      hr.axis = mu;
+      hr.join_precision = sh.prec;
+      for (int ax = 0; ax < 4; ++ax) {
+        hr.dims[ax] = ax < d ? sh.nd[ax] : 0;
+        hr.side[ax] = -1;
+      }
+      x.host_rec.push_back(hr);
+      for (int ax = 0; ax < d; ++ax) x.dims[ax] = sh.nd[ax];
+      x.nsteps = n_step;
+    }
   }
-  c.host_rec.push_back(hr);
-  for (int ax = 0; ax < d; ++ax) c.dims[ax] = sh.nd[ax];
-  c.nsteps = n_step;
 }
 
 void hotrg_step_batch_impl(std::vector<trg_ctx *> cs, int mu, int dcut) {
   std::vector<StepPrep> ps;
   for (auto *c : cs) ps.push_back(prepare_step(*c, mu, dcut));
   isometries_batch(cs, ps, mu);
-  for (size_t i = 0; i < cs.size(); ++i) contract_step(*cs[i], ps[i], mu);
+  // contexts with the same impurities share the contraction launches
+  std::vector<bool> done(cs.size(), false);
+  for (size_t i = 0; i < cs.size(); ++i) {
+    if (done[i]) continue;
+    std::vector<trg_ctx *> group;
+    std::vector<StepPrep *> preps;
+    for (size_t j = i; j < cs.size(); ++j) {
+      if (done[j] || cs[j]->nimp != cs[i]->nimp || cs[j]->imp_kind[0] != cs[i]->imp_kind[0]) continue;
+      group.push_back(cs[j]);
+      preps.push_back(&ps[j]);
+      done[j] = true;
+    }
+    contract_batch(group, preps, mu);
+  }
 }
 
 void hotrg_step_impl(trg_ctx &c, int mu, int dcut) { hotrg_step_batch_impl({&c}, mu, dcut); }
@@ -1017,6 +1118,8 @@ int trg_get_isometry(trg_ctx *ctx, int nu, double *host_U, size_t capU, double *
   });
 }
 
+}  // extern "C"
+
 // ------------------------------------------------------------ checkpoint ---
 namespace {
 struct StateHeader {
@@ -1048,6 +1151,8 @@ std::vector<std::pair<void *, size_t>> state_tensors(trg_ctx &c) {
   return v;
 }
 }  // namespace
+
+extern "C" {
 
 int trg_export_state(trg_ctx *ctx, void *host_buf, size_t cap, size_t *size) {
   if (!ctx || !size) return fail(ctx, TRG_EINVAL, "NULL argument");

@@ -154,7 +154,8 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
                const typename Prec<PREC>::in_t *__restrict__ Bt,
                typename Prec<PREC>::out_t *__restrict__ C, uint32_t tiles_m, uint32_t tiles_n,
                uint32_t ktiles, uint64_t lda, uint64_t ldb, uint64_t ldc, uint64_t planeA,
-               uint64_t planeB, uint64_t c_split_stride) {
+               uint64_t planeB, uint64_t c_split_stride, uint64_t batch_a, uint64_t batch_b,
+               uint64_t batch_c) {
   using P = Prec<PREC>;
   using in_t = typename P::in_t;
   using acc_t = typename P::acc_t;
@@ -184,6 +185,10 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
   tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
   const uint64_t m0 = uint64_t(tm) * BM, n0 = uint64_t(tn) * BN;
 
+  // batch: blockIdx.z selects a product of the strided batch (elements)
+  A += uint64_t(blockIdx.z) * batch_a;
+  Bt += uint64_t(blockIdx.z) * batch_b;
+  C += uint64_t(blockIdx.z) * batch_c;
   // split-K: blockIdx.y selects a K range of ktiles tiles and its own C slab
   const uint64_t koff = uint64_t(blockIdx.y) * ktiles * BK;
   C += uint64_t(blockIdx.y) * c_split_stride;
@@ -429,7 +434,8 @@ gemm_nt_kernel(const typename Prec<PREC>::in_t *__restrict__ A,
 template <int PREC, int BM, int BN, int WM, int WN, int STAGES = 2, int RB = 128, int SWZ = 0, int PF = 1>
 void launch_gemm(const void *A, const void *Bt, void *C, uint64_t M, uint64_t N, uint64_t K,
                  uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st,
-                 uint32_t splits = 1, uint64_t c_split_stride = 0) {
+                 uint32_t splits = 1, uint64_t c_split_stride = 0, uint32_t nb = 1, uint64_t batch_a = 0,
+                 uint64_t batch_b = 0, uint64_t batch_c = 0) {
   using P = Prec<PREC>;
   constexpr int BK = RB / P::elem;
   TRG_REQUIRE(M % BM == 0 && N % BN == 0 && K % BK == 0, "gemm: M, N, K must be tile multiples");
@@ -446,14 +452,18 @@ void launch_gemm(const void *A, const void *Bt, void *C, uint64_t M, uint64_t N,
   auto *b = static_cast<const in_t *>(Bt);
   auto *c = static_cast<out_t *>(C);
   const uint64_t plA = M * lda, plB = N * ldb;
+  TRG_REQUIRE(nb >= 1 && nb <= 65535, "gemm: batch size out of range");
+  TRG_REQUIRE(nb == 1 || (batch_a >= M * lda * P::planes && batch_b >= N * ldb * P::planes && batch_c >= M * ldc),
+              "gemm: batch strides overlap the products");
   if (K == 0) {
-    if (!accum) fill_zero(C, sizeof(out_t) * M * ldc, st);
+    if (!accum)
+      for (uint32_t b = 0; b < nb; ++b) fill_zero(c + b * batch_c, sizeof(out_t) * M * ldc, st);
     return;
   }
   // K is split into `splits` equal ranges (the caller pads K to a multiple)
   TRG_REQUIRE(splits >= 1 && K % (uint64_t(splits) * BK) == 0, "gemm: K not divisible by splits");
   const uint32_t kt = uint32_t(K / BK / splits);
-  dim3 grid(uint32_t(tiles), splits), block(64 * WM * WN);
+  dim3 grid(uint32_t(tiles), splits, nb), block(64 * WM * WN);
   // dynamic LDS above 64 KB must be allowed per kernel (once per instantiation)
   static bool attr_set = false;
   if (!attr_set) {
@@ -465,10 +475,12 @@ void launch_gemm(const void *A, const void *Bt, void *C, uint64_t M, uint64_t N,
   }
   if (accum)
     hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, RB, SWZ, PF, true>), grid, block, lds, st, a, b, c,
-                       uint32_t(tiles_m), uint32_t(tiles_n), kt, lda, ldb, ldc, plA, plB, c_split_stride);
+                       uint32_t(tiles_m), uint32_t(tiles_n), kt, lda, ldb, ldc, plA, plB, c_split_stride, batch_a,
+                       batch_b, batch_c);
   else
     hipLaunchKernelGGL((gemm_nt_kernel<PREC, BM, BN, WM, WN, STAGES, RB, SWZ, PF, false>), grid, block, lds, st, a, b, c,
-                       uint32_t(tiles_m), uint32_t(tiles_n), kt, lda, ldb, ldc, plA, plB, c_split_stride);
+                       uint32_t(tiles_m), uint32_t(tiles_n), kt, lda, ldb, ldc, plA, plB, c_split_stride, batch_a,
+                       batch_b, batch_c);
   TRG_HIP_CHECK(hipGetLastError());
 }
 
@@ -501,16 +513,24 @@ GemmTile gemm_tile(int prec) {
 }
 
 void gemm_nt(int prec, const void *A, const void *Bt, void *C, uint64_t M, uint64_t N, uint64_t K,
-             uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st) {
+             uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st, uint32_t nb, uint64_t batch_a,
+             uint64_t batch_b, uint64_t batch_c) {
   switch (prec) {
-    case 0: launch_gemm<0, 128, 128, 2, 2, TRG_F64_STAGES>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
-    case 1: launch_gemm<1, 128, 128, 2, TRG_F32_WN, TRG_F32_STAGES>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st); return;
+    case 0:
+      launch_gemm<0, 128, 128, 2, 2, TRG_F64_STAGES>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st, 1, 0, nb, batch_a,
+                                                     batch_b, batch_c);
+      return;
+    case 1:
+      launch_gemm<1, 128, 128, 2, TRG_F32_WN, TRG_F32_STAGES>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st, 1, 0, nb,
+                                                              batch_a, batch_b, batch_c);
+      return;
     case 2:
-      launch_gemm<2, BF::BM, BF::BN, BF::WM, BF::WN, BF::S, BF::RB, BF::SWZ>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st);
+      launch_gemm<2, BF::BM, BF::BN, BF::WM, BF::WN, BF::S, BF::RB, BF::SWZ>(A, Bt, C, M, N, K, lda, ldb, ldc, accum, st,
+                                                                            1, 0, nb, batch_a, batch_b, batch_c);
       return;
     case 3:
-      launch_gemm<3, BF6::BM, BF6::BN, BF6::WM, BF6::WN, BF6::S, BF6::RB, BF6::SWZ, BF6::PF>(A, Bt, C, M, N, K, lda, ldb,
-                                                                                          ldc, accum, st);
+      launch_gemm<3, BF6::BM, BF6::BN, BF6::WM, BF6::WN, BF6::S, BF6::RB, BF6::SWZ, BF6::PF>(
+          A, Bt, C, M, N, K, lda, ldb, ldc, accum, st, 1, 0, nb, batch_a, batch_b, batch_c);
       return;
   }
   throw Error(-1, "gemm: unknown precision");

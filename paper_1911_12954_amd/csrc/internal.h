@@ -14,12 +14,19 @@ struct GemmTile {
 inline int operand_planes(int prec) { return prec == 2 ? 2 : (prec == 3 ? 3 : 1); }
 inline int operand_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2 * operand_planes(prec)); }
 GemmTile gemm_tile(int prec);
+// nb > 1: a strided batch of nb products in one launch (grid.z), product b
+// reading A + b * batch_a, Bt + b * batch_b and writing C + b * batch_c
+// (element strides)
 void gemm_nt(int prec, const void *A, const void *Bt, void *C, uint64_t M, uint64_t N, uint64_t K,
-             uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st);
+             uint64_t lda, uint64_t ldb, uint64_t ldc, bool accum, hipStream_t st, uint32_t nb = 1,
+             uint64_t batch_a = 0, uint64_t batch_b = 0, uint64_t batch_c = 0);
 // split-K FP64 Gram product: C[s] = A[:, ks] * Bt[:, ks]^T for split s, tile 64
 void gemm_nt_splitk_f64(const double *A, const double *Bt, double *Cpart, uint64_t M, uint64_t N,
                         uint64_t K, uint64_t lda, uint64_t ldb, uint32_t splits, uint64_t kper,
                         hipStream_t st);
+
+// Contexts one batched launch serves (pointer tables are passed by value)
+constexpr int TRG_MAXB = 64;
 
 // ------------------------------------------------------------ tensor map ---
 // out[sum_i o_i so_i] = sum_{s} in[sum_i o_i si_i + sum_j s_j ssi_j] *
@@ -41,11 +48,16 @@ enum InKind { IN_F64 = 0, IN_F32 = 1 };
 void tensor_map(const void *in, int in_kind, const double *U, void *out, int out_kind,
                 int64_t lo_plane, const MapDim *dims, int ndims, const MapSum *sums, int nsum,
                 hipStream_t st);
+// the same map for nb contexts in one launch (grid.y = context): context i
+// reads ins[i] and Us[i] and writes outs[i]; every context has the same shape
+void tensor_map_batch(const void *const *ins, int in_kind, const double *const *Us, void *const *outs, int nb,
+                      int out_kind, int64_t lo_plane, const MapDim *dims, int ndims, const MapSum *sums,
+                      int nsum, hipStream_t st);
 
 // zero the padding of a row-major rows_pad x ld matrix whose valid part is
 // rows x cols (elements of elem_bytes; `planes` planes plane_stride apart)
 void zero_pad(void *buf, int64_t rows, int64_t rows_pad, int64_t cols, int64_t ld, int elem_bytes,
-              int planes, int64_t plane_stride, hipStream_t st);
+              int planes, int64_t plane_stride, hipStream_t st, int nb = 1, int64_t batch_stride = 0);
 void fill_zero(void *buf, size_t bytes, hipStream_t st);
 
 // sum of split-K partials: out[r*ldo + c] = sum_s part[s][r*ldp + c]
@@ -65,6 +77,21 @@ void norm_and_accumulate(const double *x, int64_t n, double *partial, int nblock
 int norm_blocks();
 // x[i] *= factor * scal[1]
 void scale_by_inverse(double *x, int64_t n, const double *scal, double factor, hipStream_t st);
+// both for nb contexts in one launch each: context i normalises xs[i] with
+// its own scalars scals[i] (c, 1/c, ln c, acc at [3]), error flag errs[i],
+// accumulator weight weight[i] (2^-n of its own step n), and writes ln c to
+// recs[i] (may be null); partial holds nb * nblocks
+struct NormBatch {
+  const double *x[TRG_MAXB];
+  double *scal[TRG_MAXB];
+  int *err[TRG_MAXB];
+  double *rec[TRG_MAXB];
+  double weight[TRG_MAXB];
+};
+void norm_and_accumulate_batch(const NormBatch &b, int nb, int64_t n, double *partial, int nblocks,
+                               hipStream_t st);
+void scale_by_inverse_batch(double *const *xs, const double *const *scals, int nb, int64_t n, double factor,
+                            hipStream_t st);
 
 // traces: out[j] = sum_{x_nu} X_j[x, x, y, y, ...] for up to 3 tensors
 // {Tr M, Tr(M M)} into out[0..1] for M[a][a'] = T with the legs of `axis`

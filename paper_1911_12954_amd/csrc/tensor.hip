@@ -59,11 +59,20 @@ __device__ inline void map_store(void *out, int64_t o, int64_t lo_plane, double 
   }
 }
 
+// per-context pointers of a batched map (grid.y = context)
+struct MapPtrs {
+  const void *in[TRG_MAXB];
+  const double *U[TRG_MAXB];
+  void *out[TRG_MAXB];
+};
+
 template <typename InT, int OUT>
 __global__ void __launch_bounds__(256)
-map_kernel(const InT *__restrict__ in, const double *__restrict__ Ug, void *__restrict__ out,
-           MapParams p) {
+map_kernel(MapPtrs ptrs, MapParams p) {
   extern __shared__ double Us[];
+  const InT *__restrict__ in = static_cast<const InT *>(ptrs.in[blockIdx.y]);
+  const double *__restrict__ Ug = ptrs.U[blockIdx.y];
+  void *__restrict__ out = ptrs.out[blockIdx.y];
   const double *U = Ug;
   if (p.u_lds > 0) {
     // every thread of the block reaches this barrier (the bound check follows)
@@ -137,14 +146,14 @@ map_kernel(const InT *__restrict__ in, const double *__restrict__ Ug, void *__re
 }
 
 template <typename InT>
-void launch_map(const InT *in, const double *U, void *out, int out_kind, MapParams &p, hipStream_t st) {
-  const dim3 grid((p.count + 255) / 256), block(256);
+void launch_map(const MapPtrs &ptrs, int nb, int out_kind, MapParams &p, hipStream_t st) {
+  const dim3 grid((p.count + 255) / 256, nb), block(256);
   const size_t lds = p.u_lds > 0 ? size_t(p.u_lds) * 8 : 0;
   switch (out_kind) {
-    case OUT_F64: hipLaunchKernelGGL((map_kernel<InT, OUT_F64>), grid, block, lds, st, in, U, out, p); break;
-    case OUT_F32: hipLaunchKernelGGL((map_kernel<InT, OUT_F32>), grid, block, lds, st, in, U, out, p); break;
-    case OUT_BF16X2: hipLaunchKernelGGL((map_kernel<InT, OUT_BF16X2>), grid, block, lds, st, in, U, out, p); break;
-    case OUT_BF16X3: hipLaunchKernelGGL((map_kernel<InT, OUT_BF16X3>), grid, block, lds, st, in, U, out, p); break;
+    case OUT_F64: hipLaunchKernelGGL((map_kernel<InT, OUT_F64>), grid, block, lds, st, ptrs, p); break;
+    case OUT_F32: hipLaunchKernelGGL((map_kernel<InT, OUT_F32>), grid, block, lds, st, ptrs, p); break;
+    case OUT_BF16X2: hipLaunchKernelGGL((map_kernel<InT, OUT_BF16X2>), grid, block, lds, st, ptrs, p); break;
+    case OUT_BF16X3: hipLaunchKernelGGL((map_kernel<InT, OUT_BF16X3>), grid, block, lds, st, ptrs, p); break;
     default: throw Error(-1, "tensor_map: bad output kind");
   }
   TRG_HIP_CHECK(hipGetLastError());
@@ -155,8 +164,10 @@ void launch_map(const InT *in, const double *U, void *out, int out_kind, MapPara
 // clears one whole element.
 template <typename Elem>
 __global__ void zero_pad_kernel(Elem *buf, int64_t rows, int64_t rows_pad, int64_t cols, int64_t ld, int planes,
-                                int64_t plane_stride) {
-  // grid-stride over (plane, row) pairs; each row clears [cols, ld) or all of it
+                                int64_t plane_stride, int64_t batch_stride) {
+  // grid.y = context (batch_stride elements apart); grid-stride over
+  // (plane, row) pairs; each row clears [cols, ld) or all of it
+  buf += int64_t(blockIdx.y) * batch_stride;
   const int64_t total = int64_t(planes) * rows_pad;
   for (int64_t rr = blockIdx.x; rr < total; rr += gridDim.x) {
     const int64_t plane = rr / rows_pad, row = rr % rows_pad;
@@ -211,8 +222,11 @@ __device__ inline double block_sum(double v, double *sh) {
   return sh[0];
 }
 
-__global__ void __launch_bounds__(256) sumsq_kernel(const double *x, int64_t n, double *partial) {
+__global__ void __launch_bounds__(256) sumsq_kernel(NormBatch nbt, int64_t n, double *partial) {
   __shared__ double sh[256];
+  // grid.y = context; its partial sums follow those of the contexts before it
+  const double *x = nbt.x[blockIdx.y];
+  partial += size_t(blockIdx.y) * gridDim.x;
   const int64_t per = (n + gridDim.x - 1) / gridDim.x;
   const int64_t b = int64_t(blockIdx.x) * per;
   const int64_t e = b + per < n ? b + per : n;
@@ -223,8 +237,15 @@ __global__ void __launch_bounds__(256) sumsq_kernel(const double *x, int64_t n, 
 }
 
 __global__ void __launch_bounds__(256)
-norm_final_kernel(const double *partial, int nb, double *scal, double *acc, double weight, int *err) {
+norm_final_kernel(NormBatch nbt, const double *partial, int nb) {
   __shared__ double sh[256];
+  // one workgroup per context, each with its own accumulator weight
+  partial += size_t(blockIdx.x) * nb;
+  const double weight = nbt.weight[blockIdx.x];
+  double *scal = nbt.scal[blockIdx.x];
+  double *acc = scal + 3;
+  int *err = nbt.err[blockIdx.x];
+  double *rec = nbt.rec[blockIdx.x];
   double s = 0.0;
   for (int i = threadIdx.x; i < nb; i += 256) s += partial[i];
   const double tot = block_sum(s, sh);
@@ -234,13 +255,21 @@ norm_final_kernel(const double *partial, int nb, double *scal, double *acc, doub
     scal[0] = c;
     scal[1] = ok ? 1.0 / c : 0.0;
     scal[2] = ok ? log(c) : 0.0;
+    if (rec) rec[0] = scal[2];
     if (ok) acc[0] += weight * log(c);
     else *err |= 1;
   }
 }
 
-__global__ void scale_kernel(double *x, int64_t n, const double *scal, double factor) {
-  const double f = factor * scal[1];
+struct ScalePtrs {
+  double *x[TRG_MAXB];
+  const double *scal[TRG_MAXB];
+};
+
+__global__ void scale_kernel(ScalePtrs sp, int64_t n, double factor) {
+  // grid.y = context
+  double *x = sp.x[blockIdx.y];
+  const double f = factor * sp.scal[blockIdx.y][1];
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     x[i] *= f;
 }
@@ -304,7 +333,17 @@ __global__ void ising_kernel(double *T, double *SE, double *SM, int d, double be
 void tensor_map(const void *in, int in_kind, const double *U, void *out, int out_kind,
                 int64_t lo_plane, const MapDim *dims, int ndims, const MapSum *sums, int nsum,
                 hipStream_t st) {
+  tensor_map_batch(&in, in_kind, &U, &out, 1, out_kind, lo_plane, dims, ndims, sums, nsum, st);
+}
+
+void tensor_map_batch(const void *const *ins, int in_kind, const double *const *Us, void *const *outs, int nb,
+                      int out_kind, int64_t lo_plane, const MapDim *dims, int ndims, const MapSum *sums,
+                      int nsum, hipStream_t st) {
+  TRG_REQUIRE(nb >= 1 && nb <= TRG_MAXB, "tensor_map: batch size out of range");
   TRG_REQUIRE(ndims >= 1 && ndims <= MAP_MAXD && nsum >= 0 && nsum <= 2, "tensor_map: bad rank");
+  const double *U = Us[0];
+  for (int b = 0; b < nb; ++b)
+    TRG_REQUIRE((Us[b] != nullptr) == (U != nullptr), "tensor_map: every context needs a matrix or none");
   TRG_REQUIRE(nsum == 0 || U != nullptr, "tensor_map: summation needs a matrix");
   for (int i = 0; i < ndims; ++i)
     TRG_REQUIRE(dims[i].size >= 1 && dims[i].size < (int64_t(1) << 31), "tensor_map: bad dim");
@@ -383,33 +422,37 @@ void tensor_map(const void *in, int in_kind, const double *U, void *out, int out
       oi += r * dims[i].si;
       ou += r * dims[i].su;
     }
-    const void *pin = static_cast<const char *>(in) + oi * esz_in;
-    const double *pu = U ? U + ou : nullptr;
-    void *pout = static_cast<char *>(out) + oo * esz_out;
+    MapPtrs ptrs{};
+    for (int b = 0; b < nb; ++b) {
+      ptrs.in[b] = static_cast<const char *>(ins[b]) + oi * esz_in;
+      ptrs.U[b] = Us[b] ? Us[b] + ou : nullptr;
+      ptrs.out[b] = static_cast<char *>(outs[b]) + oo * esz_out;
+    }
     if (in_kind == IN_F64)
-      launch_map(static_cast<const double *>(pin), pu, pout, out_kind, p, st);
+      launch_map<double>(ptrs, nb, out_kind, p, st);
     else
-      launch_map(static_cast<const float *>(pin), pu, pout, out_kind, p, st);
+      launch_map<float>(ptrs, nb, out_kind, p, st);
   }
 }
 
 void zero_pad(void *buf, int64_t rows, int64_t rows_pad, int64_t cols, int64_t ld, int elem_bytes,
-              int planes, int64_t plane_stride, hipStream_t st) {
+              int planes, int64_t plane_stride, hipStream_t st, int nb, int64_t batch_stride) {
   if (cols == ld && rows == rows_pad) return;
+  TRG_REQUIRE(nb >= 1 && nb <= 65535, "zero_pad: batch size out of range");
   const int64_t work = int64_t(planes) * rows_pad;
-  const uint32_t grid = uint32_t(work < 65536 ? work : 65536);
+  const dim3 grid(uint32_t(work < 65536 ? work : 65536), uint32_t(nb));
   switch (elem_bytes) {
     case 2:
-      hipLaunchKernelGGL(zero_pad_kernel<uint16_t>, dim3(grid), dim3(256), 0, st, static_cast<uint16_t *>(buf), rows,
-                         rows_pad, cols, ld, planes, plane_stride);
+      hipLaunchKernelGGL(zero_pad_kernel<uint16_t>, grid, dim3(256), 0, st, static_cast<uint16_t *>(buf), rows,
+                         rows_pad, cols, ld, planes, plane_stride, batch_stride);
       break;
     case 4:
-      hipLaunchKernelGGL(zero_pad_kernel<uint32_t>, dim3(grid), dim3(256), 0, st, static_cast<uint32_t *>(buf), rows,
-                         rows_pad, cols, ld, planes, plane_stride);
+      hipLaunchKernelGGL(zero_pad_kernel<uint32_t>, grid, dim3(256), 0, st, static_cast<uint32_t *>(buf), rows,
+                         rows_pad, cols, ld, planes, plane_stride, batch_stride);
       break;
     case 8:
-      hipLaunchKernelGGL(zero_pad_kernel<uint64_t>, dim3(grid), dim3(256), 0, st, static_cast<uint64_t *>(buf), rows,
-                         rows_pad, cols, ld, planes, plane_stride);
+      hipLaunchKernelGGL(zero_pad_kernel<uint64_t>, grid, dim3(256), 0, st, static_cast<uint64_t *>(buf), rows,
+                         rows_pad, cols, ld, planes, plane_stride, batch_stride);
       break;
     default:
       throw Error(-1, "zero_pad: element size must be 2, 4 or 8 bytes");
@@ -445,16 +488,40 @@ int norm_blocks() { return NORM_BLOCKS; }
 
 void norm_and_accumulate(const double *x, int64_t n, double *partial, int nblocks, double *scal,
                          double *acc, double weight, int *err, hipStream_t st) {
-  hipLaunchKernelGGL(sumsq_kernel, dim3(nblocks), dim3(256), 0, st, x, n, partial);
+  TRG_REQUIRE(acc == scal + 3, "norm: the accumulator is scal[3]");
+  NormBatch b{};
+  b.x[0] = x;
+  b.scal[0] = scal;
+  b.err[0] = err;
+  b.rec[0] = nullptr;
+  b.weight[0] = weight;
+  norm_and_accumulate_batch(b, 1, n, partial, nblocks, st);
+}
+
+void norm_and_accumulate_batch(const NormBatch &b, int nb, int64_t n, double *partial, int nblocks,
+                               hipStream_t st) {
+  TRG_REQUIRE(nb >= 1 && nb <= TRG_MAXB, "norm: batch size out of range");
+  hipLaunchKernelGGL(sumsq_kernel, dim3(nblocks, nb), dim3(256), 0, st, b, n, partial);
   TRG_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(256), 0, st, partial, nblocks, scal, acc, weight, err);
+  hipLaunchKernelGGL(norm_final_kernel, dim3(nb), dim3(256), 0, st, b, partial, nblocks);
   TRG_HIP_CHECK(hipGetLastError());
 }
 
 void scale_by_inverse(double *x, int64_t n, const double *scal, double factor, hipStream_t st) {
+  scale_by_inverse_batch(&x, &scal, 1, n, factor, st);
+}
+
+void scale_by_inverse_batch(double *const *xs, const double *const *scals, int nb, int64_t n, double factor,
+                            hipStream_t st) {
+  TRG_REQUIRE(nb >= 1 && nb <= TRG_MAXB, "scale: batch size out of range");
+  ScalePtrs sp{};
+  for (int b = 0; b < nb; ++b) {
+    sp.x[b] = xs[b];
+    sp.scal[b] = scals[b];
+  }
   const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(scale_kernel, dim3(uint32_t(blocks < 16384 ? blocks : 16384)), dim3(256), 0, st, x, n,
-                     scal, factor);
+  hipLaunchKernelGGL(scale_kernel, dim3(uint32_t(blocks < 16384 ? blocks : 16384), nb), dim3(256), 0, st, sp, n,
+                     factor);
   TRG_HIP_CHECK(hipGetLastError());
 }
 

@@ -5,10 +5,12 @@ Requests (beta, h, Dcut, L, method) arrive over time.  The server
 
 * admits a request while the device memory of the admitted runs stays
   within the HBM budget: each run's resident tensors (trg_resident_bytes)
-  plus one join workspace per lane (trg_workspace_bytes), which the runs of
-  a lane share (trg_share_workspace) because a lane steps them one after
-  another on its stream; waiting requests are admitted as soon as finished
-  runs free their memory;
+  plus its join workspace (trg_workspace_bytes).  The runs of a lane share
+  one workspace pool (trg_share_workspace); a HOTRG lane steps its
+  same-shape runs in one batched call, which holds one workspace slot per
+  run (each run brings its share), while an ATRG lane steps its runs one
+  call after another through a single share; waiting requests are admitted
+  as soon as finished runs free their memory;
 * bounds the work of one lane round: a lane holds at most
   round_flops / (join flop of one step) runs (at least one), so a round of
   a large bond dimension stays short and the runs admitted first finish
@@ -19,8 +21,9 @@ Requests (beta, h, Dcut, L, method) arrive over time.  The server
 * runs one lane (HIP stream) per (method, bond dimension), so lanes overlap
   on the device; inside a HOTRG lane, runs whose leg dims and next axis
   agree are stepped together by one batched library call
-  (trg_hotrg_step_batch), otherwise one call per run; ATRG runs take one
-  call each (trg_atrg_step);
+  (trg_hotrg_step_batch: one launch per kernel of the contraction and the
+  normalisation for all of them, one eigensolver launch); ATRG runs take
+  one call each (trg_atrg_step);
 * advances a lane as soon as its previous step has completed (event query,
   no global barrier), and records arrival, admission and completion times.
 
@@ -162,7 +165,7 @@ class Server:
         lane = self.lanes.get((method, req["dcut"]))
         if lane is not None and len(lane.runs) >= self.lane_cap(req["dcut"], method):
             return "lane"
-        need = res + (0 if lane is not None and lane.runs else ws)
+        need = res + self._share(method, ws, lane)
         if self.used + need > self.budget:
             return False
         lane = self._lane(method, req["dcut"])
@@ -173,6 +176,21 @@ class Server:
         self.used += need
         self.peak_used = max(self.peak_used, self.used)
         return True
+
+    @staticmethod
+    def _share(method, ws, lane):
+        """Workspace bytes a new run adds to its lane: a HOTRG run its own
+        slot of the batched step, an ATRG run nothing once its lane has one."""
+        if method == "atrg" and lane is not None and lane.runs:
+            return 0
+        return ws
+
+    def _release(self, lane, req):
+        """Bytes a finished run of `lane` frees (its share and residents)."""
+        freed = self.be.resident(req)
+        if lane.method != "atrg":
+            freed += self.be.workspace(lane.dcut, method=lane.method)
+        return freed
 
     def _advance(self, lane, now, t0):
         """Finish completed runs of a lane whose last step is done, then issue
@@ -186,7 +204,7 @@ class Server:
             if run.done >= run.total:
                 lnz = self.be.result(run.handle)
                 self.be.close(run.handle)
-                self.used -= self.be.resident(run.req)
+                self.used -= self._release(lane, run.req)
                 t_done = time.perf_counter() - t0
                 self.results.append({"id": run.req["id"], "lnz": lnz, "arrival": run.req["arrival"],
                                      "admitted": run.t_admit, "done": t_done,
@@ -195,7 +213,7 @@ class Server:
                                      "L": run.req["L"], "beta": run.req["beta"], "h": run.req["h"]})
             else:
                 still.append(run)
-        if had_runs and not still:
+        if had_runs and not still and lane.method == "atrg":
             self.used -= self.be.workspace(lane.dcut, method=lane.method)   # the last user freed it
         lane.runs = still
         if not still:
@@ -275,7 +293,7 @@ class Server:
         for lane in self.lanes.values():
             for run in lane.runs:
                 self.be.close(run.handle)
-                self.used -= self.be.resident(run.req)
-            if lane.runs:
+                self.used -= self._release(lane, run.req)
+            if lane.runs and lane.method == "atrg":
                 self.used -= self.be.workspace(lane.dcut, method=lane.method)
             lane.runs = []

@@ -169,7 +169,7 @@ def test_field_reversal_symmetry():
 
 
 @pytest.mark.parametrize("precision,n64,tol_f,tol_E,tol_M", [("fp32", 0, 1e-6, 1e-6, 1e-3),
-                                                           ("bf16x6", 0, 1e-6, 1e-6, 1e-3),
+                                                           ("bf16x6", 0, 1e-6, 1e-6, 1e-5),
                                                            ("bf16x3", 0, 2e-5, 1e-3, 1e-1),
                                                            ("bf16x3", 8, 1e-6, 1e-3, 1e-1)])
 def test_mixed_precision_error_dcut8(precision, n64, tol_f, tol_E, tol_M):
@@ -194,20 +194,22 @@ def test_mixed_precision_error_dcut8(precision, n64, tol_f, tol_E, tol_M):
     assert eE < tol_E and eM < tol_M
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x6", "bf16x3"])
-def test_mixed_precision_dcut4_degenerate_case(precision):
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16x6", 1e-4), ("bf16x3", 1e-4)])
+def test_mixed_precision_dcut4_degenerate_case(precision, tol):
     """Config of the smoke case (Dcut = 4, L = 16): its truncation at step 3
-    goes through a degenerate pair, and gaps near the degeneracy window let
-    rounding of the join change which vectors survive; the mixed result then
-    differs from FP64 at the truncation level, not at the rounding level.
-    Only a loose bound is asserted; the error is printed."""
+    goes through an exactly degenerate pair, which the FP64 path (window
+    1e-10) and the mixed paths (window 1e-6 after a mixed join) both keep in
+    its canonical basis.  At Dcut 4 this run is very sensitive to rounding
+    (2^-24 noise on every contracted tensor moves f by 3e-5 in the oracle),
+    so every mixed path is held to 1e-4 (measured: FP32 4.2e-5, BF16x3
+    3.7e-5, BF16x6 5.6e-8, the last one a fortunate rounding pattern)."""
     need_gpu()
     announce("mixed dcut4", precision)
     ref = _gpu_run(0.1497, 1e-5, 4, 4, 16)
     got = _gpu_run(0.1497, 1e-5, 4, 4, 16, precision=precision)
     ef = abs(got["f"] - ref["f"]) / abs(ref["f"])
     print(f"[mixed {precision} dcut4] rel err f {ef:.3e}", flush=True)
-    assert ef < 1e-3
+    assert ef < tol
 
 
 def test_fp64_steps_schedule():

@@ -104,3 +104,83 @@ def test_atrg_and_hotrg_requests_in_one_stream():
         assert alone.results[0]["lnz"] == mix[req["id"]], req
     r = atrg.run(0.1497, 1e-3, 4, 4, 4)
     assert abs(mix[1] - r.ln_z_per_site) <= 1e-10 * abs(r.ln_z_per_site)
+
+
+def _run_alone(beta, h, d, dcut, steps, impure, precision, **cfg):
+    from paper_1911_12954_amd import trg_init_ising
+    c = trg_init_ising(beta, h, d, dcut=dcut, impure=impure, precision=precision, **cfg)
+    for n in range(steps):
+        c.hotrg_step(n % d, dcut)
+    out = (c.free_energy(), c.tensor(), [c.tensor(1 + k) for k in range(len(impure))])
+    c.close()
+    return out
+
+
+@pytest.mark.parametrize("precision,budget", [("fp64", 0), ("bf16x6", 0), ("fp64", 120_000_000)])
+def test_batched_step_equals_separate_steps(precision, budget):
+    """trg_hotrg_step_batch over contexts with and without impurities (the
+    contraction and normalisation launched once per group of equal
+    impurities; with a small workspace share the joins are sliced): every
+    tensor and ln Z/V bit-identical to the same runs stepped alone."""
+    need_gpu()
+    import numpy as np
+    from paper_1911_12954_amd import trg_init_ising, trg_hotrg_step_batch
+    announce("batched step", precision, budget)
+    runs = [(0.1490, 0.0, ("E", "M")), (0.1497, 1e-5, ()), (0.1505, 1e-6, ("E", "M")), (0.1500, 0.0, ()),
+            (0.1495, 1e-5, ("E", "M"))]
+    d, dcut, steps = 4, 5, 9
+    ctxs = [trg_init_ising(b, h, d, dcut=dcut, impure=imp, precision=precision, workspace_bytes=budget)
+            for b, h, imp in runs]
+    for n in range(steps):
+        trg_hotrg_step_batch(ctxs, n % d, dcut)
+    for (b, h, imp), c in zip(runs, ctxs):
+        f, T, S = _run_alone(b, h, d, dcut, steps, imp, precision, workspace_bytes=budget)
+        assert c.free_energy() == f
+        assert np.array_equal(c.tensor(), T)
+        for k in range(len(imp)):
+            assert np.array_equal(c.tensor(1 + k), S[k])
+        c.close()
+
+
+def test_batch_beyond_one_launch():
+    """66 contexts: the contraction runs as a launch of 64 and one of 2, with
+    the bits of separate steps."""
+    need_gpu()
+    import numpy as np
+    from paper_1911_12954_amd import trg_init_ising, trg_hotrg_step_batch
+    announce("batch of 66")
+    betas = [0.40 + 0.001 * i for i in range(66)]
+    ctxs = [trg_init_ising(b, 0.01, 2, dcut=6, precision="fp64") for b in betas]
+    for n in range(6):
+        trg_hotrg_step_batch(ctxs, n % 2, 6)
+    for b, c in zip(betas, ctxs):
+        f, T, _ = _run_alone(b, 0.01, 2, 6, 6, (), "fp64")
+        assert c.free_energy() == f and np.array_equal(c.tensor(), T)
+        c.close()
+
+
+def test_batch_of_contexts_at_different_steps():
+    """Runs that reach the same leg dims and axis at different step numbers
+    (a later arrival four steps behind) share a batched call; each keeps its
+    own step count in the free-energy weights and records, with the bits of
+    the runs alone."""
+    need_gpu()
+    import numpy as np
+    from paper_1911_12954_amd import trg_init_ising, trg_hotrg_step_batch
+    announce("batch at different steps")
+    a = trg_init_ising(0.1497, 1e-5, 4, dcut=4, impure=("E", "M"), precision="fp64")
+    b = trg_init_ising(0.1495, 0.0, 4, dcut=4, impure=("E", "M"), precision="fp64")
+    for n in range(6):
+        a.hotrg_step(n % 4, 4)
+    for n in range(2):
+        b.hotrg_step(n % 4, 4)
+    assert a.dims()[0] == b.dims()[0] == (4, 4, 4, 4)
+    for n in range(8):
+        trg_hotrg_step_batch([a, b], (n + 2) % 4, 4)
+    assert [r.n for r in a.step_log()] == list(range(1, 15))
+    assert [r.n for r in b.step_log()] == list(range(1, 11))
+    for ctx, (beta, h, steps) in ((a, (0.1497, 1e-5, 14)), (b, (0.1495, 0.0, 10))):
+        f, T, S = _run_alone(beta, h, 4, 4, steps, ("E", "M"), "fp64")
+        assert ctx.free_energy() == f
+        assert np.array_equal(ctx.tensor(), T) and np.array_equal(ctx.tensor(1), S[0])
+        ctx.close()

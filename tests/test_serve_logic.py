@@ -87,7 +87,7 @@ def test_every_request_completes_and_budget_is_respected():
     assert out["completed"] == 40 and out["censored_active"] == 0
     assert srv.peak_used <= budget
     assert be.live == 0 and not be.workspaces and srv.used == 0
-    # at most one workspace per lane (Dcut) at any time
+    # at most one workspace pool per lane (Dcut) at any time
     assert be.max_workspaces <= 3
     for r in srv.results:
         assert r["latency"] >= 0 and r["admitted"] >= r["arrival"] and r["done"] >= r["admitted"]
@@ -119,9 +119,9 @@ def test_continuous_admission_while_others_run():
 
 
 def test_memory_bound_admission_waits_for_frees():
-    reqs = [{"id": i, "arrival": 0.0, "beta": 0.149, "h": 0.0, "dcut": 8, "L": 4, "method": "hotrg"} for i in range(3)]
+    reqs = [{"id": i, "arrival": 0.0, "beta": 0.149, "h": 0.0, "dcut": 6, "L": 4, "method": "hotrg"} for i in range(3)]
     be = FakeBackend(lag=1)
-    srv = Server(be, 10 * 8 ** 8 + 8 ** 9)   # room for one run at a time
+    srv = Server(be, 10 * 6 ** 8 + 6 ** 9)   # room for one run at a time
     srv.serve(reqs, idle_sleep=0)
     assert be.max_live == 1 and len(srv.results) == 3
     done = sorted(srv.results, key=lambda r: r["id"])
@@ -145,14 +145,28 @@ def test_window_censors_unfinished_runs():
     assert be.live == 0
 
 
-def test_runs_of_a_lane_share_one_workspace():
+def test_runs_of_a_lane_share_one_workspace_pool():
+    """A HOTRG lane's runs share one pool that holds a slot per run of the
+    batched step: four runs need four residents and four workspace shares;
+    with room for two shares, two run at a time.  ATRG runs, stepped one call
+    after another, share a single share."""
     reqs = [{"id": i, "arrival": 0.0, "beta": 0.149, "h": 0.0, "dcut": 6, "L": 16, "method": "hotrg"} for i in range(4)]
     be = FakeBackend(lag=1)
-    budget = 4 * 10 * 6 ** 8 + 6 ** 9      # four residents, one workspace
+    budget = 4 * (10 * 6 ** 8 + 6 ** 9)
     srv = Server(be, budget)
     srv.serve(reqs, idle_sleep=0)
     assert be.max_live == 4 and be.max_workspaces == 1
     assert srv.peak_used == budget and srv.used == 0
+    assert all(n == 4 for n, _, _, _ in be.calls)
+    be = FakeBackend(lag=1)
+    srv = Server(be, 2 * (10 * 6 ** 8 + 6 ** 9))
+    srv.serve(reqs, idle_sleep=0)
+    assert be.max_live == 2 and len(srv.results) == 4 and srv.used == 0
+    at = [dict(r, method="atrg") for r in reqs]
+    be = FakeBackend(lag=1)
+    srv = Server(be, 4 * 10 * 6 ** 8 + 6 ** 9)   # four residents, one share
+    srv.serve(at, idle_sleep=0)
+    assert be.max_live == 4 and be.max_workspaces == 1 and srv.used == 0
 
 
 def test_lane_cap_bounds_a_round_and_keeps_arrival_order():
