@@ -453,6 +453,14 @@ def _qr_sectors(Y, rpar, csec):
     return Q
 
 
+def trial_sectors(r: int, room) -> np.ndarray:
+    """Sector of each of the r trial columns: alternating (c mod 2) for the
+    first 2 min(room) columns, then the sector with more room."""
+    h = min(room)
+    big = 0 if room[0] >= room[1] else 1
+    return np.array([c % 2 if c < 2 * h else big for c in range(r)], dtype=np.int64)
+
+
 def _merge(parts, keep):
     """parts: per sector (values descending, payload); returns the `keep`
     largest values across sectors (even sector first on equal values) as
@@ -505,10 +513,13 @@ def canonical_z2(G: np.ndarray, H: np.ndarray, dcut: int, legs, bond):
 def rsvd_swap_z2(F: Factors, legs, bond, mu: int, dcut: int, p: int, q: int, step: int, seed: int):
     """rsvd_swap with the swap matrix's two parity sectors kept apart: the
     trial matrix keeps only the entries whose row parity (f_perp, k_B) equals
-    the sector of its column (column c in sector c mod 2), the QR
-    factorisations and the final SVD are done per sector, and the largest
-    dcut singular values of both sectors are kept.  Returns X, sigma, Y and
-    the parities of the new bond."""
+    the sector of its column, the QR factorisations and the final SVD are
+    done per sector, and the largest dcut singular values of both sectors are
+    kept.  Column c is in sector c mod 2 while both sectors have room for
+    another column (a sector holds at most as many columns as the swap
+    matrix has rows and columns of its parity); the remaining columns go to
+    the larger sector.  Returns X, sigma, Y and the parities of the new
+    bond."""
     d = F.d
     Ut, Vt = _swap_operands(F, mu)
     k = F.s.shape[0]
@@ -517,8 +528,9 @@ def rsvd_swap_z2(F: Factors, legs, bond, mu: int, dcut: int, p: int, q: int, ste
     n = k * nperp
     rpar = composite_parity([bond] + [legs[a] for a in perp])
     cpar = composite_parity([legs[a] for a in perp] + [bond])
-    r = min(dcut + p, n)
-    csec = np.arange(r) % 2
+    room = [min(int(np.sum(rpar == s)), int(np.sum(cpar == s))) for s in (0, 1)]
+    r = min(dcut + p, room[0] + room[1])
+    csec = trial_sectors(r, room)
     Om = trial_matrix(n, r, step, seed) * (cpar[:, None] == csec[None, :])
     Q = _qr_sectors(_apply(Ut, Vt, Om, False), rpar, csec)
     for _ in range(q):

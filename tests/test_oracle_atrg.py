@@ -261,3 +261,45 @@ def test_z2_mode_disordered_phase_gives_x_one():
     """4D, beta = 0.12 (disordered), h = 0: X -> 1 in the Z2 mode too."""
     z = atrg.run(0.12, 0.0, 4, 4, 1024, z2=True)
     assert abs(atrg.indicator_x(z.G, z.H, 0) - 1.0) < 1e-6
+
+
+def test_trial_sectors_alternate_then_fill_the_larger_sector():
+    assert list(atrg.trial_sectors(6, (8, 8))) == [0, 1, 0, 1, 0, 1]
+    s = atrg.trial_sectors(13, (3, 10))
+    assert list(s[:6]) == [0, 1, 0, 1, 0, 1] and set(s[6:]) == {1}
+    assert int(np.sum(s == 0)) == 3 and int(np.sum(s == 1)) == 10
+
+
+def _symmetric_factors(dims, legs, bond, seed):
+    """Random pieces G[b..., l], H[l, f...] that vanish unless the parity of
+    the legs equals that of the bond index."""
+    rng = np.random.default_rng(seed)
+    rp = atrg.composite_parity(legs)
+    bond = np.asarray(bond)
+    n = int(np.prod(dims))
+    G = rng.standard_normal((n, len(bond))) * (rp[:, None] == bond[None, :])
+    H = rng.standard_normal((len(bond), n)) * (bond[:, None] == rp[None, :])
+    return G.reshape(tuple(dims) + (len(bond),)), H.reshape((len(bond),) + tuple(dims))
+
+
+@pytest.mark.parametrize("mu", [0, 1, 2])
+def test_z2_swap_with_unbalanced_sectors_equals_dense_svd(mu):
+    """Unbalanced leg parities: one parity sector of the swap matrix has
+    fewer rows than half the trial columns.  With every column kept (rank
+    = matrix order) the sector-by-sector randomized swap reproduces the
+    dense SVD of the swap matrix: its singular values, and X sigma Y = M."""
+    legs = [np.array([0, 0, 1]), np.array([0, 0]), np.array([0, 0, 0, 1])]
+    bond = np.array([0, 0, 0, 1])
+    G, H = _symmetric_factors([3, 2, 4], legs, bond, seed=5 + mu)
+    F, kpar = atrg.canonical_z2(G, H, 8, legs, bond)
+    perp = [a for a in range(3) if a != mu]
+    rpar = atrg.composite_parity([kpar] + [legs[a] for a in perp])
+    n = len(rpar)
+    assert min(np.sum(rpar == 0), np.sum(rpar == 1)) < n // 2    # alternation alone would overfill
+    M = atrg.swap_matrix(F, mu)
+    X, sig, Y, par = atrg.rsvd_swap_z2(F, legs, kpar, mu, n, 0, 2, 1, 7)
+    ref = np.linalg.svd(M, compute_uv=False)
+    assert np.max(np.abs(np.sort(sig)[::-1] - ref[:len(sig)])) < 1e-12 * ref[0]
+    assert np.max(np.abs((X * sig) @ Y - M)) < 1e-12 * ref[0]
+    # each kept vector lies in the sector its parity names
+    assert np.all(np.abs(X[rpar[:, None] != par[None, :]]) == 0.0)
