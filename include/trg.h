@@ -88,6 +88,12 @@ typedef struct trg_config {
                              whatever `precision` is (0 = none).  Step n
                              enters ln Z/V with weight 2^-n, so the leading
                              steps dominate the rounding error of f. */
+  int z2;                 /* ATRG from trg_init_ising at h = 0 only: 1 keeps
+                             the pure tensor exactly Z2 symmetric (the
+                             symmetry of the h = 0 Ising tensor) by doing the
+                             swap's randomized SVD, the canonical form and the
+                             HOSVD parity sector by parity sector; 0 (default)
+                             = plain decompositions. */
 } trg_config;
 
 typedef struct trg_ctx trg_ctx;
@@ -170,7 +176,14 @@ int trg_hotrg_step_batch(trg_ctx *const *ctxs, int n, int axis, int dcut);
  * kind 0 = E, 1 = M; term 0 = impurity on the lower site, 1 = upper), and
  * the pure step's HOSVD isometries and c_n are applied; the paper uses the
  * impure-tensor method within ATRG (Sec. 3.2) without giving it.
- * Asynchronous.  Errors: TRG_EINVAL, TRG_ESTATE, TRG_ENOMEM, TRG_EHIP. */
+ * With cfg->z2 (see trg_atrg_parities) the trial matrix of the pure swap
+ * keeps only the entries whose row parity equals the sector of its column
+ * (column c in sector c mod 2 while both sectors have room for it, the rest
+ * in the larger sector), and every factorisation of the step stays inside
+ * one sector, so the zeros of the symmetric tensor stay exact zeros; the
+ * impurity SVDs stay plain.
+ * Asynchronous, except that a Z2 step waits for the device three times to
+ * read back the parities of its new bonds and legs.  Errors: TRG_EINVAL, TRG_ESTATE, TRG_ENOMEM, TRG_EHIP. */
 int trg_atrg_step(trg_ctx *ctx, int axis, int dcut);
 
 /* Create an ATRG context from host pieces T[b, f] = sum_l G[b, l] H[l, f]:
@@ -182,6 +195,29 @@ int trg_init_factors(trg_ctx **out, int d, const int *dims, int r, const double 
 
 /* Singular values (descending, *n of them) of the latest ATRG swap. */
 int trg_atrg_spectrum(trg_ctx *ctx, double *out, int cap, int *n);
+
+/* Z2 sectors of an ATRG context created with cfg->z2 = 1.  The h = 0 Ising
+ * tensor is invariant under the flip of every spin, the symmetry whose
+ * spontaneous breaking X indicates (Sec. 3.1): in the
+ * basis where each leg index and each bond index has a definite parity
+ * (0 even, 1 odd), G[b, l] and H[l, f] vanish unless the parities of the
+ * legs b (f) add up to that of l.  legs_out receives the parity of every leg
+ * index, axis after axis (dims[0] + ... + dims[d-1] entries, the forward and
+ * backward leg of an axis share them); bond_out the parity of each of the r
+ * bond indices; *r_out (if not NULL) the bond r.  Either array pointer may
+ * be NULL.  Host memory, caller owns it.
+ * Synchronises.  Errors: TRG_EINVAL (capacity too small), TRG_ESTATE (not a
+ * Z2 context). */
+int trg_atrg_parities(trg_ctx *ctx, int *legs_out, size_t cap_legs, int *bond_out, size_t cap_bond, int *r_out);
+
+/* The current pieces of an ATRG context, T[b, f] = sum_l G[b, l] H[l, f]
+ * (Sec. 2, Fig. 2): host_G receives G row-major (prod dims) x r with the d
+ * backward legs in axis order, host_H receives H row-major r x (prod dims)
+ * with the forward legs (the layout trg_init_factors takes); *r_out the
+ * bond r.  Either array pointer may be NULL (then only *r_out is written).
+ * Host memory, caller owns it.  Synchronises.  Errors: TRG_EINVAL (capacity
+ * too small), TRG_ESTATE (a HOTRG context). */
+int trg_get_factors(trg_ctx *ctx, double *host_G, size_t cap_G, double *host_H, size_t cap_H, int *r_out);
 
 /* Coarse-grain the periodic lattice L^d (L = 2^m, m >= 1; each step halves
  * the lattice, so the block volume reaches 2^n after n steps as in the

@@ -609,6 +609,8 @@ class AtrgStep:
     swap_sigma: np.ndarray
     local_s: np.ndarray
     axes: list = field(default_factory=list)
+    legs: list = None       # Z2 mode: leg parities after the step (per axis)
+    bond: np.ndarray = None  # Z2 mode: bond parities after the step
 
 
 def middle_svd(A: np.ndarray, B: np.ndarray, dcut: int, p: int, q: int, step: int, seed: int, stream: int,
@@ -803,6 +805,7 @@ def run(beta: float, h: float, d: int, dcut: int, L: int, p=None, q=None, seed: 
             F, kpar = canonical_z2(G, H, dcut, legs, bond)
             G, H, c, rec, imps2, legs, bond = atrg_step_z2(F, kpar, legs, mu, dcut, p, q, n, seed, imps)
             imps = imps2 if impure else None
+            rec.legs, rec.bond = [x.copy() for x in legs], bond.copy()
         else:
             F = canonical(G, H, dcut)
             if impure:

@@ -32,6 +32,7 @@ class TrgConfig(C.Structure):
         ("alloc_user", C.c_void_p),
         ("workspace_bytes", C.c_size_t),
         ("fp64_steps", C.c_int),
+        ("z2", C.c_int),
     ]
 
 
@@ -62,6 +63,10 @@ SIGNATURES = {
     "trg_init_factors": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int), C.c_int,
                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(TrgConfig)]),
     "trg_atrg_spectrum": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int)]),
+    "trg_atrg_parities": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_size_t, C.POINTER(C.c_int), C.c_size_t,
+                                    C.POINTER(C.c_int)]),
+    "trg_get_factors": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_size_t, C.POINTER(C.c_double), C.c_size_t,
+                                  C.POINTER(C.c_int)]),
     "trg_run": (C.c_int, [C.c_void_p, C.c_longlong]),
     "trg_free_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "trg_impure_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),

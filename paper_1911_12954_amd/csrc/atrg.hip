@@ -32,6 +32,7 @@
 // (K-contiguous, zero-padded) by the strided map kernel and multiplied by the
 // MFMA GEMM of the HOTRG join.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 
@@ -194,29 +195,33 @@ chol_inv_kernel(const double *C, int n, double shift_coef, double *R, double *Ri
   }
 }
 
-// The same factorisation for n <= 128 with the matrix in registers: a 16 x 16
-// grid of threads, thread (ti, tj) holding the 8 x 8 elements (ti + 16 a,
-// tj + 16 b).  Right-looking by columns, two barriers each: the owners of
-// row j scale it by the pivot and publish it in LDS, then every thread
-// updates its elements of the trailing triangle (A[p][q] -= R[j][p] R[j][q]);
-// the owner of the next diagonal element publishes it.  The inverse runs the
-// same way from the last row up (X[p][q] -= R[p][k] X[k][q] once row k of X
-// is final) with R read from LDS.  Each element sees the operations of the
-// column-by-column elimination in the same order as a one-thread-per-element
-// elimination would apply them.
+// The same factorisation for n <= 128, with the matrix in registers: wave w
+// (of four) owns the rows p = w (mod 4) and lane l the columns l and l + 64,
+// so thread (w, l) holds the 32 x 2 elements (w + 4 pp, l + 64 qq).  Whether
+// a thread holds row p is a property of its wave, so every row test below is
+// uniform across the wave and costs a scalar branch, not a lane mask.
+// Column j of the elimination: the wave owning row j publishes it in LDS,
+// every thread reads the pivot (a pivot at or below the dead tolerance makes
+// the row zero and its pivot 1) and updates its elements of the trailing
+// triangle, A[p][q] -= R[j][p] R[j][q]; two barriers per column.  The scaled
+// rows of R are kept in LDS (packed upper triangle) for the inverse, which
+// runs the same way from the last row up: row k of X = R^-1 is final once
+// every row below it has been eliminated, is scaled by 1 / R[k][k] and
+// published, and the rows above subtract R[p][k] X[k][q].
 constexpr int CHOL_REG_MAX = 128;
 constexpr int CHOL_THREADS = 256;
 
+__device__ inline int chol_packed(int p, int q, int n) { return p * n - (p * (p - 1)) / 2 + (q - p); }
+
 __global__ void __launch_bounds__(CHOL_THREADS)
 chol_inv_reg_kernel(const double *C, int n, double shift_coef, double *Rg, double *Rinv, int *err) {
-  extern __shared__ double Rl[];   // n x n: R for the inverse
+  extern __shared__ double Rl[];   // packed upper triangle of R, n (n + 1) / 2
   __shared__ double sh[CHOL_THREADS];
   __shared__ double shm[CHOL_THREADS];
+  __shared__ double rowv[CHOL_REG_MAX];
+  __shared__ double pivs[CHOL_REG_MAX];
   __shared__ int dead[CHOL_REG_MAX];
-  __shared__ double rowbuf[CHOL_REG_MAX];
-  __shared__ double diag;
-  const int t = threadIdx.x;
-  const int ti = t >> 4, tj = t & 15;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
   double tr = 0.0, mx = 0.0;
   for (int i = t; i < n; i += CHOL_THREADS) {
     tr += C[i * n + i];
@@ -234,128 +239,118 @@ chol_inv_reg_kernel(const double *C, int n, double shift_coef, double *Rg, doubl
   }
   const double shift = shift_coef * sh[0];
   const double tol = 1e-26 * (shm[0] + shift);
-  double A[8][8];
+  double E[32][2];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int pp = 0; pp < 32; ++pp)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int r = ti + 16 * a, c = tj + 16 * b;
-      A[a][b] = (r <= c && c < n) ? C[r * n + c] + (r == c ? shift : 0.0) : 0.0;
+    for (int qq = 0; qq < 2; ++qq) {
+      const int p = w + 4 * pp, q = l + 64 * qq;
+      E[pp][qq] = (p <= q && q < n) ? C[p * n + q] + (p == q ? shift : 0.0) : 0.0;
     }
-  for (int i = t; i < n; i += CHOL_THREADS) dead[i] = 0;
-  if (t == 0) diag = C[0] + shift;
-  __syncthreads();
   for (int j = 0; j < n; ++j) {
-    const int aj = j >> 4;
-    if (ti == (j & 15)) {
-      // row j: its diagonal has received the updates of every row above
-      double dj = diag;
-      const bool isdead = !(dj > tol);
-      if (isdead) dj = 1.0;
-      const double piv = sqrt(dj);
-      if (tj == (j & 15)) {
-        dead[j] = isdead ? 1 : 0;
-        if (isdead && !isfinite(diag)) *err |= 4;
+    if (w == (j & 3)) {
+      const int pj = j >> 2;
+#pragma unroll
+      for (int pp = 0; pp < 32; ++pp)
+        if (pp == pj) {
+#pragma unroll
+          for (int qq = 0; qq < 2; ++qq) {
+            const int q = l + 64 * qq;
+            if (q >= j && q < n) rowv[q] = E[pp][qq];
+          }
+        }
+    }
+    __syncthreads();
+    const double dj = rowv[j];
+    const bool isdead = !(dj > tol);
+    const double piv = isdead ? 1.0 : sqrt(dj);
+    const double inv = isdead ? 0.0 : 1.0 / piv;
+    if (t == 0) {
+      pivs[j] = piv;
+      dead[j] = isdead ? 1 : 0;
+      if (isdead && !isfinite(dj)) *err |= 4;
+      Rl[chol_packed(j, j, n)] = piv;
+    }
+    for (int q = j + 1 + t; q < n; q += CHOL_THREADS) Rl[chol_packed(j, q, n)] = rowv[q] * inv;
+    double rq[2];
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) {
+      const int q = l + 64 * qq;
+      rq[qq] = (q > j && q < n) ? rowv[q] * inv : 0.0;
+    }
+#pragma unroll
+    for (int pp = 0; pp < 32; ++pp) {
+      const int p = w + 4 * pp;
+      if (p > j && p < n) {
+        const double rp = rowv[p] * inv;
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq) E[pp][qq] -= rp * rq[qq];
       }
+    }
+    __syncthreads();
+  }
+  // X = R^-1 in the same registers
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const int c = tj + 16 * b;
+  for (int pp = 0; pp < 32; ++pp)
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
-          if (a == aj) {
-            if (c == j) {
-              A[a][b] = piv;
-            } else if (c > j && c < n) {
-              const double v = isdead ? 0.0 : A[a][b] / piv;
-              A[a][b] = v;
-              rowbuf[c] = v;
+    for (int qq = 0; qq < 2; ++qq) E[pp][qq] = (w + 4 * pp == l + 64 * qq) ? 1.0 : 0.0;
+  for (int k = n - 1; k >= 0; --k) {
+    if (w == (k & 3)) {
+      const int pk = k >> 2;
+      const double ik = 1.0 / pivs[k];
+#pragma unroll
+      for (int pp = 0; pp < 32; ++pp)
+        if (pp == pk) {
+#pragma unroll
+          for (int qq = 0; qq < 2; ++qq) {
+            const int q = l + 64 * qq;
+            if (q >= k && q < n) {
+              E[pp][qq] *= ik;
+              rowv[q] = E[pp][qq];
             }
           }
-      }
-    }
-    __syncthreads();
-    // trailing triangle j < p <= q
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int p = ti + 16 * a;
-      if (p > j && p < n) {
-        const double rp = rowbuf[p];
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int q = tj + 16 * b;
-          if (q >= p && q < n) A[a][b] -= rp * rowbuf[q];
         }
-      }
-    }
-    const int jn = j + 1;
-    if (jn < n && ti == (jn & 15) && tj == (jn & 15)) {
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-        if (a == (jn >> 4)) diag = A[a][a];
     }
     __syncthreads();
-  }
-  // R to LDS (upper triangle; the lower one is never read), X = I in registers
+    double xq[2];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int r = ti + 16 * a, c = tj + 16 * b;
-      if (r <= c && c < n) Rl[r * n + c] = A[a][b];
-      A[a][b] = (r == c && c < n) ? 1.0 : 0.0;
+    for (int qq = 0; qq < 2; ++qq) {
+      const int q = l + 64 * qq;
+      xq[qq] = (q >= k && q < n) ? rowv[q] : 0.0;
     }
-  __syncthreads();
-  for (int k = n - 1; k >= 0; --k) {
-    const int ak = k >> 4;
-    if (ti == (k & 15)) {
-      const double inv = 1.0 / Rl[k * n + k];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const int c = tj + 16 * b;
-#pragma unroll
-        for (int a = 0; a < 8; ++a)
-          if (a == ak && c >= k && c < n) {
-            A[a][b] *= inv;
-            rowbuf[c] = A[a][b];
-          }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int p = ti + 16 * a;
+    for (int pp = 0; pp < 32; ++pp) {
+      const int p = w + 4 * pp;
       if (p < k) {
-        const double rpk = Rl[p * n + k];
+        const double rpk = Rl[chol_packed(p, k, n)];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int q = tj + 16 * b;
-          if (q >= k && q < n) A[a][b] -= rpk * rowbuf[q];
-        }
+        for (int qq = 0; qq < 2; ++qq) E[pp][qq] -= rpk * xq[qq];
       }
     }
     __syncthreads();
   }
+  for (int i = t; i < n * n; i += CHOL_THREADS) {
+    const int r = i / n, c = i % n;
+    Rg[i] = (r <= c && !dead[r]) ? Rl[chol_packed(r, c, n)] : 0.0;
+  }
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int pp = 0; pp < 32; ++pp)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int r = ti + 16 * a, c = tj + 16 * b;
-      if (r < n && c < n) {
-        Rinv[r * n + c] = (r <= c && !dead[c]) ? A[a][b] : 0.0;
-        Rg[r * n + c] = (r <= c && !dead[r]) ? Rl[r * n + c] : 0.0;
-      }
+    for (int qq = 0; qq < 2; ++qq) {
+      const int p = w + 4 * pp, q = l + 64 * qq;
+      if (p < n && q < n) Rinv[p * n + q] = (p <= q && !dead[q]) ? E[pp][qq] : 0.0;
     }
 }
 
 void launch_chol_inv(const double *C, int n, double shift, double *R, double *Rinv, int *err, hipStream_t st) {
   TRG_REQUIRE(n >= 1 && n <= 1024, "chol: bad order");
   if (n <= CHOL_REG_MAX) {
-    const size_t lds = size_t(n) * n * 8;   // R for the inverse
+    const size_t lds = size_t(n) * (n + 1) / 2 * 8;   // packed R for the inverse
     static bool attr = false;
     if (!attr) {
       TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&chol_inv_reg_kernel),
                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        CHOL_REG_MAX * CHOL_REG_MAX * 8));
+                                        CHOL_REG_MAX * (CHOL_REG_MAX + 1) / 2 * 8));
       attr = true;
     }
     hipLaunchKernelGGL(chol_inv_reg_kernel, dim3(1), dim3(CHOL_THREADS), lds, st, C, n, shift, R, Rinv, err);
@@ -423,65 +418,190 @@ ts_gram_kernel(const double *__restrict__ Y, int64_t m, int k, int64_t rpw, doub
       }
 }
 
-// Q = Y R for a tall m x k row-major Y and a k x k R (k <= 128) on FP64
-// MFMA, in place: a workgroup takes 128 rows of Y, staged in LDS with a row
-// stride of 130 doubles (the 16 rows x 2 k values that 32 lanes read fall on
-// distinct banks; 16 consecutive lanes store contiguous bytes), each wave 32
-// rows x 128 columns, so every fragment of R read from L2 feeds two MFMAs.
-constexpr int TSM_ROWS = 128, TSM_LD = 130;
+// Q = Y R for a tall m x k row-major Y and an upper triangular k x k R
+// (k <= 128; the inverse Cholesky factor) on FP64 MFMA.  R is staged once
+// per workgroup in LDS (row stride 144 doubles: the four k-rows that one
+// MFMA's B fragment reads fall on the two halves of the banks); the
+// workgroup then walks row tiles of 256 rows, each of its eight waves 32
+// rows x all columns, with Y read straight from memory into the A fragments
+// (lane (g, r16) takes columns 16u + 4g .. 16u + 4g + 3 of its two rows for
+// K chunk u, the next chunk prefetched while the current one is multiplied)
+// and Q written from the accumulators.  K index 16u + 4g + e feeds MFMA e of
+// chunk u on both sides, so the order of K inside a chunk is permuted alike
+// for A and B.  Blocks of R below the diagonal are zero and skipped: chunk u
+// only meets column blocks j >= u.
+constexpr int TSM_WAVES = 8, TSM_ROWS = 32 * TSM_WAVES, TSM_LD = 144;
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * TSM_WAVES)
 ts_mul_kernel(const double *__restrict__ Y, int64_t m, int k, const double *__restrict__ R, double *__restrict__ Q) {
-  extern __shared__ double L[];
+  extern __shared__ double Rl[];   // TSG_K x TSM_LD
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int g = lane >> 4, r16 = lane & 15;
-  const int64_t r0 = int64_t(blockIdx.x) * TSM_ROWS;
-  const int64_t rows = m - r0 < TSM_ROWS ? m - r0 : TSM_ROWS;
-  for (int idx = t; idx < TSM_ROWS * TSG_K; idx += 256) {
+  for (int idx = t; idx < TSG_K * TSG_K; idx += 64 * TSM_WAVES) {
     const int r = idx / TSG_K, c = idx % TSG_K;
-    L[r * TSM_LD + c] = (r < rows && c < k) ? Y[(r0 + r) * k + c] : 0.0;
+    Rl[r * TSM_LD + c] = (r < k && c < k) ? R[r * k + c] : 0.0;
   }
   __syncthreads();
-  tsg_v4d acc[2][8];
+  const int nu = (k + 15) / 16;   // K chunks = column blocks
+  const int64_t ntiles = (m + TSM_ROWS - 1) / TSM_ROWS;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t rbase = tile * TSM_ROWS + 32 * wave;
+    int64_t rows[2];
+    bool rok[2];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc[h][j] = tsg_v4d{0.0, 0.0, 0.0, 0.0};
-  for (int s = 0; s < TSG_K / 4; ++s) {
-    const int kk = 4 * s + g;
-    double a[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) a[h] = L[(32 * wave + 16 * h + r16) * TSM_LD + kk];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int col = 16 * j + r16;
-      const double b = (kk < k && col < k) ? R[kk * k + col] : 0.0;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) acc[h][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], b, acc[h][j], 0, 0, 0);
+    for (int h = 0; h < 2; ++h) {
+      rows[h] = rbase + 16 * h + r16;
+      rok[h] = rows[h] < m;
     }
-  }
+    auto load = [&](int u, double (&a)[2][4]) {
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+        for (int e = 0; e < 4; ++e) {
+          const int col = 16 * u + 4 * g + e;
+          a[h][e] = (rok[h] && col < k) ? Y[rows[h] * k + col] : 0.0;
+        }
+    };
+    tsg_v4d acc[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[h][j] = tsg_v4d{0.0, 0.0, 0.0, 0.0};
+    double a[2][4], an[2][4];
+    load(0, a);
+    for (int u = 0; u < nu; ++u) {
+      if (u + 1 < nu) load(u + 1, an);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t row = 32 * wave + 16 * h + g + 4 * e;
-        const int col = 16 * j + r16;
-        if (row < rows && col < k) Q[(r0 + row) * k + col] = acc[h][j][e];
+        const double *brow = Rl + (16 * u + 4 * g + e) * TSM_LD + r16;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j >= u && j < nu) {
+            const double b = brow[16 * j];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) acc[h][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][e], b, acc[h][j], 0, 0, 0);
+          }
       }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[h][e] = an[h][e];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = rbase + 16 * h + g + 4 * e;
+          const int col = 16 * j + r16;
+          if (row < m && col < k) Q[row * k + col] = acc[h][j][e];
+        }
+  }
 }
 
 void launch_ts_mul(const double *Y, int64_t m, int k, const double *R, double *Q, hipStream_t st) {
-  const size_t lds = size_t(TSM_ROWS) * TSM_LD * 8;
+  TRG_REQUIRE(k >= 1 && k <= TSG_K, "ts_mul: k out of range");
+  const size_t lds = size_t(TSG_K) * TSM_LD * 8;
   static bool attr = false;
   if (!attr) {
     TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&ts_mul_kernel),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     attr = true;
   }
-  hipLaunchKernelGGL(ts_mul_kernel, dim3(uint32_t((m + TSM_ROWS - 1) / TSM_ROWS)), dim3(256), lds, st, Y, m, k, R, Q);
+  // one workgroup per CU (the LDS copy of R), each walking its row tiles
+  const int64_t ntiles = (m + TSM_ROWS - 1) / TSM_ROWS;
+  const uint32_t grid = uint32_t(ntiles < 256 ? ntiles : 256);
+  hipLaunchKernelGGL(ts_mul_kernel, dim3(grid), dim3(64 * TSM_WAVES), lds, st, Y, m, k, R, Q);
   TRG_HIP_CHECK(hipGetLastError());
+}
+
+// One isometry applied to a leg pair on FP64 MFMA:
+//   out[kept..., B] = sum_{a, b} src[..., a, ..., b, ...] P[a, b, B]
+// with P row-major [a][b][B] (dn x dn x nd).  Rows m of the product are the
+// kept legs (mixed radix over size[], outermost first; src strides sstr,
+// out strides ostr), K = (a, b) and N = B.  Each wave takes 32 rows and
+// every column block of B, so each source element is read once; lane
+// (g, r16) loads rows 16 h + r16 (consecutive source addresses when the
+// innermost kept leg has source stride 1) at K index 4 s + g, and the P
+// fragment comes through the cache (P is small).
+struct PairSpec {
+  int nk;
+  int64_t size[7], sstr[7], ostr[7];
+  int64_t M;
+  int dn, nd;
+  int64_t sa, sb, ostrB;
+};
+constexpr int PC_WAVES = 4;
+
+__global__ void __launch_bounds__(64 * PC_WAVES)
+pair_contract_kernel(const double *__restrict__ src, const double *__restrict__ P, double *__restrict__ out,
+                     PairSpec ps) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  const int64_t m0 = (int64_t(blockIdx.x) * PC_WAVES + wave) * 32;
+  if (m0 >= ps.M) return;
+  const int K = ps.dn * ps.dn;
+  const int nj = (ps.nd + 15) / 16;
+  // source offsets of this lane's two A rows
+  int64_t soff[2];
+  bool rok[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    int64_t m = m0 + 16 * h + r16;
+    rok[h] = m < ps.M;
+    int64_t off = 0;
+    for (int f = ps.nk - 1; f >= 0; --f) {
+      const int64_t q = m / ps.size[f];
+      off += (m - q * ps.size[f]) * ps.sstr[f];
+      m = q;
+    }
+    soff[h] = rok[h] ? off : 0;
+  }
+  tsg_v4d acc[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[h][j] = tsg_v4d{0.0, 0.0, 0.0, 0.0};
+  int a = g / ps.dn, b = g - (g / ps.dn) * ps.dn;   // (a, b) of K index k = 4 s + g
+  for (int k = g; k - g < K; k += 4) {
+    const bool kok = k < K;
+    const int64_t koff = int64_t(a) * ps.sa + int64_t(b) * ps.sb;
+    double av[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) av[h] = (rok[h] && kok) ? src[soff[h] + koff] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < nj) {
+        const int n = 16 * j + r16;
+        const double bv = (kok && n < ps.nd) ? P[int64_t(k) * ps.nd + n] : 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[h][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h], bv, acc[h][j], 0, 0, 0);
+      }
+    b += 4;
+    while (b >= ps.dn) {
+      b -= ps.dn;
+      ++a;
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int64_t m = m0 + 16 * h + g + 4 * e;
+      if (m >= ps.M) continue;
+      int64_t off = 0;
+      for (int f = ps.nk - 1; f >= 0; --f) {
+        const int64_t q = m / ps.size[f];
+        off += (m - q * ps.size[f]) * ps.ostr[f];
+        m = q;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = 16 * j + r16;
+        if (j < nj && n < ps.nd) out[off + int64_t(n) * ps.ostrB] = acc[h][j][e];
+      }
+    }
 }
 
 // C = A B for n x n matrices (one workgroup)
@@ -616,6 +736,86 @@ __global__ void __launch_bounds__(256) sum_partials(const double *partial, int n
   if (threadIdx.x == 0) *out = sh[0];
 }
 
+// --------------------------------------------------------------- Z2 sectors ---
+// In the Z2 mode every leg index and bond index has a parity (0 even, 1
+// odd) and the pieces vanish unless the legs' parities add up to the bond's.
+// Every kernel of the step keeps such zeros exact (a product with an exact
+// zero is zero, and the decompositions below only combine indices of one
+// sector), so no projection is ever needed.
+
+// Bond of the initial pieces rotated to definite parity: the column pair
+// (l0, l1) of the n x 2 row-major G becomes ((l0 + l1), (l0 - l1)) / sqrt 2,
+// likewise the two rows of the 2 x n H.  At h = 0 the spin-down entries are
+// the spin-up ones times (-1)^(number of odd legs) exactly, so the rotated
+// entries of the wrong parity are exact zeros.  Either pointer may be null.
+__global__ void z2_rotate_kernel(double *G, double *H, int64_t n) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const double r = 0.70710678118654752440;
+  if (G) {
+    const double a = G[2 * i], b = G[2 * i + 1];
+    G[2 * i] = (a + b) * r;
+    G[2 * i + 1] = (a - b) * r;
+  }
+  if (H) {
+    const double a = H[i], b = H[n + i];
+    H[i] = (a + b) * r;
+    H[n + i] = (a - b) * r;
+  }
+}
+
+// Parity of a composite row index (row-major over nf legs, outermost
+// first) from the legs' parity tables packed in `par` at off[f].
+struct ParSpec {
+  int nf;
+  int size[5];
+  int off[5];
+};
+
+__device__ inline int spec_parity(const int *par, const ParSpec &s, int64_t i) {
+  int p = 0;
+  for (int f = s.nf - 1; f >= 0; --f) {
+    const int64_t sz = s.size[f];
+    const int64_t q = i / sz;
+    p ^= par[s.off[f] + int(i - q * sz)];
+    i = q;
+  }
+  return p;
+}
+
+// Trial matrix Om[rows, cols] (rows (f_perp, kB)): an entry survives only
+// when its row parity equals the sector of its column, c mod 2 for c < 2 h
+// and `big` beyond.
+__global__ void z2_mask_kernel(double *Om, int64_t rows, int cols, const int *par, ParSpec spec, int h, int big) {
+  const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t row = e / cols;
+  const int col = int(e - row * cols);
+  const int sec = col < 2 * h ? (col & 1) : big;
+  if (spec_parity(par, spec, row) != sec) Om[e] = 0.0;
+}
+
+// B[b][i][j] = A[b][perm_b[i]][perm_b[j]] for the batch of symmetric n x n
+// matrices (grid.y = batch; perm holds n entries per matrix)
+__global__ void gather_sym_kernel(const double *A, double *B, const int *perm, int n) {
+  const int64_t nn = int64_t(n) * n;
+  const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (e >= nn) return;
+  const int i = int(e / n), j = int(e - int64_t(e / n) * n);
+  const int *p = perm + size_t(blockIdx.y) * n;
+  B[size_t(blockIdx.y) * nn + e] = A[size_t(blockIdx.y) * nn + size_t(p[i]) * n + p[j]];
+}
+
+// eigenvector rows back to the original order: V[b][perm_b[i]][c] = Vs[b][i][c]
+__global__ void scatter_rows_kernel(const double *Vs, double *V, const int *perm, int n) {
+  const int64_t nn = int64_t(n) * n;
+  const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (e >= nn) return;
+  const int i = int(e / n), col = int(e - int64_t(e / n) * n);
+  const int *p = perm + size_t(blockIdx.y) * n;
+  V[size_t(blockIdx.y) * nn + size_t(p[i]) * n + col] = Vs[size_t(blockIdx.y) * nn + e];
+}
+
 // ------------------------------------------------------------- host helpers ---
 // Step trace for diagnosing an ATRG run: with TRG_DEBUG set in the
 // environment, every named intermediate is copied back and summarised on
@@ -707,10 +907,92 @@ void cholqr3(trg_ctx &c, const double *Y, int64_t m, int k, double *Q, double *R
   if (Rout) TRG_HIP_CHECK(hipMemcpyAsync(Rout, Racc, size_t(k) * k * 8, hipMemcpyDeviceToDevice, c.st));
 }
 
+// ---- Z2 bookkeeping on the host
+using Par = std::vector<int8_t>;
+
+// numbers of even and odd composite indices of legs with these parities
+std::array<int64_t, 2> parity_counts(const std::vector<const Par *> &legs) {
+  int64_t e = 1, o = 0;
+  for (const Par *p : legs) {
+    int64_t pe = 0, po = 0;
+    for (int8_t x : *p) (x ? po : pe) += 1;
+    const int64_t ne = e * pe + o * po, no = e * po + o * pe;
+    e = ne;
+    o = no;
+  }
+  return {e, o};
+}
+
+// composite parity of the row-major index over two legs
+Par pair_parity(const Par &a, const Par &b) {
+  Par out;
+  out.reserve(a.size() * b.size());
+  for (int8_t x : a)
+    for (int8_t y : b) out.push_back(int8_t(x ^ y));
+  return out;
+}
+
+// the indices of parity 0 in order, then those of parity 1, appended to out
+void append_sector_order(const Par &p, std::vector<int> &out) {
+  for (int s = 0; s < 2; ++s)
+    for (size_t i = 0; i < p.size(); ++i)
+      if (p[i] == s) out.push_back(int(i));
+}
+
+// Parity of each column of the rows x cols row-major device matrix M whose
+// rows have parities rowpar: the sector that holds the larger part of the
+// column's squared norm (the other part is zero for a column inside one
+// sector).  Synchronises.
+Par column_parities(trg_ctx &c, const double *M, int64_t rows, int cols, const Par &rowpar) {
+  TRG_REQUIRE(int64_t(rowpar.size()) == rows, "z2: row parity table has the wrong size");
+  std::vector<double> h(size_t(rows) * cols);
+  TRG_HIP_CHECK(hipMemcpyAsync(h.data(), M, h.size() * 8, hipMemcpyDeviceToHost, c.st));
+  sync_check(c);
+  Par out(size_t(cols), 0);
+  for (int j = 0; j < cols; ++j) {
+    double w[2] = {0.0, 0.0};
+    for (int64_t i = 0; i < rows; ++i) w[rowpar[size_t(i)]] += h[size_t(i) * cols + j] * h[size_t(i) * cols + j];
+    out[size_t(j)] = int8_t(w[1] > w[0]);
+  }
+  return out;
+}
+
+// host table -> device buffer `tag`, queued on the context's stream; the
+// table is one of the context's staging vectors, so it outlives the copy
+int *upload(trg_ctx &c, const std::vector<int> &v, const std::string &tag) {
+  int *d = c.wsp<int>(tag, v.size() * 4);
+  TRG_HIP_CHECK(hipMemcpyAsync(d, v.data(), v.size() * 4, hipMemcpyHostToDevice, c.st));
+  return d;
+}
+
+// eigh_batched of `batch` symmetric n x n matrices whose indices fall into
+// two parity sectors, with perm (device, n entries per matrix) the sector
+// order of each: Jacobi keeps sectors apart by itself; above its range the
+// matrices are diagonalised in sector order and the eigenvector rows put
+// back.  perm == nullptr: plain eigh_batched.
+void eigh_sectors(trg_ctx &c, double *A, double *w, double *V, int *sw, int n, int batch, const int *perm,
+                  const std::string &tag) {
+  if (!perm || n <= JACOBI_MAX_N) {
+    eigh_batched(A, w, V, sw, n, batch, c.st);
+    return;
+  }
+  double *As = c.wsp<double>("zA" + tag, size_t(batch) * n * n * 8);
+  double *Vs = c.wsp<double>("zV" + tag, size_t(batch) * n * n * 8);
+  const dim3 grid(uint32_t((int64_t(n) * n + 255) / 256), uint32_t(batch));
+  hipLaunchKernelGGL(gather_sym_kernel, grid, dim3(256), 0, c.st, A, As, perm, n);
+  TRG_HIP_CHECK(hipGetLastError());
+  eigh_batched(As, w, Vs, sw, n, batch, c.st);
+  hipLaunchKernelGGL(scatter_rows_kernel, grid, dim3(256), 0, c.st, Vs, V, perm, n);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
 // SVD of the k x k matrix Cm = W diag(s) Z^T through the eigendecomposition
-// of [[0, Cm], [Cm^T, 0]]; keeps the first kk columns.
+// of [[0, Cm], [Cm^T, 0]]; keeps the first kk columns.  par (optional): the
+// parity of the k row indices and of the k column indices of a Cm that
+// vanishes between different parities; stage: the context staging vector
+// for the sector order of the eigenproblem.
 void small_svd(trg_ctx &c, const double *Cm, int k, int kk, double *s, double *sqs, double *W, double *Z,
-               const std::string &tag) {
+               const std::string &tag, const Par *par = nullptr, std::vector<int> *stage = nullptr) {
   const int m = 2 * k;
   double *J = c.wsp<double>("svdJ" + tag, size_t(m) * m * 8);
   double *w = c.wsp<double>("svdw" + tag, size_t(m) * 8);
@@ -718,7 +1000,16 @@ void small_svd(trg_ctx &c, const double *Cm, int k, int kk, double *s, double *s
   int *sw = c.wsp<int>("svdsw" + tag, 16);
   hipLaunchKernelGGL(jw_build_kernel, dim3(64), dim3(256), 0, c.st, Cm, k, J);
   TRG_HIP_CHECK(hipGetLastError());
-  eigh_batched(J, w, V, sw, m, 1, c.st);
+  const int *perm = nullptr;
+  if (par && m > JACOBI_MAX_N) {
+    TRG_REQUIRE(int(par->size()) == k && stage, "small_svd: bad sector table");
+    Par jp(*par);
+    jp.insert(jp.end(), par->begin(), par->end());
+    stage->clear();
+    append_sector_order(jp, *stage);
+    perm = upload(c, *stage, "svdperm" + tag);
+  }
+  eigh_sectors(c, J, w, V, sw, m, 1, perm, "svd" + tag);
   hipLaunchKernelGGL(jw_extract_kernel, dim3(1), dim3(256), 0, c.st, w, V, k, kk, s, sqs, W, Z);
   TRG_HIP_CHECK(hipGetLastError());
 }
@@ -818,6 +1109,39 @@ void einsum2(trg_ctx &c, const double *A, const View &va, const double *B, const
   apply_map(Cp, prec == TRG_FP64 ? IN_F64 : IN_F32, cv, nullptr, {}, {}, C, OUT_F64, 0, contiguous(ol), c.st);
 }
 
+// out (view outv) = src (view inv) with the leg pair (la, lb) contracted
+// against P[la, lb, lB] (row-major, FP64): outv holds every other leg of inv
+// and lB.  Rows are ordered as the kept legs appear in outv.
+void pair_contract(trg_ctx &c, const double *src, const View &inv, const std::string &la, const std::string &lb,
+                   const double *P, const std::string &lB, double *out, const View &outv) {
+  PairSpec ps{};
+  const Leg &A = find_leg(inv, la), &B = find_leg(inv, lb), &O = find_leg(outv, lB);
+  TRG_REQUIRE(A.size == B.size && A.size <= 1024, "pair_contract: pair legs differ");
+  TRG_REQUIRE(O.size >= 1 && O.size <= 64, "pair_contract: isometry width out of range");
+  ps.dn = int(A.size);
+  ps.nd = int(O.size);
+  ps.sa = A.stride;
+  ps.sb = B.stride;
+  ps.ostrB = O.stride;
+  ps.M = 1;
+  for (const auto &l : outv) {
+    if (l.name == lB) continue;
+    TRG_REQUIRE(ps.nk < 7, "pair_contract: too many legs");
+    const Leg &sl = find_leg(inv, l.name);
+    TRG_REQUIRE(sl.size == l.size, "pair_contract: leg sizes differ");
+    ps.size[ps.nk] = l.size;
+    ps.sstr[ps.nk] = sl.stride;
+    ps.ostr[ps.nk] = l.stride;
+    ++ps.nk;
+    ps.M *= l.size;
+  }
+  TRG_REQUIRE(int64_t(ps.nk) + 2 == int64_t(inv.size()) && ps.nk >= 1, "pair_contract: stray legs");
+  const int64_t blocks = (ps.M + 32 * PC_WAVES - 1) / (32 * PC_WAVES);
+  TRG_REQUIRE(blocks < (int64_t(1) << 31), "pair_contract: too many rows");
+  hipLaunchKernelGGL(pair_contract_kernel, dim3(uint32_t(blocks)), dim3(64 * PC_WAVES), 0, c.st, src, P, out, ps);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
 // --------------------------------------------------------------- init / step ---
 void atrg_init_ising(trg_ctx &c, double beta, double h) {
   const int d = c.d;
@@ -828,6 +1152,14 @@ void atrg_init_ising(trg_ctx &c, double beta, double h) {
   double *G = static_cast<double *>(c.G.ptr), *H = static_cast<double *>(c.H.ptr);
   hipLaunchKernelGGL(atrg_ising_kernel, dim3(1), dim3(64), 0, c.st, G, H, d, beta, h);
   TRG_HIP_CHECK(hipGetLastError());
+  if (c.z2) {
+    // bond of definite parity; every leg index b of the W basis has parity b
+    TRG_REQUIRE(h == 0.0, "the Z2 mode needs h = 0");
+    hipLaunchKernelGGL(z2_rotate_kernel, dim3(1), dim3(64), 0, c.st, G, H, n);
+    TRG_HIP_CHECK(hipGetLastError());
+    for (int a = 0; a < d; ++a) c.z2_legs[a] = {0, 1};
+    c.z2_bond = {0, 1};
+  }
   // c_0 = ||G H||_F, both pieces scaled by c_0^{-1/2}
   double *GtG = c.wsp<double>("nGtG", 4 * 8), *HHt = c.wsp<double>("nHHt", 4 * 8);
   View vg = contiguous({{"b", n}, {"l", 2}}), vh = contiguous({{"l", 2}, {"f", n}});
@@ -851,6 +1183,10 @@ void atrg_init_ising(trg_ctx &c, double beta, double h) {
     hipLaunchKernelGGL(atrg_impurity_kernel, dim3(1), dim3(64), 0, c.st, c.imp_kind[j] == 0 ? HS : nullptr,
                        c.imp_kind[j] == 1 ? HS : nullptr, d, beta, h);
     TRG_HIP_CHECK(hipGetLastError());
+    if (c.z2) {   // the impurity's bond rotated like the pure one
+      hipLaunchKernelGGL(z2_rotate_kernel, dim3(1), dim3(64), 0, c.st, nullptr, HS, n);
+      TRG_HIP_CHECK(hipGetLastError());
+    }
     scale_by_inverse(HS, n * 2, c.scal(), 1.0, c.st);
     c.imp_r[j] = 2;
   }
@@ -961,7 +1297,10 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
   double *s = c.wsp<double>("cs", size_t(k) * 8), *sqs = c.wsp<double>("csq", size_t(k) * 8);
   double *W = c.wsp<double>("cW", size_t(r) * k * 8), *Z = c.wsp<double>("cZ", size_t(r) * k * 8);
   dbg(c, "Cm", Cm, int64_t(r) * r);
-  small_svd(c, Cm, r, k, s, sqs, W, Z, "core");
+  if (c.z2) TRG_REQUIRE(int(c.z2_bond.size()) == r, "z2: bond parity table does not match the bond");
+  small_svd(c, Cm, r, k, s, sqs, W, Z, "core", c.z2 ? &c.z2_bond : nullptr, &c.z2_stage[0]);
+  // Z2: parity of each kept bond index (its left singular vector lies in one sector)
+  const Par kpar = c.z2 ? column_parities(c, W, r, k, c.z2_bond) : Par{};
   dbg(c, "s", s, k);
   dbg(c, "W", W, int64_t(r) * k);
   // Ut[b..., k] = Qg W sqrt(s); Vt[k, f...] = sqrt(s) (Qh Z)^T
@@ -1004,16 +1343,38 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
   // in factored form (two GEMMs each).  Returns Xs[kA, b_perp, l] =
   // Q W sqrt(sigma), Ys[l, f_perp, kB] = sqrt(sigma) (Qbt Z)^T and sigma in
   // workspace buffers named with `tag`, and the rank.
+  // With `sectors` (Z2 mode, pure swap) the trial columns are split into the
+  // two parity sectors (column c in sector c mod 2 while both have room,
+  // i.e. fewer columns than rows and columns of that parity, the rest in
+  // the larger sector) and the trial matrix keeps only the entries whose
+  // row parity equals the column's sector; every later product and
+  // factorisation keeps the sectors apart, and par receives the parity of
+  // each kept singular vector.
   struct SwapOut {
     double *Xs, *Ys, *sig;
     int dc;
+    Par par;
   };
   auto partial_svd = [&](const double *A, const View &vA, int64_t ra, const double *B, const View &vB,
-                         int64_t cb, uint32_t stream, const std::string &tag) -> SwapOut {
+                         int64_t cb, uint32_t stream, const std::string &tag, bool sectors) -> SwapOut {
     const int64_t nr = ra * nperp, nc = nperp * cb;
     int r2 = dcut + p;
     if (r2 > nr) r2 = int(nr);
     if (r2 > nc) r2 = int(nc);
+    int zh = 0, zbig = 0;
+    Par sec;
+    if (sectors) {
+      TRG_REQUIRE(ra == k && cb == k && int64_t(kpar.size()) == k, "z2: sectors apply to the pure swap only");
+      // rows (kA, b_perp) and columns (f_perp, kB) carry the same parities
+      std::vector<const Par *> f{&kpar};
+      for (int a : perp) f.push_back(&c.z2_legs[a]);
+      const auto room = parity_counts(f);
+      if (r2 > room[0] + room[1]) r2 = int(room[0] + room[1]);
+      zh = int(std::min(room[0], room[1]));
+      zbig = room[0] >= room[1] ? 0 : 1;
+      sec.resize(size_t(r2));
+      for (int col = 0; col < r2; ++col) sec[size_t(col)] = int8_t(col < 2 * zh ? (col & 1) : zbig);
+    }
     auto zview = [&](int64_t cols) {  // rows (f_perp, kB)
       std::vector<std::pair<std::string, int64_t>> l;
       for (int a : perp) l.push_back({fn[a], dims[a]});
@@ -1059,6 +1420,24 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
       hipLaunchKernelGGL(trial_kernel, dim3(uint32_t((cnt + 255) / 256)), dim3(256), 0, st, Om, uint32_t(cnt),
                          uint32_t(n_step), stream, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32));
       TRG_HIP_CHECK(hipGetLastError());
+      if (sectors) {
+        // parity tables of the row legs (f_perp..., kB), packed
+        std::vector<int> &tab = c.z2_stage[1];
+        tab.clear();
+        ParSpec ps{};
+        auto add = [&](const Par &pv) {
+          ps.size[ps.nf] = int(pv.size());
+          ps.off[ps.nf] = int(tab.size());
+          for (int8_t x : pv) tab.push_back(x);
+          ++ps.nf;
+        };
+        for (int a : perp) add(c.z2_legs[a]);
+        add(kpar);
+        const int *pd = upload(c, tab, "zmask");
+        hipLaunchKernelGGL(z2_mask_kernel, dim3(uint32_t((cnt + 255) / 256)), dim3(256), 0, st, Om, nc, r2, pd, ps,
+                           zh, zbig);
+        TRG_HIP_CHECK(hipGetLastError());
+      }
     }
     dbg(c, "Om", Om, nc * r2);
     apply_M(Om, Yb);
@@ -1082,10 +1461,10 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
     double *sg = c.wsp<double>("swsig" + tag, size_t(dcx) * 8), *sqsig = c.wsp<double>("swsq", size_t(dcx) * 8);
     double *Wb = c.wsp<double>("swW", size_t(r2) * dcx * 8), *Zs = c.wsp<double>("swZs", size_t(r2) * dcx * 8);
     dbg(c, "Rb", Rb, int64_t(r2) * r2);
-    small_svd(c, RbT, r2, dcx, sg, sqsig, Wb, Zs, "sw");
+    small_svd(c, RbT, r2, dcx, sg, sqsig, Wb, Zs, "sw", sectors ? &sec : nullptr, &c.z2_stage[2]);
     dbg(c, "sigma", sg, dcx);
     SwapOut o{c.wsp<double>("Xs" + tag, size_t(nr) * dcx * 8), c.wsp<double>("Ys" + tag, size_t(nc) * dcx * 8), sg,
-              dcx};
+              dcx, sectors ? column_parities(c, Wb, r2, dcx, sec) : Par{}};
     double *tmp = c.wsp<double>("swtmp", size_t(nmax) * dcx * 8);
     einsum2(c, Qb, contiguous({{"i", nr}, {"j", r2}}), Wb, contiguous({{"j", r2}, {"l", dcx}}), tmp, {"i", "l"},
             TRG_FP64, "sx");
@@ -1099,7 +1478,7 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
   };
   dbg(c, "Ut", Ut, n * k);
   dbg(c, "Vt", Vt, n * k);
-  const SwapOut pure = partial_svd(Vt, vVA, k, Ut, vUB, k, 0u, "");
+  const SwapOut pure = partial_svd(Vt, vVA, k, Ut, vUB, k, 0u, "", c.z2);
   double *Xs = pure.Xs, *Ys = pure.Ys, *sig = pure.sig;
   const int dc = pure.dc;
   c.ensure(c.atrg_sigma, size_t(dc) * 8);
@@ -1230,14 +1609,29 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
               {"fa", "fb", "fa2", "fb2"}, TRG_FP64, "h4");
     }
   }
+  // Z2: the sector order of each Gram's pair index (both sides of an axis
+  // share it), for the orders beyond the Jacobi range
+  const int *gperm = nullptr;
+  std::vector<size_t> gperm_off(size_t(npp), 0);
+  if (c.z2 && nnmax > JACOBI_MAX_N) {
+    std::vector<int> &tab = c.z2_stage[3];
+    tab.clear();
+    for (int idx = 0; idx < npp; ++idx) {
+      const Par pp = pair_parity(c.z2_legs[perp[idx]], c.z2_legs[perp[idx]]);
+      gperm_off[size_t(idx)] = tab.size();
+      for (int side = 0; side < 2; ++side) append_sector_order(pp, tab);
+    }
+    gperm = upload(c, tab, "zgperm");
+  }
   if (same_n) {
     const int nn = dims[perp[0]] * dims[perp[0]];
-    eigh_batched(Gall, Wall, Vall, swall, nn, 2 * npp, st);
+    eigh_sectors(c, Gall, Wall, Vall, swall, nn, 2 * npp, gperm, "gram");
   } else {
     for (int idx = 0; idx < npp; ++idx) {
       const int nn = dims[perp[idx]] * dims[perp[idx]];
-      eigh_batched(Gall + size_t(2) * idx * nnmax * nnmax, Wall + size_t(2) * idx * nnmax,
-                   Vall + size_t(2) * idx * nnmax * nnmax, swall + 2 * idx, nn, 2, st);
+      eigh_sectors(c, Gall + size_t(2) * idx * nnmax * nnmax, Wall + size_t(2) * idx * nnmax,
+                   Vall + size_t(2) * idx * nnmax * nnmax, swall + 2 * idx, nn, 2,
+                   gperm ? gperm + gperm_off[size_t(idx)] : nullptr, "gram" + std::to_string(idx));
     }
   }
   for (int idx = 0; idx < npp; ++idx) {
@@ -1255,6 +1649,12 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
                  static_cast<double *>(c.spec[nu].ptr)};
     select_isometry(Wv, Vv, sw, nn, kn, c.force_side, degeneracy_window(producer_precision(c)), so, st);
   }
+  // Z2: parity of each new leg index (its isometry column lies in one sector)
+  Par new_legs[4];
+  if (c.z2)
+    for (int nu : perp)
+      new_legs[nu] = column_parities(c, static_cast<const double *>(c.U[nu].ptr), int64_t(dims[nu]) * dims[nu], nd[nu],
+                                     pair_parity(c.z2_legs[nu], c.z2_legs[nu]));
 
   dbg(c, "Wf", Wf, int64_t(dc) * dc);
   dbg(c, "Wb", Wbk, int64_t(dc) * dc);
@@ -1320,9 +1720,7 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
       }
       const View tv = contiguous(tl);
       double *dst = last ? Gn : c.wsp<double>("kG2" + std::to_string(j), size_t(view_count(tv)) * 8);
-      apply_map(src, IN_F64, cur, P(nu),
-                {{nm("bA", nu), int64_t(dims[nu]) * nd[nu]}, {nm("bB", nu), nd[nu]}, {nm("B", nu), 1}},
-                {nm("bA", nu), nm("bB", nu)}, dst, OUT_F64, 0, tv, st);
+      pair_contract(c, src, cur, nm("bA", nu), nm("bB", nu), P(nu), nm("B", nu), dst, tv);
       src = dst;
       cur = tv;
     }
@@ -1385,9 +1783,7 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
       }
       const View tv = contiguous(tl);
       double *dst = last ? Hn : c.wsp<double>("kG2" + std::to_string(j), size_t(view_count(tv)) * 8);
-      apply_map(src, IN_F64, cur, P(nu),
-                {{nm("fA", nu), int64_t(dims[nu]) * nd[nu]}, {nm("fB", nu), nd[nu]}, {nm("F", nu), 1}},
-                {nm("fA", nu), nm("fB", nu)}, dst, OUT_F64, 0, tv, st);
+      pair_contract(c, src, cur, nm("fA", nu), nm("fB", nu), P(nu), nm("F", nu), dst, tv);
       src = dst;
       cur = tv;
     }
@@ -1459,12 +1855,14 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
     double *HSn = c.wsp<double>("iH", size_t(nnew) * mcap * 8);
     double *gt = c.wsp<double>("iGt", size_t(nnew) * dcut * 8);
     // impurity on the lower site: M_1 = sum_j H_S[m, f_perp, j] Ut[j, b_perp, kB]
-    const SwapOut s1 = partial_svd(HS, rename(vHS, {{"kk", "kA"}, {fn[mu], "j"}}), m, Ut, vUB, k, 1u + 2u * kind, "i");
+    const SwapOut s1 =
+        partial_svd(HS, rename(vHS, {{"kk", "kA"}, {fn[mu], "j"}}), m, Ut, vUB, k, 1u + 2u * kind, "i", false);
     const int64_t d1 = s1.dc;
     gblock(GS, vGSA, m, s1.Xs, xview(m, d1), d1, gt);
     hblock(s1.Ys, yview(d1, k), k, Vt, vVB, d1, HSn);
     // impurity on the upper site: M_2 = sum_j Vt[kA, f_perp, j] G_S[j, b_perp, m]
-    const SwapOut s2 = partial_svd(Vt, vVA, k, GS, rename(vGS, {{"kk", "kB"}, {bn[mu], "j"}}), m, 2u + 2u * kind, "i");
+    const SwapOut s2 =
+        partial_svd(Vt, vVA, k, GS, rename(vGS, {{"kk", "kB"}, {bn[mu], "j"}}), m, 2u + 2u * kind, "i", false);
     const int64_t d2 = s2.dc, mn = d1 + d2;
     apply_map(gt, IN_F64, contiguous({{"b", nnew}, {"l", d1}}), nullptr, {}, {}, GSn, OUT_F64, 0,
               View{Leg{"b", nnew, mn}, Leg{"l", d1, 1}}, st);
@@ -1493,6 +1891,10 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
   for (int a = 0; a < d; ++a) c.dims[a] = nd[a];
   c.r = dc;
   c.nsteps = n_step;
+  if (c.z2) {
+    for (int nu : perp) c.z2_legs[nu] = new_legs[nu];
+    c.z2_bond = pure.par;
+  }
 }
 
 }  // namespace trg

@@ -125,6 +125,12 @@ struct trg_ctx {
   int imp_r[2] = {0, 0};  // ATRG: bond of impurity j's pieces S[j] (G_S) and Sn[j] (H_S)
   int r = 0;
   int atrg_nsig = 0;
+  // ATRG Z2 mode: parity (0 even, 1 odd) of every leg index of each axis and
+  // of every bond index; host staging of the parity tables a step uploads
+  // (kept here so that they outlive the asynchronous copies)
+  bool z2 = false;
+  std::vector<int8_t> z2_legs[4], z2_bond;
+  std::vector<int> z2_stage[4];
 
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> join_events;

@@ -170,6 +170,7 @@ jacobi_kernel(double *Aall, double *wall, double *Vall, int *sweeps_out, int n) 
 // matrix.  Deterministic (fixed order everywhere).
 constexpr int TQ_THREADS = 1024;
 constexpr int TQ_MAX = 1024;
+constexpr int TQ_CHUNK = 16;
 
 __device__ inline double tq_sum(double v, double *sh) {
   const int t = threadIdx.x;
@@ -230,10 +231,23 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
     const double K = 0.5 * tau * tq_sum(pv, sh);
     for (int j = t; j < m; j += TQ_THREADS) ww[j] -= K * vv[j];   // w = p - K v
     __syncthreads();
-    // A_sub <- A_sub - v w^T - w v^T
-    for (int idx = t; idx < m * m; idx += TQ_THREADS) {
-      const int i = idx / m, j = idx % m;
-      A[(k + 1 + i) * n + (k + 1 + j)] -= vv[i] * ww[j] + ww[i] * vv[j];
+    // A_sub <- A_sub - v w^T - w v^T (TQ_CHUNK independent elements per
+    // thread loaded before any is stored, so their loads overlap)
+    for (int base = t; base < m * m; base += TQ_THREADS * TQ_CHUNK) {
+      double a[TQ_CHUNK];
+#pragma unroll
+      for (int u = 0; u < TQ_CHUNK; ++u) {
+        const int idx = base + u * TQ_THREADS;
+        if (idx < m * m) a[u] = A[(k + 1 + idx / m) * n + (k + 1 + idx % m)];
+      }
+#pragma unroll
+      for (int u = 0; u < TQ_CHUNK; ++u) {
+        const int idx = base + u * TQ_THREADS;
+        if (idx < m * m) {
+          const int i = idx / m, j = idx % m;
+          A[(k + 1 + i) * n + (k + 1 + j)] = a[u] - (vv[i] * ww[j] + ww[i] * vv[j]);
+        }
+      }
     }
     for (int i = t; i < m; i += TQ_THREADS) {
       const double val = i == 0 ? alpha : 0.0;
@@ -262,9 +276,21 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
       ww[j] = acc;
     }
     __syncthreads();
-    for (int idx = t; idx < m * m; idx += TQ_THREADS) {
-      const int i = idx / m, j = idx % m;
-      A[(k + 1 + i) * n + (k + 1 + j)] -= vv[i] * ww[j];
+    for (int base = t; base < m * m; base += TQ_THREADS * TQ_CHUNK) {
+      double a[TQ_CHUNK];
+#pragma unroll
+      for (int u = 0; u < TQ_CHUNK; ++u) {
+        const int idx = base + u * TQ_THREADS;
+        if (idx < m * m) a[u] = A[(k + 1 + idx / m) * n + (k + 1 + idx % m)];
+      }
+#pragma unroll
+      for (int u = 0; u < TQ_CHUNK; ++u) {
+        const int idx = base + u * TQ_THREADS;
+        if (idx < m * m) {
+          const int i = idx / m, j = idx % m;
+          A[(k + 1 + i) * n + (k + 1 + j)] = a[u] - vv[i] * ww[j];
+        }
+      }
     }
     __syncthreads();
   }
@@ -346,19 +372,34 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
       if (done_flag) break;
       // rotations i = hi down to lo act on columns (i, i+1) of every row of
       // Q, i.e. on rows (i, i+1) of Z; the new entry i is carried in a
-      // register into the next rotation
+      // register into the next rotation.  Entries are read TQ_CHUNK at a
+      // time before any of them is written back (each rotation reads entry
+      // i and writes entry i + 1, so a chunk's reads all precede its
+      // writes), which keeps TQ_CHUNK loads in flight instead of one.
       const int lo = sweep_lo, hi = sweep_hi;
       if (hi >= lo) {
         for (int row = t; row < n; row += TQ_THREADS) {
           double *z = V + row;
-          double zi1 = z[size_t(hi + 1) * n];
-          for (int i = hi; i >= lo; --i) {
-            const double zi = z[size_t(i) * n];
-            const double f = zi1;
-            z[size_t(i + 1) * n] = rs[i] * zi + rc[i] * f;
-            zi1 = rc[i] * zi - rs[i] * f;
+          double carry = z[size_t(hi + 1) * n];
+          for (int i0 = hi; i0 >= lo; i0 -= TQ_CHUNK) {
+            const int cnt = i0 - lo + 1 < TQ_CHUNK ? i0 - lo + 1 : TQ_CHUNK;
+            double v[TQ_CHUNK];
+#pragma unroll
+            for (int u = 0; u < TQ_CHUNK; ++u)
+              if (u < cnt) v[u] = z[size_t(i0 - u) * n];
+#pragma unroll
+            for (int u = 0; u < TQ_CHUNK; ++u)
+              if (u < cnt) {
+                const int i = i0 - u;
+                const double zi = v[u], f = carry;
+                v[u] = rs[i] * zi + rc[i] * f;      // new entry i + 1
+                carry = rc[i] * zi - rs[i] * f;
+              }
+#pragma unroll
+            for (int u = 0; u < TQ_CHUNK; ++u)
+              if (u < cnt) z[size_t(i0 - u + 1) * n] = v[u];
           }
-          z[size_t(lo) * n] = zi1;
+          z[size_t(lo) * n] = carry;
         }
       }
       ++iter;
@@ -489,9 +530,8 @@ select_kernel(const double *w2, const double *V2, const int *sweeps2, int n, int
 
 }  // namespace
 
-// Jacobi up to order 160 (accurate, and cheap while the matrix is small),
-// tridiagonalisation + QL above.
-constexpr int JACOBI_MAX_N = 160;
+// Jacobi up to order JACOBI_MAX_N (accurate, and cheap while the matrix is
+// small), tridiagonalisation + QL above.
 
 void eigh_batched(double *A, double *w, double *V, int *sweeps, int n, int batch, hipStream_t st) {
   TRG_REQUIRE(n >= 1 && n <= MAX_N && batch >= 1, "eigh: order must be in [1, 1024]");

@@ -692,6 +692,7 @@ trg_ctx *new_ctx(int d, const trg_config *cfg) {
   if (cfg) c->cfg = *cfg;
   if (c->cfg.dcut <= 0) c->cfg.dcut = 8;
   c->st = static_cast<hipStream_t>(c->cfg.stream);
+  c->z2 = c->cfg.z2 != 0;
   return c;
 }
 
@@ -712,6 +713,8 @@ void validate_cfg(const trg_config *cfg, int d) {
   TRG_REQUIRE((cfg->impure & ~3u) == 0, "unknown impurity bits");
   TRG_REQUIRE(!cfg->alloc == !cfg->free, "alloc and free must be given together");
   TRG_REQUIRE(cfg->fp64_steps >= 0, "fp64_steps must be >= 0");
+  TRG_REQUIRE(cfg->z2 == 0 || cfg->z2 == 1, "z2 must be 0 or 1");
+  TRG_REQUIRE(!cfg->z2 || cfg->method == TRG_ATRG, "the Z2 mode is an ATRG mode");
 }
 
 // normalise the freshly written tensors: c_0 = ||T||, acc = ln c_0
@@ -775,6 +778,7 @@ int trg_init_ising(trg_ctx **out, double beta, double h, int d, const trg_config
     TRG_REQUIRE(!(imp & TRG_IMPURE_E) || beta > 0.0, "the energy impurity needs beta > 0");
     const bool atrg = cfg && cfg->method == TRG_ATRG;
     TRG_REQUIRE(!atrg || cfg->precision <= TRG_FP32, "ATRG supports FP64 and FP32 contractions");
+    TRG_REQUIRE(!(cfg && cfg->z2) || h == 0.0, "the Z2 mode needs h = 0 (the symmetric tensor)");
     c = new_ctx(d, cfg);
     for (int a = 0; a < d; ++a) c->dims[a] = 2;
     c->has_e = imp & TRG_IMPURE_E;
@@ -899,6 +903,7 @@ int trg_init_factors(trg_ctx **out, int d, const int *dims, int r, const double 
     validate_cfg(cfg, d);
     TRG_REQUIRE(cfg && cfg->method == TRG_ATRG, "factors need method TRG_ATRG");
     TRG_REQUIRE(cfg->impure == 0 && cfg->precision <= TRG_FP32, "unsupported ATRG configuration");
+    TRG_REQUIRE(!cfg->z2, "the Z2 mode starts from trg_init_ising (its parities are known there)");
     TRG_REQUIRE(r >= 1 && r <= 512, "rank out of range");
     int64_t n = 1;
     for (int a = 0; a < d; ++a) {
@@ -933,6 +938,49 @@ int trg_atrg_spectrum(trg_ctx *ctx, double *out, int cap, int *n) {
     if (out && ctx->atrg_nsig > 0) {
       TRG_REQUIRE(cap >= ctx->atrg_nsig, "capacity too small");
       TRG_HIP_CHECK(hipMemcpy(out, ctx->atrg_sigma.ptr, size_t(ctx->atrg_nsig) * 8, hipMemcpyDeviceToHost));
+    }
+    return TRG_OK;
+  });
+}
+
+int trg_atrg_parities(trg_ctx *ctx, int *legs_out, size_t cap_legs, int *bond_out, size_t cap_bond, int *r_out) {
+  if (!ctx) return fail(nullptr, TRG_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&]() -> int {
+    if (!ctx->z2) return fail(ctx, TRG_ESTATE, "not a Z2 context");
+    sync_check(*ctx);
+    if (r_out) *r_out = int(ctx->z2_bond.size());
+    size_t nl = 0;
+    for (int a = 0; a < ctx->d; ++a) nl += ctx->z2_legs[a].size();
+    if (legs_out) {
+      TRG_REQUIRE(cap_legs >= nl, "legs capacity too small");
+      size_t e = 0;
+      for (int a = 0; a < ctx->d; ++a)
+        for (int8_t x : ctx->z2_legs[a]) legs_out[e++] = x;
+    }
+    if (bond_out) {
+      TRG_REQUIRE(cap_bond >= ctx->z2_bond.size(), "bond capacity too small");
+      for (size_t i = 0; i < ctx->z2_bond.size(); ++i) bond_out[i] = ctx->z2_bond[i];
+    }
+    return TRG_OK;
+  });
+}
+
+int trg_get_factors(trg_ctx *ctx, double *host_G, size_t cap_G, double *host_H, size_t cap_H, int *r_out) {
+  if (!ctx) return fail(nullptr, TRG_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&]() -> int {
+    if (ctx->cfg.method != TRG_ATRG) return fail(ctx, TRG_ESTATE, "not an ATRG context");
+    sync_check(*ctx);
+    int64_t n = 1;
+    for (int a = 0; a < ctx->d; ++a) n *= ctx->dims[a];
+    const size_t cnt = size_t(n) * size_t(ctx->r);
+    if (r_out) *r_out = ctx->r;
+    if (host_G) {
+      TRG_REQUIRE(cap_G >= cnt, "G capacity too small");
+      TRG_HIP_CHECK(hipMemcpy(host_G, ctx->G.ptr, cnt * 8, hipMemcpyDeviceToHost));
+    }
+    if (host_H) {
+      TRG_REQUIRE(cap_H >= cnt, "H capacity too small");
+      TRG_HIP_CHECK(hipMemcpy(host_H, ctx->H.ptr, cnt * 8, hipMemcpyDeviceToHost));
     }
     return TRG_OK;
   });
@@ -1128,9 +1176,18 @@ struct StateHeader {
   int32_t d, method, precision, dcut, rsvd_p, rsvd_q, fp64_steps, nsteps, nimp, r, force_side;
   int32_t imp_kind[2], imp_r[2], dims[4];
   uint64_t seed, rec_bytes, nhost, ndoubles;
+  int32_t z2, pad;   // z2: the leg and bond parity bytes follow the tensors
 };
 constexpr char STATE_MAGIC[8] = {'T', 'R', 'G', 'S', 'T', 'A', 'T', 'E'};
-constexpr uint32_t STATE_VERSION = 1;
+constexpr uint32_t STATE_VERSION = 2;
+
+// bytes of the Z2 parity tables: every leg index of each axis, then the bond
+size_t z2_table_bytes(int z2, int d, const int32_t *dims, int r) {
+  if (!z2) return 0;
+  size_t n = size_t(r);
+  for (int a = 0; a < d; ++a) n += size_t(dims[a]);
+  return n;
+}
 
 // the device buffers of the state, in blob order, with their sizes in doubles
 std::vector<std::pair<void *, size_t>> state_tensors(trg_ctx &c) {
@@ -1162,8 +1219,11 @@ int trg_export_state(trg_ctx *ctx, void *host_buf, size_t cap, size_t *size) {
     size_t nd = 0;
     for (const auto &t : ten) nd += t.second;
     const size_t rec_bytes = size_t(ctx->nsteps + 1) * REC_BYTES;
+    int32_t dims32[4];
+    for (int a = 0; a < 4; ++a) dims32[a] = ctx->dims[a];
+    const size_t zb = z2_table_bytes(ctx->z2, ctx->d, dims32, ctx->r);
     const size_t total = sizeof(StateHeader) + 16 * 8 + rec_bytes + ctx->host_rec.size() * sizeof(trg_step_rec) +
-                         nd * 8;
+                         nd * 8 + zb;
     *size = total;
     if (!host_buf) return TRG_OK;
     TRG_REQUIRE(cap >= total, "state buffer too small");
@@ -1191,6 +1251,7 @@ int trg_export_state(trg_ctx *ctx, void *host_buf, size_t cap, size_t *size) {
     h.rec_bytes = rec_bytes;
     h.nhost = ctx->host_rec.size();
     h.ndoubles = nd;
+    h.z2 = ctx->z2 ? 1 : 0;
     char *p = static_cast<char *>(host_buf);
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
@@ -1203,6 +1264,16 @@ int trg_export_state(trg_ctx *ctx, void *host_buf, size_t cap, size_t *size) {
     for (const auto &t : ten) {
       TRG_HIP_CHECK(hipMemcpy(p, t.first, t.second * 8, hipMemcpyDeviceToHost));
       p += t.second * 8;
+    }
+    if (ctx->z2) {
+      for (int a = 0; a < ctx->d; ++a) {
+        TRG_REQUIRE(int(ctx->z2_legs[a].size()) == ctx->dims[a], "z2: leg parity table out of step");
+        std::memcpy(p, ctx->z2_legs[a].data(), ctx->z2_legs[a].size());
+        p += ctx->z2_legs[a].size();
+      }
+      TRG_REQUIRE(int(ctx->z2_bond.size()) == ctx->r, "z2: bond parity table out of step");
+      std::memcpy(p, ctx->z2_bond.data(), ctx->z2_bond.size());
+      p += ctx->z2_bond.size();
     }
     return TRG_OK;
   });
@@ -1221,7 +1292,10 @@ int trg_import_state(trg_ctx **out, const void *host_buf, size_t size, const trg
     TRG_REQUIRE(h.d >= 2 && h.d <= 4 && h.nsteps >= 0 && h.nimp >= 0 && h.nimp <= 2, "corrupt state header");
     TRG_REQUIRE(h.rec_bytes == size_t(h.nsteps + 1) * REC_BYTES, "corrupt state header (records)");
     for (int a = 0; a < h.d; ++a) TRG_REQUIRE(h.dims[a] >= 1 && h.dims[a] <= 1024, "corrupt state header (dims)");
-    const size_t need = sizeof(StateHeader) + 16 * 8 + h.rec_bytes + h.nhost * sizeof(trg_step_rec) + h.ndoubles * 8;
+    TRG_REQUIRE((h.z2 == 0 || h.z2 == 1) && (!h.z2 || h.method == TRG_ATRG), "corrupt state header (z2)");
+    TRG_REQUIRE(h.r >= 0 && h.r <= 4096, "corrupt state header (bond)");
+    const size_t need = sizeof(StateHeader) + 16 * 8 + h.rec_bytes + h.nhost * sizeof(trg_step_rec) +
+                        h.ndoubles * 8 + z2_table_bytes(h.z2, h.d, h.dims, h.r);
     TRG_REQUIRE(size == need, "state blob size does not match its header");
     // the blob fixes the numerics; cfg may bring the stream, allocator and
     // workspace budget
@@ -1234,6 +1308,7 @@ int trg_import_state(trg_ctx **out, const void *host_buf, size_t size, const trg
     k.rsvd_q = h.rsvd_q;
     k.fp64_steps = h.fp64_steps;
     k.seed = h.seed;
+    k.z2 = h.z2;
     validate_cfg(&k, h.d);
     c = new_ctx(h.d, &k);
     for (int a = 0; a < h.d; ++a) c->dims[a] = h.dims[a];
@@ -1298,6 +1373,16 @@ int trg_import_state(trg_ctx **out, const void *host_buf, size_t size, const trg
     for (const auto &t : state_tensors(*c)) {
       TRG_HIP_CHECK(hipMemcpy(t.first, p, t.second * 8, hipMemcpyHostToDevice));
       p += t.second * 8;
+    }
+    if (c->z2) {
+      auto table = [&](size_t n) {
+        std::vector<int8_t> v(reinterpret_cast<const int8_t *>(p), reinterpret_cast<const int8_t *>(p) + n);
+        for (int8_t x : v) TRG_REQUIRE(x == 0 || x == 1, "corrupt state blob (parity)");
+        p += n;
+        return v;
+      };
+      for (int a = 0; a < h.d; ++a) c->z2_legs[a] = table(size_t(h.dims[a]));
+      c->z2_bond = table(size_t(h.r));
     }
     return TRG_OK;
   });

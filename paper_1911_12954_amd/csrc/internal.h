@@ -107,6 +107,11 @@ void ising_init(double *T, double *SE, double *SM, int d, double beta, double h,
 
 // ------------------------------------------------------------- eigen ---
 // batched Jacobi: A (batch x n x n) overwritten; w, V sorted descending
+// Orders up to JACOBI_MAX_N use cyclic Jacobi (rotations only between
+// coupled indices, so exact zeros of A stay exact zeros); larger orders use
+// Householder tridiagonalisation + QL, which keeps a block-diagonal A block
+// diagonal only when each block's indices are contiguous.
+constexpr int JACOBI_MAX_N = 160;
 void eigh_batched(double *A, double *w, double *V, int *sweeps, int n, int batch, hipStream_t st);
 
 // isometry selection of one transverse axis from both sides' eigensystems

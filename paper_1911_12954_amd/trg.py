@@ -53,7 +53,7 @@ def _torch_allocator(stream_ptr):
 
 
 def make_config(precision="fp64", method="hotrg", dcut=8, impure=(), stream=None,
-                use_torch_allocator=True, workspace_bytes=0, rsvd_p=0, rsvd_q=0, seed=0, fp64_steps=0):
+                use_torch_allocator=True, workspace_bytes=0, rsvd_p=0, rsvd_q=0, seed=0, fp64_steps=0, z2=False):
     """Build a trg_config.  ``stream``: a torch.cuda.Stream, an int handle or
     None (torch's current stream when torch has a GPU, else the default)."""
     cfg = L.TrgConfig()
@@ -67,6 +67,7 @@ def make_config(precision="fp64", method="hotrg", dcut=8, impure=(), stream=None
     cfg.rsvd_p, cfg.rsvd_q, cfg.seed = int(rsvd_p), int(rsvd_q), int(seed)
     cfg.workspace_bytes = int(workspace_bytes)
     cfg.fp64_steps = int(fp64_steps)
+    cfg.z2 = 1 if z2 else 0
     keep = []
     sp = None
     try:
@@ -207,6 +208,35 @@ class Context:
         _err(_lib().trg_atrg_spectrum(self.handle, out.ctypes.data_as(C.POINTER(C.c_double)), out.size,
                                       C.byref(n)), self.handle)
         return out[: n.value]
+
+    def atrg_parities(self):
+        """trg_atrg_parities: (per-axis leg parity arrays, bond parity array)
+        of a Z2-mode ATRG context."""
+        dims, _ = self.dims()
+        ip = C.POINTER(C.c_int)
+        r = C.c_int()
+        _err(_lib().trg_atrg_parities(self.handle, None, 0, None, 0, C.byref(r)), self.handle)
+        legs = np.zeros(max(sum(dims), 1), dtype=np.int32)
+        bond = np.zeros(max(r.value, 1), dtype=np.int32)
+        _err(_lib().trg_atrg_parities(self.handle, legs.ctypes.data_as(ip), legs.size, bond.ctypes.data_as(ip),
+                                      bond.size, None), self.handle)
+        out, o = [], 0
+        for n in dims:
+            out.append(legs[o:o + n].copy())
+            o += n
+        return out, bond[: r.value].copy()
+
+    def factors(self):
+        """trg_get_factors: the ATRG pieces G [b0..b_{d-1}, l] and H [l, f0..f_{d-1}]."""
+        dims, _ = self.dims()
+        r = C.c_int()
+        _err(_lib().trg_get_factors(self.handle, None, 0, None, 0, C.byref(r)), self.handle)
+        G = np.empty(tuple(dims) + (r.value,))
+        H = np.empty((r.value,) + tuple(dims))
+        dp = C.POINTER(C.c_double)
+        _err(_lib().trg_get_factors(self.handle, G.ctypes.data_as(dp), G.size, H.ctypes.data_as(dp), H.size, None),
+             self.handle)
+        return G, H
 
     def set_profiling(self, on=True):
         _err(_lib().trg_set_profiling(self.handle, 1 if on else 0), self.handle)

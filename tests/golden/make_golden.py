@@ -1,8 +1,8 @@
 """Write oracle_values.json: HOTRG and ATRG results of the FP64 oracle for
 small, fully specified runs, used as stored expected values by the GPU tests.
 
-Run from the repository root:  python tests/golden/make_golden.py
-Calls nothing but `oracle/`."""
+Run from the repository root:  python tests/golden/make_golden.py [case ...]
+(no case: all of them).  Calls nothing but `oracle/`."""
 import json
 import os
 import sys
@@ -22,32 +22,47 @@ CASES = [
 
 
 ATRG_CASES = [
-    # (name, beta, h, d, dcut, L, seed); p = 4 dcut, q = 2 dcut
-    ("atrg_4d_dcut4_L4_h1e-3", 0.1497, 1e-3, 4, 4, 4, 5),
-    ("atrg_2d_dcut8_L64_h1e-2", 0.4000, 1e-2, 2, 8, 64, 1),
+    # (name, beta, h, d, dcut, L, seed, z2); p = 4 dcut, q = 2 dcut
+    ("atrg_4d_dcut4_L4_h1e-3", 0.1497, 1e-3, 4, 4, 4, 5, False),
+    ("atrg_2d_dcut8_L64_h1e-2", 0.4000, 1e-2, 2, 8, 64, 1, False),
+    ("atrg_z2_4d_dcut6_L1024_b0.2", 0.2000, 0.0, 4, 6, 1024, 0, True),
 ]
 
 
-def main():
-    out = {"source": "oracle/hotrg.py run(beta, h, d, dcut, L, impure=True) and oracle/atrg.py "
-                     "run(beta, h, d, dcut, L, seed=seed, impure=True), FP64", "cases": {}}
+def main(names):
+    """Recompute the named cases (all when none is named) and merge them
+    into the stored file."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_values.json")
+    out = {"cases": {}}
+    if os.path.exists(path):
+        with open(path) as f:
+            out = json.load(f)
+    out["source"] = ("oracle/hotrg.py run(beta, h, d, dcut, L, impure=True) and oracle/atrg.py "
+                     "run(beta, h, d, dcut, L, seed=seed, impure=True, z2=z2), FP64")
     for name, beta, h, d, dcut, L in CASES:
+        if names and name not in names:
+            continue
         r = hotrg.run(beta, h, d, dcut, L, impure=True)
         out["cases"][name] = {"beta": beta, "h": h, "d": d, "dcut": dcut, "L": L,
                               "ln_z_per_site": repr(r.ln_z_per_site), "energy": repr(r.energy),
                               "magnetization": repr(r.magnetization)}
         print(name, out["cases"][name], flush=True)
-    for name, beta, h, d, dcut, L, seed in ATRG_CASES:
-        r = atrg.run(beta, h, d, dcut, L, seed=seed, impure=True)
-        out["cases"][name] = {"method": "atrg", "beta": beta, "h": h, "d": d, "dcut": dcut, "L": L, "seed": seed,
-                              "ln_z_per_site": repr(r.ln_z_per_site), "energy": repr(r.energy),
-                              "magnetization": repr(r.magnetization)}
+    for name, beta, h, d, dcut, L, seed, z2 in ATRG_CASES:
+        if names and name not in names:
+            continue
+        r = atrg.run(beta, h, d, dcut, L, seed=seed, impure=True, z2=z2)
+        case = {"method": "atrg", "beta": beta, "h": h, "d": d, "dcut": dcut, "L": L, "seed": seed,
+                "ln_z_per_site": repr(r.ln_z_per_site), "energy": repr(r.energy),
+                "magnetization": repr(r.magnetization)}
+        if z2:
+            case["z2"] = True
+            case["x"] = repr(atrg.indicator_x(r.G, r.H, 0))
+        out["cases"][name] = case
         print(name, out["cases"][name], flush=True)
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_values.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])

@@ -139,3 +139,25 @@ def test_more_argument_checks_on_the_host(lib):
     assert lib.trg_eigh(C.byref(one), C.byref(one), C.byref(one), C.byref(iv), 2000, 1, None) == L.TRG_EINVAL
     dims = (C.c_int * 4)(2, 2, 2, 2)
     assert lib.trg_init_factors(C.byref(h), 4, dims, 2, None, None, None) == L.TRG_EINVAL
+
+
+def test_z2_mode_argument_checks_on_the_host(lib):
+    """The Z2 mode is an ATRG mode for the h = 0 tensor built by
+    trg_init_ising; everything else is refused before device work."""
+    h = C.c_void_p()
+    cfg = L.TrgConfig()
+    cfg.z2 = 1                                   # HOTRG
+    assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
+    assert b"ATRG" in lib.trg_last_error(None)
+    cfg.method = L.TRG_ATRG
+    assert lib.trg_init_ising(C.byref(h), 0.1, 1e-5, 4, C.byref(cfg)) == L.TRG_EINVAL
+    assert b"h = 0" in lib.trg_last_error(None)
+    cfg.z2 = 2
+    assert lib.trg_init_ising(C.byref(h), 0.1, 0.0, 4, C.byref(cfg)) == L.TRG_EINVAL
+    cfg.z2 = 1
+    dims = (C.c_int * 2)(2, 2)
+    g = (C.c_double * 8)()
+    assert lib.trg_init_factors(C.byref(h), 2, dims, 2, g, g, C.byref(cfg)) == L.TRG_EINVAL
+    assert b"trg_init_ising" in lib.trg_last_error(None)
+    assert lib.trg_atrg_parities(None, None, 0, None, 0, None) == L.TRG_EINVAL
+    assert lib.trg_get_factors(None, None, 0, None, 0, None) == L.TRG_EINVAL

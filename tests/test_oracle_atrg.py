@@ -2,7 +2,9 @@
 known answers, exactness against brute-force spin sums when nothing is
 truncated, RSVD against a dense SVD, the p,q-independence the paper reports,
 and Onsager's solution on a large 2D lattice."""
+import json
 import math
+import os
 import warnings
 
 import numpy as np
@@ -255,6 +257,13 @@ def test_z2_mode_keeps_the_symmetric_fixed_point_in_4d():
     assert abs(atrg.indicator_x(z.G, z.H, 0) - 2.0) < 1e-10
     assert abs(plain.magnetization) > 1e-6
     assert abs(z.ln_z_per_site - plain.ln_z_per_site) < 1e-10 * abs(plain.ln_z_per_site)
+    # the stored values of this run (tests/golden) are still the oracle's
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_values.json")) as f:
+        c = json.load(f)["cases"]["atrg_z2_4d_dcut6_L1024_b0.2"]
+    assert (c["beta"], c["h"], c["d"], c["dcut"], c["L"], c["seed"], c["z2"]) == (0.2, 0.0, 4, 6, 1024, 0, True)
+    assert z.ln_z_per_site == pytest.approx(float(c["ln_z_per_site"]), rel=1e-12, abs=0)
+    assert z.energy == pytest.approx(float(c["energy"]), rel=1e-10, abs=0)
+    assert abs(float(c["magnetization"])) < 1e-12
 
 
 def test_z2_mode_disordered_phase_gives_x_one():
