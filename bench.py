@@ -103,7 +103,7 @@ def parse():
     p.add_argument("--serve-budget-gb", type=float, default=200.0)
     p.add_argument("--tc-bisect", default=None,
                    help="instead of timing: 'd,dcut,steps,beta_lo,beta_hi,tol[,method]' bisection of the "
-                        "transition on the degeneracy indicator X (FP64; method hotrg or atrg)")
+                        "transition on the degeneracy indicator X (FP64; method hotrg, atrg or atrg-z2)")
     p.add_argument("--atrg-study", default=None,
                    help="instead of timing: 'dcuts;pq_dcut;hotrg_dcut' (e.g. '8,12,16,20,24;16;8'): ATRG f at "
                         "T = 6.65035, L = 1024 for each Dcut, the RSVD (p, q) study at pq_dcut and the ratio to "
@@ -569,11 +569,13 @@ def main():
         fields = a.tc_bisect.split(",")
         d, dcut, steps, blo, bhi, tol = fields[:6]
         method = fields[6] if len(fields) > 6 else "hotrg"
+        z2 = method == "atrg-z2"
+        run_method = "atrg" if z2 else method
         d, dcut, steps, blo, bhi, tol = int(d), int(dcut), int(steps), float(blo), float(bhi), float(tol)
         t0 = time.perf_counter()
 
         def ev(beta):
-            x = indicator_after(beta, d, dcut, steps, method=method)
+            x = indicator_after(beta, d, dcut, steps, method=run_method, z2=z2)
             progress(f"tc-bisect: beta {beta:.8f} X {x:.6f} at {time.perf_counter() - t0:.1f} s")
             return x
 

@@ -197,31 +197,33 @@ chol_inv_kernel(const double *C, int n, double shift_coef, double *R, double *Ri
 
 // The same factorisation for n <= 128, with the matrix in registers: wave w
 // (of four) owns the rows p = w (mod 4) and lane l the columns l and l + 64,
-// so thread (w, l) holds the 32 x 2 elements (w + 4 pp, l + 64 qq).  Whether
-// a thread holds row p is a property of its wave, so every row test below is
-// uniform across the wave and costs a scalar branch, not a lane mask.
-// Column j of the elimination: the wave owning row j publishes it in LDS,
-// every thread reads the pivot (a pivot at or below the dead tolerance makes
-// the row zero and its pivot 1) and updates its elements of the trailing
-// triangle, A[p][q] -= R[j][p] R[j][q]; two barriers per column.  The scaled
-// rows of R are kept in LDS (packed upper triangle) for the inverse, which
-// runs the same way from the last row up: row k of X = R^-1 is final once
-// every row below it has been eliminated, is scaled by 1 / R[k][k] and
-// published, and the rows above subtract R[p][k] X[k][q].
+// so thread (w, l) holds the 32 x 2 elements (w + 4 pp, l + 64 qq).
+// Column j of the elimination: the wave owning row j takes the pivot from
+// the lane holding the diagonal, scales the row (a pivot at or below the
+// dead tolerance makes the row zero and its pivot 1) and publishes it as a
+// 128-entry LDS row that is zero outside j < q < n; after one barrier every
+// thread subtracts R[j][p] R[j][q] from all its elements, which leaves the
+// rows at or above j unchanged (their entry of the published row is zero).
+// The published row alternates between two buffers, so one barrier per
+// column suffices: a buffer is written again only after the next barrier.
+// R is also kept transposed in LDS (zero below its diagonal) for the
+// inverse, which runs the same way from the last row up: row k of
+// X = R^-1 is final once every row below it has been eliminated, is scaled
+// by 1 / R[k][k] and published, and every thread subtracts R[p][k] X[k][q].
+// All LDS reads are unconditional, so they go out together.
 constexpr int CHOL_REG_MAX = 128;
 constexpr int CHOL_THREADS = 256;
-
-__device__ inline int chol_packed(int p, int q, int n) { return p * n - (p * (p - 1)) / 2 + (q - p); }
+constexpr int CHOL_RT_LD = CHOL_REG_MAX + 1;   // row stride of R^T in LDS (lanes write a column)
 
 __global__ void __launch_bounds__(CHOL_THREADS)
 chol_inv_reg_kernel(const double *C, int n, double shift_coef, double *Rg, double *Rinv, int *err) {
-  extern __shared__ double Rl[];   // packed upper triangle of R, n (n + 1) / 2
+  extern __shared__ double RT[];   // CHOL_REG_MAX x CHOL_RT_LD: RT[q][p] = R[p][q] for p < q, else 0
   __shared__ double sh[CHOL_THREADS];
   __shared__ double shm[CHOL_THREADS];
-  __shared__ double rowv[CHOL_REG_MAX];
+  __shared__ double row[2][CHOL_REG_MAX];
   __shared__ double pivs[CHOL_REG_MAX];
   __shared__ int dead[CHOL_REG_MAX];
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
   double tr = 0.0, mx = 0.0;
   for (int i = t; i < n; i += CHOL_THREADS) {
     tr += C[i * n + i];
@@ -229,6 +231,7 @@ chol_inv_reg_kernel(const double *C, int n, double shift_coef, double *Rg, doubl
   }
   sh[t] = tr;
   shm[t] = mx;
+  for (int i = t; i < CHOL_REG_MAX * CHOL_RT_LD; i += CHOL_THREADS) RT[i] = 0.0;
   __syncthreads();
   for (int s = CHOL_THREADS / 2; s > 0; s >>= 1) {
     if (t < s) {
@@ -248,90 +251,84 @@ chol_inv_reg_kernel(const double *C, int n, double shift_coef, double *Rg, doubl
       E[pp][qq] = (p <= q && q < n) ? C[p * n + q] + (p == q ? shift : 0.0) : 0.0;
     }
   for (int j = 0; j < n; ++j) {
+    double *rj = row[j & 1];
     if (w == (j & 3)) {
       const int pj = j >> 2;
+      double r0 = 0.0, r1 = 0.0;
 #pragma unroll
       for (int pp = 0; pp < 32; ++pp)
         if (pp == pj) {
-#pragma unroll
-          for (int qq = 0; qq < 2; ++qq) {
-            const int q = l + 64 * qq;
-            if (q >= j && q < n) rowv[q] = E[pp][qq];
-          }
+          r0 = E[pp][0];
+          r1 = E[pp][1];
         }
-    }
-    __syncthreads();
-    const double dj = rowv[j];
-    const bool isdead = !(dj > tol);
-    const double piv = isdead ? 1.0 : sqrt(dj);
-    const double inv = isdead ? 0.0 : 1.0 / piv;
-    if (t == 0) {
-      pivs[j] = piv;
-      dead[j] = isdead ? 1 : 0;
-      if (isdead && !isfinite(dj)) *err |= 4;
-      Rl[chol_packed(j, j, n)] = piv;
-    }
-    for (int q = j + 1 + t; q < n; q += CHOL_THREADS) Rl[chol_packed(j, q, n)] = rowv[q] * inv;
-    double rq[2];
-#pragma unroll
-    for (int qq = 0; qq < 2; ++qq) {
-      const int q = l + 64 * qq;
-      rq[qq] = (q > j && q < n) ? rowv[q] * inv : 0.0;
-    }
-#pragma unroll
-    for (int pp = 0; pp < 32; ++pp) {
-      const int p = w + 4 * pp;
-      if (p > j && p < n) {
-        const double rp = rowv[p] * inv;
-#pragma unroll
-        for (int qq = 0; qq < 2; ++qq) E[pp][qq] -= rp * rq[qq];
+      const double mine = (j >> 6) ? r1 : r0;
+      const int lo = __builtin_amdgcn_readlane(int(__double_as_longlong(mine)), j & 63);
+      const int hi = __builtin_amdgcn_readlane(int(__double_as_longlong(mine) >> 32), j & 63);
+      const double dj = __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+      const bool isdead = !(dj > tol);
+      const double piv = isdead ? 1.0 : sqrt(dj);
+      const double inv = isdead ? 0.0 : 1.0 / piv;
+      const double v0 = (l > j && l < n) ? r0 * inv : 0.0;
+      const double v1 = (l + 64 > j && l + 64 < n) ? r1 * inv : 0.0;
+      rj[l] = v0;
+      rj[l + 64] = v1;
+      if (l > j && l < n) RT[l * CHOL_RT_LD + j] = v0;
+      if (l + 64 > j && l + 64 < n) RT[(l + 64) * CHOL_RT_LD + j] = v1;
+      if (l == (j & 63)) {
+        pivs[j] = piv;
+        dead[j] = isdead ? 1 : 0;
+        if (isdead && !isfinite(dj)) *err |= 4;
       }
     }
     __syncthreads();
+    double rq[2], rv[32];
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) rq[qq] = rj[l + 64 * qq];
+#pragma unroll
+    for (int pp = 0; pp < 32; ++pp) rv[pp] = rj[w + 4 * pp];
+#pragma unroll
+    for (int pp = 0; pp < 32; ++pp)
+#pragma unroll
+      for (int qq = 0; qq < 2; ++qq) E[pp][qq] -= rv[pp] * rq[qq];
   }
+  __syncthreads();
   // X = R^-1 in the same registers
 #pragma unroll
   for (int pp = 0; pp < 32; ++pp)
 #pragma unroll
-    for (int qq = 0; qq < 2; ++qq) E[pp][qq] = (w + 4 * pp == l + 64 * qq) ? 1.0 : 0.0;
+    for (int qq = 0; qq < 2; ++qq) {
+      const int p = w + 4 * pp, q = l + 64 * qq;
+      E[pp][qq] = (p == q && q < n) ? 1.0 : 0.0;
+    }
   for (int k = n - 1; k >= 0; --k) {
+    double *xk = row[k & 1];
     if (w == (k & 3)) {
       const int pk = k >> 2;
       const double ik = 1.0 / pivs[k];
 #pragma unroll
       for (int pp = 0; pp < 32; ++pp)
         if (pp == pk) {
-#pragma unroll
-          for (int qq = 0; qq < 2; ++qq) {
-            const int q = l + 64 * qq;
-            if (q >= k && q < n) {
-              E[pp][qq] *= ik;
-              rowv[q] = E[pp][qq];
-            }
-          }
+          E[pp][0] *= ik;
+          E[pp][1] *= ik;
+          xk[l] = E[pp][0];
+          xk[l + 64] = E[pp][1];
         }
     }
     __syncthreads();
-    double xq[2];
+    double xq[2], rv[32];
 #pragma unroll
-    for (int qq = 0; qq < 2; ++qq) {
-      const int q = l + 64 * qq;
-      xq[qq] = (q >= k && q < n) ? rowv[q] : 0.0;
-    }
+    for (int qq = 0; qq < 2; ++qq) xq[qq] = xk[l + 64 * qq];
 #pragma unroll
-    for (int pp = 0; pp < 32; ++pp) {
-      const int p = w + 4 * pp;
-      if (p < k) {
-        const double rpk = Rl[chol_packed(p, k, n)];
+    for (int pp = 0; pp < 32; ++pp) rv[pp] = RT[k * CHOL_RT_LD + w + 4 * pp];
 #pragma unroll
-        for (int qq = 0; qq < 2; ++qq) E[pp][qq] -= rpk * xq[qq];
-      }
-    }
-    __syncthreads();
+    for (int pp = 0; pp < 32; ++pp)
+#pragma unroll
+      for (int qq = 0; qq < 2; ++qq) E[pp][qq] -= rv[pp] * xq[qq];
   }
+  __syncthreads();
   for (int i = t; i < n * n; i += CHOL_THREADS) {
     const int r = i / n, c = i % n;
-    Rg[i] = (r <= c && !dead[r]) ? Rl[chol_packed(r, c, n)] : 0.0;
+    Rg[i] = (r <= c && !dead[r]) ? (r == c ? pivs[r] : RT[c * CHOL_RT_LD + r]) : 0.0;
   }
 #pragma unroll
   for (int pp = 0; pp < 32; ++pp)
@@ -345,12 +342,11 @@ chol_inv_reg_kernel(const double *C, int n, double shift_coef, double *Rg, doubl
 void launch_chol_inv(const double *C, int n, double shift, double *R, double *Rinv, int *err, hipStream_t st) {
   TRG_REQUIRE(n >= 1 && n <= 1024, "chol: bad order");
   if (n <= CHOL_REG_MAX) {
-    const size_t lds = size_t(n) * (n + 1) / 2 * 8;   // packed R for the inverse
+    const size_t lds = size_t(CHOL_REG_MAX) * CHOL_RT_LD * 8;   // R^T for the inverse
     static bool attr = false;
     if (!attr) {
       TRG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&chol_inv_reg_kernel),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        CHOL_REG_MAX * (CHOL_REG_MAX + 1) / 2 * 8));
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
       attr = true;
     }
     hipLaunchKernelGGL(chol_inv_reg_kernel, dim3(1), dim3(CHOL_THREADS), lds, st, C, n, shift, R, Rinv, err);

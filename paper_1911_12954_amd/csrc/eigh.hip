@@ -185,10 +185,44 @@ __device__ inline double tq_sum(double v, double *sh) {
   return r;
 }
 
+// out[j] = sum_i v[i] B[i][j] for the m x m block B (row stride ld) of a
+// matrix in global memory, j < m: column j is summed by one thread, or by
+// two (the upper and the lower half of the rows, added through w2) when 2 m
+// fits the workgroup; loads go out eight at a time so that several are in
+// flight per thread.  Ends with a barrier.
+__device__ inline void tq_colvec(const double *B, int ld, int m, const double *v, double *out, double *w2, int t) {
+  const bool split = 2 * m <= TQ_THREADS;
+  const int half = split ? t / (TQ_THREADS / 2) : 0;
+  const int j0 = split ? t % (TQ_THREADS / 2) : t;
+  const int stride = split ? TQ_THREADS / 2 : TQ_THREADS;
+  const int i0 = split ? half * (m / 2) : 0, i1 = split ? (half ? m : m / 2) : m;
+  for (int j = j0; j < m; j += stride) {
+    double a0 = 0.0, a1 = 0.0;
+    int i = i0;
+    for (; i + 8 <= i1; i += 8) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = B[size_t(i + u) * ld + j];
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        a0 += x[u] * v[i + u];
+        a1 += x[u + 1] * v[i + u + 1];
+      }
+    }
+    for (; i < i1; ++i) a0 += B[size_t(i) * ld + j] * v[i];
+    if (half) w2[j] = a0 + a1;
+    else out[j] = a0 + a1;
+  }
+  __syncthreads();
+  if (split)
+    for (int j = t; j < m; j += TQ_THREADS) out[j] += w2[j];
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(TQ_THREADS)
 tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) {
   __shared__ double sh[TQ_THREADS];
-  __shared__ double vv[TQ_MAX], ww[TQ_MAX];
+  __shared__ double vv[TQ_MAX], ww[TQ_MAX], w2[TQ_MAX];
   __shared__ double dd[TQ_MAX], ee[TQ_MAX];
   __shared__ double rc[TQ_MAX], rs[TQ_MAX];
   __shared__ int rank[TQ_MAX];
@@ -220,11 +254,8 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
     if (!(vtv > 0.0)) continue;          // column already reduced: H = I
     const double tau = 2.0 / vtv;
     // p = tau A_sub v  (A symmetric: column access, coalesced across threads)
-    for (int j = t; j < m; j += TQ_THREADS) {
-      double acc = 0.0;
-      for (int i = 0; i < m; ++i) acc += A[(k + 1 + i) * n + (k + 1 + j)] * vv[i];
-      ww[j] = tau * acc;
-    }
+    tq_colvec(A + (k + 1) * n + (k + 1), n, m, vv, ww, w2, t);
+    for (int j = t; j < m; j += TQ_THREADS) ww[j] *= tau;
     __syncthreads();
     double pv = 0.0;
     for (int i = t; i < m; i += TQ_THREADS) pv += ww[i] * vv[i];
@@ -270,11 +301,7 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
     for (int i = t; i < m; i += TQ_THREADS) vv[i] = V[(k + 1 + i) * n + k];
     __syncthreads();
     // ww[j] = sum_i u_i Q[k+1+i][k+1+j]; then Q_sub -= u ww^T
-    for (int j = t; j < m; j += TQ_THREADS) {
-      double acc = 0.0;
-      for (int i = 0; i < m; ++i) acc += vv[i] * A[(k + 1 + i) * n + (k + 1 + j)];
-      ww[j] = acc;
-    }
+    tq_colvec(A + (k + 1) * n + (k + 1), n, m, vv, ww, w2, t);
     __syncthreads();
     for (int base = t; base < m * m; base += TQ_THREADS * TQ_CHUNK) {
       double a[TQ_CHUNK];
@@ -321,6 +348,14 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
   for (int l = 0; l < n; ++l) {
     int iter = 0;
     while (true) {
+      // Thread 0's sweep is one dependent chain of FP64 operations per
+      // rotation, so each Givens rotation takes r, c, s from one reciprocal
+      // square root refined by two Newton steps (y <- y (3 - x y^2) / 2
+      // doubles the correct bits of the hardware estimate) instead of hypot
+      // and two divisions.  The matrices diagonalised here (Grams of
+      // normalised tensors, singular-value blocks) have entries of order one
+      // or below, far from overflow; an f^2 + g^2 that underflows to zero is
+      // the zero rotation, as r = 0 was.
       if (t == 0) {
         int mm = l;
         for (; mm < n - 1; ++mm) {
@@ -340,16 +375,21 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
           bool underflow = false;
           for (; i >= l; --i) {
             const double f = s * ee[i], bb = c * ee[i];
-            r = hypot(f, g);
-            ee[i + 1] = r;
-            if (r == 0.0) {
+            const double x = fma(f, f, g * g);
+            if (x == 0.0) {
+              ee[i + 1] = 0.0;
               dd[i + 1] -= p;
               ee[mm] = 0.0;
               underflow = true;
               break;
             }
-            s = f / r;
-            c = g / r;
+            double y = __builtin_amdgcn_rsq(x);
+            y = y * fma(-0.5 * x * y, y, 1.5);
+            y = y * fma(-0.5 * x * y, y, 1.5);
+            r = x * y;
+            ee[i + 1] = r;
+            s = f * y;
+            c = g * y;
             g = dd[i + 1] - p;
             r = (dd[i] - g) * s + 2.0 * c * bb;
             p = s * r;

@@ -17,11 +17,13 @@ class Bisection:
 
 
 def indicator_after(beta: float, d: int, dcut: int, steps: int, precision: str = "fp64", axis: int = 0,
-                    h: float = 0.0, method: str = "hotrg") -> float:
+                    h: float = 0.0, method: str = "hotrg", z2: bool = False) -> float:
     """X of the tensor after `steps` HOTRG (or ATRG) steps (axes cycled
-    from 0)."""
+    from 0); `z2` runs ATRG in its Z2 mode (h = 0), which keeps the ordered
+    phase's symmetric fixed point (X -> 2) that a plain randomized swap
+    loses over many steps."""
     from .trg import trg_init_ising
-    ctx = trg_init_ising(beta, h, d, dcut=dcut, precision=precision, method=method)
+    ctx = trg_init_ising(beta, h, d, dcut=dcut, precision=precision, method=method, z2=z2)
     try:
         for n in range(steps):
             if method == "atrg":
@@ -35,11 +37,11 @@ def indicator_after(beta: float, d: int, dcut: int, steps: int, precision: str =
 
 def bisect_transition(d: int, dcut: int, beta_lo: float, beta_hi: float, steps: int, tol: float,
                       precision: str = "fp64", threshold: float = 1.5, evaluate=None,
-                      method: str = "hotrg") -> Bisection:
+                      method: str = "hotrg", z2: bool = False) -> Bisection:
     """Halve [beta_lo, beta_hi] until it is narrower than `tol`, keeping X
     below `threshold` at beta_lo and above it at beta_hi.  `evaluate(beta)`
     replaces the GPU run (tests)."""
-    ev = evaluate or (lambda b: indicator_after(b, d, dcut, steps, precision, method=method))
+    ev = evaluate or (lambda b: indicator_after(b, d, dcut, steps, precision, method=method, z2=z2))
     out = Bisection(beta_lo, beta_hi)
     x_lo, x_hi = ev(beta_lo), ev(beta_hi)
     out.evaluations += [(beta_lo, x_lo), (beta_hi, x_hi)]
