@@ -106,7 +106,8 @@ typedef struct trg_step_rec {
   int side[4];            /* per transverse axis: 0 backward, 1 forward pair; -1 on axis */
   int kept[4];            /* kept columns k_nu; 0 on the coarse-grained axis */
   int degenerate_cut[4];  /* 1 if the cut splits a degenerate eigenspace */
-  int sweeps[4];          /* Jacobi sweeps used (chosen side) */
+  int sweeps[4];          /* chosen side: Jacobi sweeps (order <= 160), else the
+                             number of eigenvectors computed */
   int join_precision;     /* TRG_FP64 / TRG_FP32 / TRG_BF16X3 / TRG_BF16X6 of this step's join */
   double ln_c;            /* ln of the Frobenius norm c_n of the new tensor */
   double eps[4][2];       /* discarded eigenvalue sum, [axis][backward, forward] */
@@ -360,6 +361,24 @@ int trg_gemm_tile(int precision, int *tile_m, int *tile_n, int *tile_k);
  * columns of V[b*n*n ...] (row-major, column j belongs to w[j]).  A is
  * overwritten.  sweeps[b] receives the sweeps used (-1: not converged). */
 int trg_eigh(double *A, double *w, double *V, int *sweeps, int n, int batch, void *stream);
+
+/* The eigensolver of the isometry selection (Sec. 2: HOSVD of HOTRG and
+ * ATRG keeps the eigenvectors of the largest eigenvalues of each Gram
+ * matrix): for each of `batch` symmetric matrices of order n (layout as
+ * trg_eigh) every eigenvalue in descending order, and eigenvectors only for
+ * the leading kk indices, kk = k extended while the next eigenvalue is within
+ * cluster_rel * w[0] of the previous one (a near-degenerate cluster that the
+ * cut at k splits); columns kk.. of V are zero and sweeps[b] receives kk.
+ * Orders up to 160 use the Jacobi solver of trg_eigh instead (every vector,
+ * sweeps[b] the sweeps used); larger ones Householder reduction, bisection
+ * for the eigenvalues and inverse iteration for the vectors.  A is overwritten.  work: device
+ * memory of trg_eigh_top_work_bytes(n, batch) bytes (may be NULL when n <=
+ * 160), owned by the caller, not kept.  Asynchronous on `stream`.  Errors:
+ * TRG_EINVAL (n outside 1..1024, k < 1, batch < 1, cluster_rel outside
+ * [0, 1), a NULL pointer). */
+int trg_eigh_top(double *A, double *w, double *V, int *sweeps, int n, int batch, int k, double cluster_rel,
+                 void *work, void *stream);
+size_t trg_eigh_top_work_bytes(int n, int batch);
 
 /* ---- diagnostics ----
  * Time the join GEMM launches of a context with HIP events on its stream

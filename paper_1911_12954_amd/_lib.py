@@ -92,6 +92,9 @@ SIGNATURES = {
                            C.c_longlong, C.c_longlong, C.c_longlong, C.c_longlong, C.c_int, C.c_void_p]),
     "trg_gemm_tile": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "trg_eigh": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+    "trg_eigh_top": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                               C.c_double, C.c_void_p, C.c_void_p]),
+    "trg_eigh_top_work_bytes": (C.c_size_t, [C.c_int, C.c_int]),
     "trg_set_profiling": (C.c_int, [C.c_void_p, C.c_int]),
     "trg_join_profile": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                                    C.POINTER(C.c_double)]),

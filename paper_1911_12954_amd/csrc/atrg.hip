@@ -358,59 +358,89 @@ void launch_chol_inv(const double *C, int n, double shift, double *R, double *Ri
 
 // Gram matrix C = Y^T Y of a tall m x k row-major matrix (k <= 128) on FP64
 // MFMA, read in place: workgroup b sums the rows [b rpw, (b+1) rpw) into its
-// own 128 x 128 slab part[b] (columns beyond k are zero), four waves of
-// 64 x 64; rows are staged through LDS 32 at a time (row stride 144 doubles:
-// the four rows a k-step reads fall on disjoint halves of the banks).  The
-// slabs are then summed in a fixed order, so the result is deterministic.
-// v_mfma_f64_16x16x4: lane (g, r16) supplies A[r16][g] = Y[row g][col r16]
-// and B[r16][g] likewise; accumulator e of the lane is C[g + 4e][r16].
+// own 128 x 128 slab part[b]; the slabs are then summed in a fixed order, so
+// the result is deterministic.  Only the nb (nb + 1) / 2 blocks of 16 x 16
+// on and above the diagonal are computed (nb = ceil(k / 16)), dealt round
+// robin to the four waves; each block is written to the slab together with
+// its transpose.  Rows are staged through LDS 32 at a time, double-buffered:
+// the next chunk is loaded into registers while the current one is
+// multiplied, and stored to the other buffer after it (one barrier per
+// chunk; a buffer is refilled only after every wave passed the barrier that
+// ended its last use).  Row stride 144 doubles: the four rows a k-step reads
+// fall on the two halves of the banks.  v_mfma_f64_16x16x4: lane (g, r16)
+// supplies A[r16][g] = Y[row g][col r16] and B[g][r16] likewise; accumulator
+// e of the lane is C[g + 4e][r16].
 constexpr int TSG_K = 128, TSG_ROWS = 32, TSG_LD = 144;
+constexpr int TSG_MAXB = 9;   // blocks per wave: ceil(36 / 4)
+
 typedef double tsg_v4d __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256)
 ts_gram_kernel(const double *__restrict__ Y, int64_t m, int k, int64_t rpw, double *__restrict__ part) {
-  __shared__ double L[TSG_ROWS * TSG_LD];
+  __shared__ double L[2][TSG_ROWS * TSG_LD];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int g = lane >> 4, r16 = lane & 15;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int nb = (k + 15) / 16;
+  int bi[TSG_MAXB], bj[TSG_MAXB], nmine = 0;
+#pragma unroll
+  for (int q = 0; q < TSG_MAXB; ++q) bi[q] = bj[q] = 0;
+  for (int i = 0, e = 0; i < nb; ++i)
+    for (int j = i; j < nb; ++j, ++e)
+      if ((e & 3) == wave && nmine < TSG_MAXB) {
+        bi[nmine] = i;
+        bj[nmine] = j;
+        ++nmine;
+      }
   const int64_t r0 = int64_t(blockIdx.x) * rpw;
   const int64_t r1 = r0 + rpw < m ? r0 + rpw : m;
-  tsg_v4d acc[4][4];
+  const int nch = r1 > r0 ? int((r1 - r0 + TSG_ROWS - 1) / TSG_ROWS) : 0;
+  constexpr int PER = TSG_ROWS * TSG_K / 256;   // values per thread per chunk
+  double pre[PER];
+  auto gload = [&](int ch) {
+    const int64_t base = r0 + int64_t(ch) * TSG_ROWS;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = tsg_v4d{0.0, 0.0, 0.0, 0.0};
-  for (int64_t base = r0; base < r1; base += TSG_ROWS) {
-    const int64_t rows = r1 - base < TSG_ROWS ? r1 - base : TSG_ROWS;
-    for (int idx = t; idx < TSG_ROWS * TSG_K; idx += 256) {
-      const int r = idx / TSG_K, c = idx % TSG_K;
-      L[r * TSG_LD + c] = (r < rows && c < k) ? Y[(base + r) * k + c] : 0.0;
+    for (int u = 0; u < PER; ++u) {
+      const int idx = t + 256 * u, r = idx / TSG_K, col = idx % TSG_K;
+      pre[u] = (base + r < r1 && col < k) ? Y[(base + r) * k + col] : 0.0;
     }
-    __syncthreads();
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = t + 256 * u, r = idx / TSG_K, col = idx % TSG_K;
+      L[buf][r * TSG_LD + col] = pre[u];
+    }
+  };
+  tsg_v4d acc[TSG_MAXB];
+#pragma unroll
+  for (int q = 0; q < TSG_MAXB; ++q) acc[q] = tsg_v4d{0.0, 0.0, 0.0, 0.0};
+  if (nch > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    if (ch + 1 < nch) gload(ch + 1);
+    const double *Lb = L[ch & 1];
 #pragma unroll
     for (int s = 0; s < TSG_ROWS / 4; ++s) {
-      const double *row = L + (4 * s + g) * TSG_LD;
-      double a[4], b[4];
+      const double *row = Lb + (4 * s + g) * TSG_LD + r16;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = row[64 * wm + 16 * i + r16];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = row[64 * wn + 16 * j + r16];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int q = 0; q < TSG_MAXB; ++q)
+        if (q < nmine) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * bi[q]], row[16 * bj[q]], acc[q], 0, 0, 0);
     }
+    if (ch + 1 < nch) sstore((ch + 1) & 1);
     __syncthreads();
   }
   double *out = part + size_t(blockIdx.x) * TSG_K * TSG_K;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
+  for (int q = 0; q < TSG_MAXB; ++q)
+    if (q < nmine)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = 64 * wm + 16 * i + g + 4 * e, col = 64 * wn + 16 * j + r16;
-        out[row * TSG_K + col] = acc[i][j][e];
+        const int row = 16 * bi[q] + g + 4 * e, col = 16 * bj[q] + r16;
+        out[row * TSG_K + col] = acc[q][e];
+        out[col * TSG_K + row] = acc[q][e];
       }
 }
 
@@ -870,7 +900,8 @@ void cholqr3(trg_ctx &c, const double *Y, int64_t m, int k, double *Q, double *R
   const double u = std::ldexp(1.0, -53);
   const double *src = Y;
   const bool tsg = k <= TSG_K;
-  const int64_t tsg_rows = std::max<int64_t>(TSG_ROWS, (m + 255) / 256);   // about 256 workgroups
+  // about 512 workgroups (two per CU), each a whole number of 32-row chunks
+  const int64_t tsg_rows = std::max<int64_t>(TSG_ROWS, ((m + 511) / 512 + TSG_ROWS - 1) / TSG_ROWS * TSG_ROWS);
   const int64_t tsg_wg = (m + tsg_rows - 1) / tsg_rows;
   double *part = tsg ? c.wsp<double>("qrP" + tag, size_t(tsg_wg) * TSG_K * TSG_K * 8) : nullptr;
   for (int pass = 0; pass < 3; ++pass) {
@@ -961,15 +992,17 @@ int *upload(trg_ctx &c, const std::vector<int> &v, const std::string &tag) {
   return d;
 }
 
-// eigh_batched of `batch` symmetric n x n matrices whose indices fall into
-// two parity sectors, with perm (device, n entries per matrix) the sector
-// order of each: Jacobi keeps sectors apart by itself; above its range the
-// matrices are diagonalised in sector order and the eigenvector rows put
-// back.  perm == nullptr: plain eigh_batched.
-void eigh_sectors(trg_ctx &c, double *A, double *w, double *V, int *sw, int n, int batch, const int *perm,
-                  const std::string &tag) {
+// eigh_top_batched (every eigenvalue, the leading eigenvectors: k, extended
+// over a cluster that the cut splits) of `batch` symmetric n x n matrices
+// whose indices may fall into two parity sectors, with perm (device, n
+// entries per matrix) the sector order of each: Jacobi keeps sectors apart
+// by itself; above its range the matrices are diagonalised in sector order
+// and the eigenvector rows put back.  perm == nullptr: no reordering.
+void eigh_sectors(trg_ctx &c, double *A, double *w, double *V, int *sw, int n, int batch, const int *perm, int k,
+                  double cluster_rel, const std::string &tag) {
+  double *work = n > JACOBI_MAX_N ? c.wsp<double>("ztop" + tag, eigh_top_work_doubles(n, batch) * 8) : nullptr;
   if (!perm || n <= JACOBI_MAX_N) {
-    eigh_batched(A, w, V, sw, n, batch, c.st);
+    eigh_top_batched(A, w, V, sw, n, batch, k, cluster_rel, work, c.st);
     return;
   }
   double *As = c.wsp<double>("zA" + tag, size_t(batch) * n * n * 8);
@@ -977,7 +1010,7 @@ void eigh_sectors(trg_ctx &c, double *A, double *w, double *V, int *sw, int n, i
   const dim3 grid(uint32_t((int64_t(n) * n + 255) / 256), uint32_t(batch));
   hipLaunchKernelGGL(gather_sym_kernel, grid, dim3(256), 0, c.st, A, As, perm, n);
   TRG_HIP_CHECK(hipGetLastError());
-  eigh_batched(As, w, Vs, sw, n, batch, c.st);
+  eigh_top_batched(As, w, Vs, sw, n, batch, k, cluster_rel, work, c.st);
   hipLaunchKernelGGL(scatter_rows_kernel, grid, dim3(256), 0, c.st, Vs, V, perm, n);
   TRG_HIP_CHECK(hipGetLastError());
 }
@@ -1005,7 +1038,7 @@ void small_svd(trg_ctx &c, const double *Cm, int k, int kk, double *s, double *s
     append_sector_order(jp, *stage);
     perm = upload(c, *stage, "svdperm" + tag);
   }
-  eigh_sectors(c, J, w, V, sw, m, 1, perm, "svd" + tag);
+  eigh_sectors(c, J, w, V, sw, m, 1, perm, kk, 0.0, "svd" + tag);
   hipLaunchKernelGGL(jw_extract_kernel, dim3(1), dim3(256), 0, c.st, w, V, k, kk, s, sqs, W, Z);
   TRG_HIP_CHECK(hipGetLastError());
 }
@@ -1621,14 +1654,22 @@ void atrg_step_impl(trg_ctx &c, int mu, int dcut) {
   }
   if (same_n) {
     const int nn = dims[perp[0]] * dims[perp[0]];
-    eigh_sectors(c, Gall, Wall, Vall, swall, nn, 2 * npp, gperm, "gram");
+    eigh_sectors(c, Gall, Wall, Vall, swall, nn, 2 * npp, gperm, nd[perp[0]], degeneracy_window(producer_precision(c)),
+                 "gram");
   } else {
     for (int idx = 0; idx < npp; ++idx) {
       const int nn = dims[perp[idx]] * dims[perp[idx]];
       eigh_sectors(c, Gall + size_t(2) * idx * nnmax * nnmax, Wall + size_t(2) * idx * nnmax,
                    Vall + size_t(2) * idx * nnmax * nnmax, swall + 2 * idx, nn, 2,
-                   gperm ? gperm + gperm_off[size_t(idx)] : nullptr, "gram" + std::to_string(idx));
+                   gperm ? gperm + gperm_off[size_t(idx)] : nullptr, nd[perp[idx]],
+                   degeneracy_window(producer_precision(c)), "gram" + std::to_string(idx));
     }
+  }
+  for (int idx = 0; idx < 2 * npp; ++idx) {
+    const int nn = dims[perp[idx / 2]] * dims[perp[idx / 2]];
+    const size_t stride = same_n ? size_t(nn) : size_t(nnmax);
+    dbg(c, "gram w", Wall + idx * stride, nn);
+    dbg(c, "gram V", Vall + idx * stride * stride, int64_t(nn) * nn);
   }
   for (int idx = 0; idx < npp; ++idx) {
     const int nu = perp[idx];

@@ -172,6 +172,19 @@ constexpr int TQ_THREADS = 1024;
 constexpr int TQ_MAX = 1024;
 constexpr int TQ_CHUNK = 16;
 
+__device__ inline double tq_max(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = TQ_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
 __device__ inline double tq_sum(double v, double *sh) {
   const int t = threadIdx.x;
   sh[t] = v;
@@ -219,28 +232,35 @@ __device__ inline void tq_colvec(const double *B, int ld, int m, const double *v
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(TQ_THREADS)
-tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) {
-  __shared__ double sh[TQ_THREADS];
-  __shared__ double vv[TQ_MAX], ww[TQ_MAX], w2[TQ_MAX];
-  __shared__ double dd[TQ_MAX], ee[TQ_MAX];
-  __shared__ double rc[TQ_MAX], rs[TQ_MAX];
-  __shared__ int rank[TQ_MAX];
-  __shared__ int sweep_lo, sweep_hi, done_flag, iters_total;
-  const int b = blockIdx.x;
-  double *A = Aall + size_t(b) * n * n;
-  double *V = Vall + size_t(b) * n * n;   // Householder vectors, then Q, then eigenvectors
-  double *w = wall + size_t(b) * n;
+// Householder reduction of the symmetric n x n matrix A (global memory) to
+// tridiagonal form, diagonal in dd and subdiagonal in ee (LDS); reflector k
+// is left in column k of V (rows k+1..n-1), scaled so that H_k = I - u u^T.
+// A is overwritten.  Every thread of the workgroup calls it.
+__device__ void tq_tridiagonalise(double *A, double *V, int n, double *sh, double *vv, double *ww, double *w2,
+                                  double *dd, double *ee) {
   const int t = threadIdx.x;
-
-  // ---- Householder tridiagonalisation; v_k stored in column k of V (rows k+1..n-1)
   for (int i = t; i < n * n; i += TQ_THREADS) V[i] = 0.0;
   __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;              // length of the column below the diagonal
-    double s2 = 0.0;
+    // The reflector is built from the column scaled by a power of two that
+    // brings its largest entry into [1, 2): H = I - 2 v v^T / v^T v does not
+    // depend on the scale of v, and sums of squares of columns far below
+    // the matrix's scale (a parity block of a Gram whose weights are
+    // 1e-150 of the other block's) neither underflow nor make tau overflow.
+    double amax = 0.0;
     for (int i = t; i < m; i += TQ_THREADS) {
       const double x = A[(k + 1 + i) * n + k];
+      vv[i] = x;
+      amax = fmax(amax, fabs(x));
+    }
+    amax = tq_max(amax, sh);
+    if (amax == 0.0) continue;           // column already reduced: H = I
+    int ex;
+    (void)frexp(amax, &ex);
+    double s2 = 0.0;
+    for (int i = t; i < m; i += TQ_THREADS) {
+      const double x = ldexp(vv[i], -ex);
       vv[i] = x;
       s2 += x * x;
     }
@@ -281,7 +301,7 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
       }
     }
     for (int i = t; i < m; i += TQ_THREADS) {
-      const double val = i == 0 ? alpha : 0.0;
+      const double val = i == 0 ? ldexp(alpha, ex) : 0.0;
       A[(k + 1 + i) * n + k] = val;
       A[k * n + (k + 1 + i)] = val;
       V[(k + 1 + i) * n + k] = vv[i] * sqrt(tau);   // scaled: H = I - u u^T
@@ -293,6 +313,24 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
     ee[i] = i + 1 < n ? A[(i + 1) * n + i] : 0.0;
   }
   __syncthreads();
+}
+
+__global__ void __launch_bounds__(TQ_THREADS)
+tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) {
+  __shared__ double sh[TQ_THREADS];
+  __shared__ double vv[TQ_MAX], ww[TQ_MAX], w2[TQ_MAX];
+  __shared__ double dd[TQ_MAX], ee[TQ_MAX];
+  __shared__ double rc[TQ_MAX], rs[TQ_MAX];
+  __shared__ int rank[TQ_MAX];
+  __shared__ int sweep_lo, sweep_hi, done_flag, iters_total;
+  const int b = blockIdx.x;
+  double *A = Aall + size_t(b) * n * n;
+  double *V = Vall + size_t(b) * n * n;   // Householder vectors, then Q, then eigenvectors
+  double *w = wall + size_t(b) * n;
+  const int t = threadIdx.x;
+
+  // ---- Householder tridiagonalisation; v_k stored in column k of V (rows k+1..n-1)
+  tq_tridiagonalise(A, V, n, sh, vv, ww, w2, dd, ee);
   // ---- Q = H_0 H_1 ... H_{n-3}, built backwards in A (Q_k = H_k Q_{k+1})
   for (int i = t; i < n * n; i += TQ_THREADS) A[i] = (i / n == i % n) ? 1.0 : 0.0;
   __syncthreads();
@@ -352,10 +390,9 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
       // rotation, so each Givens rotation takes r, c, s from one reciprocal
       // square root refined by two Newton steps (y <- y (3 - x y^2) / 2
       // doubles the correct bits of the hardware estimate) instead of hypot
-      // and two divisions.  The matrices diagonalised here (Grams of
-      // normalised tensors, singular-value blocks) have entries of order one
-      // or below, far from overflow; an f^2 + g^2 that underflows to zero is
-      // the zero rotation, as r = 0 was.
+      // and two divisions; f and g are first scaled by the power of two that
+      // brings the larger into [1, 2), so that f^2 + g^2 neither underflows
+      // nor overflows (f = g = 0 is the zero rotation).
       if (t == 0) {
         int mm = l;
         for (; mm < n - 1; ++mm) {
@@ -375,21 +412,25 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
           bool underflow = false;
           for (; i >= l; --i) {
             const double f = s * ee[i], bb = c * ee[i];
-            const double x = fma(f, f, g * g);
-            if (x == 0.0) {
+            const double a = fmax(fabs(f), fabs(g));
+            if (a == 0.0) {
               ee[i + 1] = 0.0;
               dd[i + 1] -= p;
               ee[mm] = 0.0;
               underflow = true;
               break;
             }
+            int ex;
+            (void)frexp(a, &ex);
+            const double fs = ldexp(f, -ex), gs = ldexp(g, -ex);
+            const double x = fma(fs, fs, gs * gs);   // in [1/4, 2)
             double y = __builtin_amdgcn_rsq(x);
             y = y * fma(-0.5 * x * y, y, 1.5);
             y = y * fma(-0.5 * x * y, y, 1.5);
-            r = x * y;
+            r = ldexp(x * y, ex);
             ee[i + 1] = r;
-            s = f * y;
-            c = g * y;
+            s = fs * y;
+            c = gs * y;
             g = dd[i + 1] - p;
             r = (dd[i] - g) * s + 2.0 * c * bb;
             p = s * r;
@@ -463,6 +504,270 @@ tridiag_ql_kernel(double *Aall, double *wall, double *Vall, int *status, int n) 
   }
   __syncthreads();
   for (int i = t; i < n * n; i += TQ_THREADS) V[i] = A[i];
+}
+
+// ------------------------------------------ leading eigenpairs (large n) ---
+// The isometry selection needs every eigenvalue (the discarded weight, the
+// degenerate-cut flag, the spectrum record) but the eigenvectors only of the
+// kept indices and of the rest of a cluster of near-degenerate eigenvalues
+// that the cut splits.  tridiag_top_kernel computes exactly that, with no
+// serial QL sweeps and no n x n rotation accumulation:
+//   1. Householder reduction to tridiagonal T (as for the full solver);
+//   2. T splits into blocks where an off-diagonal is negligible against its
+//      neighbours or exactly zero (as between the parity sectors of a
+//      sector-ordered matrix); every eigenvalue of every block by bisection
+//      on Sturm counts, one thread per eigenvalue, then sorted descending;
+//   3. the number kk of vectors needed: k, extended while the next
+//      eigenvalue continues a cluster (gap <= cluster_rel * lambda_max);
+//   4. each needed eigenvector of its block by inverse iteration: LU with
+//      partial pivoting of T_b - lambda I (pivots below eps ||T_b|| raised to
+//      that size), three solves from a fixed start vector, each followed by
+//      Gram-Schmidt against the block's earlier vectors and normalisation;
+//      one wave per block, vectors in descending order (Wilkinson, The
+//      Algebraic Eigenvalue Problem, 1965, ch. 5 and 9);
+//   5. back-transformation by the reflectors, one wave per vector;
+//   6. V gets the kk vectors as its leading columns (zeros elsewhere), w
+//      every eigenvalue, status the number of vectors computed.
+// work: per matrix 2 n^2 + TOP_WAVES * 6 n doubles (reflectors row by row,
+// the vectors, each wave's LU factors and iterate).
+constexpr int TOP_THREADS = 1024;
+constexpr int TOP_WAVES = TOP_THREADS / 64;
+constexpr int TOP_ITERS = 3;
+
+__device__ inline double top_wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// fixed start vector of inverse iteration: entries in [-1, 1) from a hash of
+// the vector's rank and the entry's index
+__device__ inline double top_start(int r, int i) {
+  uint32_t x = uint32_t(r) * 0x9E3779B1u ^ (uint32_t(i) + 0x7F4A7C15u) * 0x85EBCA77u;
+  x ^= x >> 15;
+  x *= 0x2C1B3C6Du;
+  x ^= x >> 12;
+  x *= 0x297A2D39u;
+  x ^= x >> 15;
+  return double(x) * (2.0 / 4294967296.0) - 1.0;
+}
+
+__global__ void __launch_bounds__(TOP_THREADS)
+tridiag_top_kernel(double *Aall, double *wall, double *Vall, int *status, int n, int k, double cluster_rel,
+                   double *workall) {
+  __shared__ double sh[TOP_THREADS];
+  __shared__ double vv[TQ_MAX], ww[TQ_MAX], w2[TQ_MAX];
+  __shared__ double dd[TQ_MAX], ee[TQ_MAX];
+  __shared__ int blk_of[TQ_MAX], bstart[TQ_MAX + 1], slot_of[TQ_MAX];
+  __shared__ int nblk_s, kk_s;
+  double *lam = vv, *ee2 = w2;   // reused once the reduction is done
+  const int b = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  double *A = Aall + size_t(b) * n * n;
+  double *V = Vall + size_t(b) * n * n;
+  double *w = wall + size_t(b) * n;
+  double *work = workall + size_t(b) * (size_t(2) * n * n + size_t(TOP_WAVES) * 6 * n);
+  double *Ur = work;                          // reflector j in row j (entries of rows j+1..n-1)
+  double *Zv = work + size_t(n) * n;          // vector of rank r in row r
+  double *scr = work + size_t(2) * n * n + size_t(wave) * 6 * n;
+  const double eps = 2.220446049250313e-16;
+
+  // ---- 1. tridiagonal T; reflectors out of V's columns into rows of Ur
+  tq_tridiagonalise(A, V, n, sh, vv, ww, w2, dd, ee);
+  for (int idx = t; idx < n * n; idx += TOP_THREADS) {
+    const int j = idx / n, i = idx % n;
+    Ur[idx] = (i < n - j - 1) ? V[size_t(j + 1 + i) * n + j] : 0.0;
+    Zv[idx] = 0.0;
+  }
+  __syncthreads();
+  // ---- 2. blocks, bisection
+  if (t == 0) {
+    int nb = 0;
+    bstart[0] = 0;
+    for (int i = 0; i + 1 < n; ++i) {
+      const double lim = eps * sqrt(fabs(dd[i])) * sqrt(fabs(dd[i + 1]));
+      if (ee[i] == 0.0 || fabs(ee[i]) <= lim) {
+        ee[i] = 0.0;
+        bstart[++nb] = i + 1;
+      }
+    }
+    bstart[++nb] = n;
+    nblk_s = nb;
+  }
+  __syncthreads();
+  const int nblk = nblk_s;
+  for (int i = t; i < n; i += TOP_THREADS) {
+    int lo = 0, hi = nblk;   // bstart[lo] <= i < bstart[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (bstart[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    blk_of[i] = lo;
+    ee2[i] = ee[i] * ee[i];
+  }
+  __syncthreads();
+  for (int slot = t; slot < n; slot += TOP_THREADS) {
+    const int bb = blk_of[slot], s0 = bstart[bb], e0 = bstart[bb + 1];
+    const int target = e0 - slot;   // (slot - s0 + 1)-th largest = target-th smallest
+    double lo = 0.0, hi = 0.0, emax2 = 0.0;
+    for (int i = s0; i < e0; ++i) {
+      const double r = (i > s0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < e0 ? fabs(ee[i]) : 0.0);
+      lo = i == s0 ? dd[i] - r : fmin(lo, dd[i] - r);
+      hi = i == s0 ? dd[i] + r : fmax(hi, dd[i] + r);
+      if (i + 1 < e0) emax2 = fmax(emax2, ee2[i]);
+    }
+    const double bn = fmax(fabs(lo), fabs(hi));
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+    lo -= 2.0 * eps * bn + pivmin;
+    hi += 2.0 * eps * bn + pivmin;
+    for (int it = 0; it < 120; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (!(mid > lo && mid < hi) || hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+      // Sturm count: eigenvalues of the block below mid
+      int cnt = 0;
+      double q = dd[s0] - mid;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+      for (int i = s0 + 1; i < e0; ++i) {
+        q = (dd[i] - mid) - ee2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+      }
+      if (cnt >= target) hi = mid;
+      else lo = mid;
+    }
+    lam[slot] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  // ---- sort descending (ties by slot)
+  for (int slot = t; slot < n; slot += TOP_THREADS) {
+    const double v = lam[slot];
+    int rk = 0;
+    for (int u = 0; u < n; ++u) rk += (lam[u] > v) || (lam[u] == v && u < slot);
+    w[rk] = v;
+    slot_of[rk] = slot;
+  }
+  __syncthreads();
+  // ---- 3. vectors needed
+  if (t == 0) {
+    const double tol = cluster_rel * fmax(w[0], 0.0);
+    int bnd = k < n ? k : n;
+    while (bnd < n && w[bnd - 1] - w[bnd] <= tol) ++bnd;
+    kk_s = bnd;
+  }
+  __syncthreads();
+  const int kk = kk_s;
+  // ---- 4. inverse iteration, one wave per block
+  double *DL = scr, *D = scr + n, *DU = scr + 2 * n, *DU2 = scr + 3 * n, *PV = scr + 4 * n, *X = scr + 5 * n;
+  for (int bb = wave; bb < nblk; bb += TOP_WAVES) {
+    const int s0 = bstart[bb], e0 = bstart[bb + 1], nb = e0 - s0;
+    double bnorm = 0.0;
+    for (int i = s0 + lane; i < e0; i += 64)
+      bnorm = fmax(bnorm, fabs(dd[i]) + (i > s0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < e0 ? fabs(ee[i]) : 0.0));
+    for (int off = 32; off > 0; off >>= 1) bnorm = fmax(bnorm, __shfl_xor(bnorm, off, 64));
+    const double ptol = fmax(eps * bnorm, 2.2250738585072014e-308);
+    for (int r = 0; r < kk; ++r) {
+      const int slot = slot_of[r];
+      if (slot < s0 || slot >= e0) continue;   // uniform: every lane reads the same slot
+      const double sigma = w[r];
+      if (lane == 0) {
+        // LU with partial pivoting of T_b - sigma I (rows i, i+1 swapped where PV[i] = 1)
+        for (int i = 0; i < nb; ++i) {
+          D[i] = dd[s0 + i] - sigma;
+          DL[i] = i + 1 < nb ? ee[s0 + i] : 0.0;
+          DU[i] = DL[i];
+          DU2[i] = 0.0;
+        }
+        for (int i = 0; i + 1 < nb; ++i) {
+          if (fabs(D[i]) >= fabs(DL[i])) {
+            PV[i] = 0.0;
+            const double f = D[i] != 0.0 ? DL[i] / D[i] : 0.0;
+            DL[i] = f;
+            D[i + 1] -= f * DU[i];
+          } else {
+            PV[i] = 1.0;
+            const double f = D[i] / DL[i];
+            D[i] = DL[i];
+            DL[i] = f;
+            const double tmp = DU[i];
+            DU[i] = D[i + 1];
+            D[i + 1] = tmp - f * D[i + 1];
+            if (i + 2 < nb) {
+              DU2[i] = DU[i + 1];
+              DU[i + 1] = -f * DU[i + 1];
+            }
+          }
+        }
+      }
+      for (int i = lane; i < nb; i += 64) X[i] = top_start(r, i);
+      __builtin_amdgcn_wave_barrier();
+      __threadfence_block();
+      for (int it = 0; it < TOP_ITERS; ++it) {
+        if (lane == 0) {
+          for (int i = 0; i + 1 < nb; ++i) {
+            if (PV[i] == 0.0) {
+              X[i + 1] -= DL[i] * X[i];
+            } else {
+              const double tmp = X[i];
+              X[i] = X[i + 1];
+              X[i + 1] = tmp - DL[i] * X[i];
+            }
+          }
+          for (int i = nb - 1; i >= 0; --i) {
+            double piv = D[i];
+            if (fabs(piv) < ptol) piv = piv >= 0.0 ? ptol : -ptol;
+            double v = X[i];
+            if (i + 1 < nb) v -= DU[i] * X[i + 1];
+            if (i + 2 < nb) v -= DU2[i] * X[i + 2];
+            X[i] = v / piv;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __threadfence_block();
+        // Gram-Schmidt against the block's earlier vectors, then normalise
+        for (int r2 = 0; r2 < r; ++r2) {
+          const int sl2 = slot_of[r2];
+          if (sl2 < s0 || sl2 >= e0) continue;
+          const double *z = Zv + size_t(r2) * n + s0;
+          double dot = 0.0;
+          for (int i = lane; i < nb; i += 64) dot += z[i] * X[i];
+          dot = top_wave_sum(dot);
+          for (int i = lane; i < nb; i += 64) X[i] -= dot * z[i];
+        }
+        double nrm = 0.0;
+        for (int i = lane; i < nb; i += 64) nrm += X[i] * X[i];
+        nrm = top_wave_sum(nrm);
+        const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+        for (int i = lane; i < nb; i += 64) X[i] *= inv;
+        __builtin_amdgcn_wave_barrier();
+        __threadfence_block();
+      }
+      for (int i = lane; i < nb; i += 64) Zv[size_t(r) * n + s0 + i] = X[i];
+      __builtin_amdgcn_wave_barrier();
+      __threadfence_block();
+    }
+  }
+  __syncthreads();
+  // ---- 5. back-transformation z <- H_0 ... H_{n-3} z, one wave per vector
+  for (int r = wave; r < kk; r += TOP_WAVES) {
+    double *z = Zv + size_t(r) * n;
+    for (int j = n - 3; j >= 0; --j) {
+      const int m = n - j - 1;
+      const double *u = Ur + size_t(j) * n;
+      double dot = 0.0;
+      for (int i = lane; i < m; i += 64) dot += u[i] * z[j + 1 + i];
+      dot = top_wave_sum(dot);
+      if (dot != 0.0)
+        for (int i = lane; i < m; i += 64) z[j + 1 + i] -= u[i] * dot;
+    }
+  }
+  __syncthreads();
+  // ---- 6. output
+  for (int idx = t; idx < n * n; idx += TOP_THREADS) {
+    const int i = idx / n, c = idx % n;
+    V[idx] = c < kk ? Zv[size_t(c) * n + i] : 0.0;
+  }
+  if (t == 0) status[b] = kk;
 }
 
 // ------------------------------------------------------------- selection ---
@@ -579,6 +884,23 @@ void eigh_batched(double *A, double *w, double *V, int *sweeps, int n, int batch
     hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(EIGH_THREADS), 0, st, A, w, V, sweeps, n);
   else
     hipLaunchKernelGGL(tridiag_ql_kernel, dim3(batch), dim3(TQ_THREADS), 0, st, A, w, V, sweeps, n);
+  TRG_HIP_CHECK(hipGetLastError());
+}
+
+size_t eigh_top_work_doubles(int n, int batch) {
+  return size_t(batch) * (size_t(2) * n * n + size_t(TOP_WAVES) * 6 * n);
+}
+
+void eigh_top_batched(double *A, double *w, double *V, int *sweeps, int n, int batch, int k, double cluster_rel,
+                      double *work, hipStream_t st) {
+  TRG_REQUIRE(n >= 1 && n <= MAX_N && batch >= 1 && k >= 1, "eigh_top: bad sizes");
+  if (n <= JACOBI_MAX_N) {
+    hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(EIGH_THREADS), 0, st, A, w, V, sweeps, n);
+  } else {
+    TRG_REQUIRE(work != nullptr, "eigh_top: workspace missing");
+    hipLaunchKernelGGL(tridiag_top_kernel, dim3(batch), dim3(TOP_THREADS), 0, st, A, w, V, sweeps, n, k,
+                       cluster_rel, work);
+  }
   TRG_HIP_CHECK(hipGetLastError());
 }
 

@@ -425,13 +425,29 @@ void isometries_batch(std::vector<trg_ctx *> &cs, std::vector<StepPrep> &ps, int
       }
     }
   }
+  // every eigenvalue, and the eigenvectors of the kept columns plus a
+  // cluster the cut splits (the widest window and most columns over the
+  // batch, so that each context's selection finds what it reads)
+  double rel = 0.0;
+  std::vector<int> kmax(size_t(nax), 1);
+  for (int i = 0; i < nc; ++i) {
+    rel = std::max(rel, degeneracy_window(producer_precision(*cs[i])));
+    for (int a = 0; a < nax; ++a) kmax[size_t(a)] = std::max(kmax[size_t(a)], ps[i].sh.nd[others[a]]);
+  }
   if (same_n) {
     const int n = c0.dims[others[0]] * c0.dims[others[0]];
-    eigh_batched(G, W, V, sw, n, int(per_ax) * nax, c0.st);
+    const int kk = *std::max_element(kmax.begin(), kmax.end());
+    double *work = n > JACOBI_MAX_N ? c0.wsp<double>("gram_top", eigh_top_work_doubles(n, int(per_ax) * nax) * 8)
+                                    : nullptr;
+    eigh_top_batched(G, W, V, sw, n, int(per_ax) * nax, kk, rel, work, c0.st);
   } else {
     for (int a = 0; a < nax; ++a) {
       const int n = c0.dims[others[a]] * c0.dims[others[a]];
-      eigh_batched(G + gbase(a), W + wbase(a), V + gbase(a), sw + size_t(a) * per_ax, n, int(per_ax), c0.st);
+      double *work = n > JACOBI_MAX_N ? c0.wsp<double>("gram_top" + std::to_string(a),
+                                                       eigh_top_work_doubles(n, int(per_ax)) * 8)
+                                      : nullptr;
+      eigh_top_batched(G + gbase(a), W + wbase(a), V + gbase(a), sw + size_t(a) * per_ax, n, int(per_ax),
+                       kmax[size_t(a)], rel, work, c0.st);
     }
   }
   for (int a = 0; a < nax; ++a) {
@@ -1557,6 +1573,24 @@ int trg_eigh(double *A, double *w, double *V, int *sweeps, int n, int batch, voi
     eigh_batched(A, w, V, sweeps, n, batch, static_cast<hipStream_t>(stream));
     return TRG_OK;
   });
+}
+
+int trg_eigh_top(double *A, double *w, double *V, int *sweeps, int n, int batch, int k, double cluster_rel,
+                 void *work, void *stream) {
+  return guarded(nullptr, [&]() -> int {
+    TRG_REQUIRE(A && w && V && sweeps, "NULL argument");
+    TRG_REQUIRE(n >= 1 && n <= 1024 && batch >= 1 && k >= 1, "eigh_top: bad sizes");
+    TRG_REQUIRE(cluster_rel >= 0.0 && cluster_rel < 1.0, "eigh_top: cluster_rel outside [0, 1)");
+    TRG_REQUIRE(work || n <= JACOBI_MAX_N, "eigh_top: workspace missing");
+    eigh_top_batched(A, w, V, sweeps, n, batch, k, cluster_rel, static_cast<double *>(work),
+                     static_cast<hipStream_t>(stream));
+    return TRG_OK;
+  });
+}
+
+size_t trg_eigh_top_work_bytes(int n, int batch) {
+  if (n < 1 || n > 1024 || batch < 1) return 0;
+  return eigh_top_work_doubles(n, batch) * 8;
 }
 
 int trg_set_profiling(trg_ctx *ctx, int on) {

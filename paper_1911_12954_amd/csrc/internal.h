@@ -113,6 +113,15 @@ void ising_init(double *T, double *SE, double *SM, int d, double beta, double h,
 // diagonal only when each block's indices are contiguous.
 constexpr int JACOBI_MAX_N = 160;
 void eigh_batched(double *A, double *w, double *V, int *sweeps, int n, int batch, hipStream_t st);
+// Every eigenvalue (descending) but eigenvectors only for the leading kk
+// indices: k, extended while the next eigenvalue continues a cluster (gap
+// <= cluster_rel * lambda_max); the other columns of V are zero.  Above the
+// Jacobi range: Householder, bisection and inverse iteration (sweeps receives
+// kk); up to it, the full Jacobi solver.  work: eigh_top_work_doubles(n,
+// batch) doubles of device memory.
+size_t eigh_top_work_doubles(int n, int batch);
+void eigh_top_batched(double *A, double *w, double *V, int *sweeps, int n, int batch, int k, double cluster_rel,
+                      double *work, hipStream_t st);
 
 // isometry selection of one transverse axis from both sides' eigensystems
 struct SelectOut {

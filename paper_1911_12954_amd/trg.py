@@ -393,3 +393,11 @@ def trg_gemm_tile(precision):
 
 def trg_eigh(A_ptr, w_ptr, V_ptr, sweeps_ptr, n, batch, stream=None):
     _err(_lib().trg_eigh(A_ptr, w_ptr, V_ptr, sweeps_ptr, n, batch, stream))
+
+
+def trg_eigh_top(A_ptr, w_ptr, V_ptr, sweeps_ptr, n, batch, k, cluster_rel, work_ptr, stream=None):
+    _err(_lib().trg_eigh_top(A_ptr, w_ptr, V_ptr, sweeps_ptr, n, batch, k, float(cluster_rel), work_ptr, stream))
+
+
+def trg_eigh_top_work_bytes(n, batch):
+    return int(_lib().trg_eigh_top_work_bytes(n, batch))

@@ -221,3 +221,129 @@ def test_eigh_degenerate_and_zero_matrices(n):
         assert np.max(np.abs(w[b] - ref)) < 1e-13 * scale
         assert np.allclose(V[b].T @ V[b], np.eye(n), atol=1e-13)
         assert np.allclose(V[b] @ np.diag(w[b]) @ V[b].T, A[b], atol=1e-13 * scale)
+
+
+@pytest.mark.parametrize("n", [100, 200, 400])
+@pytest.mark.parametrize("tiny", [1e-160, 1e-250])
+def test_eigh_block_far_below_the_matrix_scale(n, tiny):
+    """Two diagonal blocks (contiguous, as in a parity-sorted Gram), the
+    second scaled by `tiny`, so that sums of squares of its columns fall
+    below the FP64 normal range (1e-160: into the subnormals, where an
+    unscaled Householder reflector's 2 / v^T v overflows): eigenvalues to
+    1e-13 of the matrix norm, orthonormal and finite eigenvectors, each lying
+    in one block with exact zeros in the other, and the reconstruction.
+    Both solver paths (Jacobi to 160, Householder + QL above)."""
+    torch = need_gpu()
+    from paper_1911_12954_amd import trg_eigh
+    announce("eigh tiny block", n, tiny)
+    n0 = n // 2 + 3
+    a = gram_like(n0, min(n0, 12), 5 + n)
+    b = random_symmetric(n - n0, 6 + n)
+    b = b @ b.T / (n - n0)                  # positive semi-definite, O(1)
+    A = np.zeros((n, n))
+    A[:n0, :n0] = a
+    A[n0:, n0:] = tiny * b
+    dA = torch.from_numpy(A.copy()).cuda()
+    dw = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    dV = torch.empty((1, n, n), dtype=torch.float64, device="cuda")
+    ds = torch.empty(1, dtype=torch.int32, device="cuda")
+    trg_eigh(dA.data_ptr(), dw.data_ptr(), dV.data_ptr(), ds.data_ptr(), n, 1,
+             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    w, V = dw.cpu().numpy()[0], dV.cpu().numpy()[0]
+    assert np.all(np.isfinite(w)) and np.all(np.isfinite(V))
+    nrm = np.linalg.norm(A)
+    assert np.max(np.abs(w - np.sort(np.linalg.eigvalsh(A))[::-1])) < 1e-13 * nrm
+    assert np.allclose(V.T @ V, np.eye(n), atol=1e-13)
+    assert np.allclose(V @ np.diag(w) @ V.T, A, atol=1e-13 * nrm)
+    in_a = np.abs(V[:n0]).sum(0) > 0
+    in_b = np.abs(V[n0:]).sum(0) > 0
+    assert not np.any(in_a & in_b)
+    assert int(in_a.sum()) == n0 and int(in_b.sum()) == n - n0
+
+
+def _eigh_top(A, k, rel):
+    torch = need_gpu()
+    from paper_1911_12954_amd import trg_eigh_top, trg_eigh_top_work_bytes
+    batch, n = A.shape[0], A.shape[1]
+    dA = torch.from_numpy(A.copy()).cuda()
+    dw = torch.empty((batch, n), dtype=torch.float64, device="cuda")
+    dV = torch.empty((batch, n, n), dtype=torch.float64, device="cuda")
+    ds = torch.empty(batch, dtype=torch.int32, device="cuda")
+    nb = trg_eigh_top_work_bytes(n, batch)
+    work = torch.empty(max(nb // 8, 1), dtype=torch.float64, device="cuda")
+    trg_eigh_top(dA.data_ptr(), dw.data_ptr(), dV.data_ptr(), ds.data_ptr(), n, batch, k, rel, work.data_ptr(),
+                 torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return dw.cpu().numpy(), dV.cpu().numpy(), ds.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [150, 169, 256, 576])
+def test_eigh_top_leading_pairs(n):
+    """Every eigenvalue and the leading eigenvectors of Gram-like matrices
+    (fast-decaying spectra, as the HOSVD Grams) and of random symmetric ones,
+    against LAPACK: eigenvalues to 1e-13 of the norm, each computed vector an
+    eigenvector (residual 1e-12 of the norm) orthonormal to the others, the
+    columns beyond those needed zero."""
+    announce("eigh_top", n)
+    k = 24
+    A = np.stack([gram_like(n, min(n, 60), 30 + n), random_symmetric(n, 40 + n)])
+    w, V, kk = _eigh_top(A, k, 1e-10)
+    for b in range(2):
+        ref = np.sort(np.linalg.eigvalsh(A[b]))[::-1]
+        nrm = np.linalg.norm(A[b])
+        assert np.max(np.abs(w[b] - ref)) < 1e-13 * nrm
+        q = int(kk[b]) if n > 160 else n     # the Jacobi path returns every vector (and its sweeps)
+        assert k <= q <= n
+        Vk = V[b][:, :q]
+        assert np.all(V[b][:, q:] == 0.0)
+        assert np.allclose(Vk.T @ Vk, np.eye(q), atol=1e-12)
+        assert np.max(np.abs(A[b] @ Vk - Vk * w[b][:q])) < 1e-12 * nrm
+
+
+def test_eigh_top_extends_over_a_split_cluster():
+    """Eigenvalues 5, 4, 3 (x3), 2, ...: with k = 3 the cut splits the triple,
+    so kk = 5 vectors come back, spanning the triple's eigenspace."""
+    announce("eigh_top cluster")
+    n = 200
+    rng = np.random.default_rng(7)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.concatenate([[5.0, 4.0, 3.0, 3.0, 3.0, 2.0], np.linspace(1.0, 0.0, n - 6)])
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    w, V, kk = _eigh_top(A[None], 3, 1e-10)
+    assert int(kk[0]) == 5
+    P = V[0][:, 2:5] @ V[0][:, 2:5].T
+    Pref = Q[:, 2:5] @ Q[:, 2:5].T
+    assert np.max(np.abs(P - Pref)) < 1e-12
+
+
+def test_eigh_top_parity_blocks_stay_exact():
+    """A sector-ordered block-diagonal matrix (second block 1e-160 of the
+    first, and exactly degenerate eigenvalues across the blocks): every
+    computed vector lies in one block with exact zeros in the other, and the
+    degenerate pair across the blocks gives one vector in each."""
+    announce("eigh_top parity blocks")
+    n, n0 = 300, 170
+    a = gram_like(n0, 40, 11)
+    b = gram_like(n - n0, 40, 12)
+    A = np.zeros((2, n, n))
+    A[0, :n0, :n0] = a
+    A[0, n0:, n0:] = 1e-160 * b
+    A[1, :n0, :n0] = a
+    A[1, n0:, n0:] = a[: n - n0, : n - n0] * 0.0 + np.diag(np.linalg.eigvalsh(a)[::-1][: n - n0])
+    w, V, kk = _eigh_top(A, 10, 1e-10)
+    for bb in range(2):
+        q = int(kk[bb])
+        Vk = V[bb][:, :q]
+        in_a = np.abs(Vk[:n0]).sum(0) > 0
+        in_b = np.abs(Vk[n0:]).sum(0) > 0
+        assert not np.any(in_a & in_b)
+        assert np.all(np.isfinite(Vk))
+        nrm = np.linalg.norm(A[bb])
+        assert np.max(np.abs(A[bb] @ Vk - Vk * w[bb][:q])) < 1e-12 * nrm
+    # the second matrix: block b holds the leading eigenvalues of block a, so
+    # every leading eigenvalue is doubly degenerate across the blocks
+    q = int(kk[1])
+    in_b = np.abs(V[1][n0:, :q]).sum(0) > 0
+    assert 0 < int(in_b.sum()) < q
