@@ -111,6 +111,10 @@ def parse():
     p.add_argument("--copy-cal", type=float, default=0.0,
                    help="only copy this many GiB device to device three times (calibration of the "
                         "FETCH_SIZE / WRITE_SIZE counters)")
+    p.add_argument("--step-error", default=None,
+                   help="instead of timing: 'D,prec[,prec...]' one HOTRG step of a seeded 4D tensor with every leg "
+                        "D (decaying HOSVD spectra) in FP64 and in each precision; errors of ln c and of the "
+                        "new tensor against FP64")
     p.add_argument("--atrg-scan", default=None,
                    help="instead of timing: 'dcut;L;beta0,dbeta,n;precisions' (e.g. '24;1024;0.1490,0.0001,4;"
                         "fp64,fp32'): ATRG ln Z/V over a beta scan in each contraction precision, with the "
@@ -227,6 +231,45 @@ def accuracy(spec, variants):
             continue
         out[f"rel_err_{key}"] = {k: abs(res[key][k] - ref[k]) / max(abs(ref[k]), 1e-300) for k in ("f", "E", "M")}
         out[f"abs_err_{key}"] = {k: abs(res[key][k] - ref[k]) for k in ("f", "E", "M")}
+    return out
+
+
+def step_error(spec):
+    """One steady-state HOTRG step (all legs D, axis 0) from the same seeded
+    tensor with decaying HOSVD spectra, in FP64 and in each listed join
+    precision: |ln c - ln c_64| and |T' - T'_64| / |T'_64| (Frobenius and
+    max-abs), T' the normalised new tensor."""
+    import numpy as np
+    import torch
+    from paper_1911_12954_amd import trg_init_tensor
+    from trg_inputs import decaying_site_tensor
+    fields = spec.split(",")
+    D, precs = int(fields[0]), [p for p in fields[1:] if p != "fp64"]
+    t0 = time.perf_counter()
+    T = decaying_site_tensor((D,) * 4, seed=1201)
+    progress(f"step-error: D = {D} input built in {time.perf_counter() - t0:.1f} s")
+    out = {"workload": f"one HOTRG step, 4D, every leg D = {D}, seeded tensor with decaying HOSVD spectra", "runs": {}}
+    ref = None
+    for prec in ["fp64"] + precs:
+        t1 = time.perf_counter()
+        ctx = trg_init_tensor(T, precision=prec)
+        ctx.hotrg_step(0, D)
+        ln_c = ctx.step_log()[-1].ln_c
+        Tn = ctx.tensor()
+        ctx.close()
+        torch.cuda.empty_cache()
+        row = {"ln_c": ln_c, "seconds": time.perf_counter() - t1}
+        if ref is None:
+            ref = (ln_c, Tn)
+        else:
+            d = Tn - ref[1]
+            row["abs_err_ln_c"] = abs(ln_c - ref[0])
+            row["rel_err_tensor_fro"] = float(np.linalg.norm(d.ravel()) / np.linalg.norm(ref[1].ravel()))
+            row["rel_err_tensor_max"] = float(np.max(np.abs(d)) / np.max(np.abs(ref[1])))
+            del d
+        out["runs"][prec] = row
+        progress(f"step-error: {prec} {row}")
+        del Tn
     return out
 
 
@@ -548,6 +591,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
+        return
+    if a.step_error:
+        print(json.dumps(step_error(a.step_error)), flush=True)
         return
     if a.atrg_scan:
         print(json.dumps(atrg_scan(a.atrg_scan)), flush=True)
