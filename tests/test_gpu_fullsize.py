@@ -1,5 +1,6 @@
 """One steady-state HOTRG step at the benchmark's size (4D, every leg at
-Dcut = 10, the same chunking of the join) against the oracle, on sampled
+Dcut = 10, the same chunking of the join) and at Dcut = 8 (the bond
+dimension of the accuracy runs) against the oracle, on sampled
 output blocks T'[x0, x2, Y, Y', Z, Z', :, :] that the oracle computes one by
 one, plus properties that hold at any size.  The input has geometrically
 decaying HOSVD spectra (as the Ising tensor has), so that the kept
@@ -17,32 +18,33 @@ from trg_inputs import decaying_site_tensor
 
 pytestmark = pytest.mark.gpu
 
-D = 10
 # (x0, x2, Y, Y', Z, Z'): corners, the ragged last x0 slice and interior values
-BLOCKS = [(0, 0, 0, 0, 0, 0), (9, 9, 9, 9, 9, 9), (9, 2, 3, 7, 1, 8), (4, 6, 5, 0, 9, 2)]
+BLOCKS = {10: [(0, 0, 0, 0, 0, 0), (9, 9, 9, 9, 9, 9), (9, 2, 3, 7, 1, 8), (4, 6, 5, 0, 9, 2)],
+          8: [(0, 0, 0, 0, 0, 0), (7, 7, 7, 7, 7, 7), (7, 2, 3, 6, 1, 5), (4, 6, 5, 0, 7, 2)]}
 
 
-@pytest.fixture(scope="module")
-def problem():
-    T = decaying_site_tensor((D,) * 4, seed=101)
+@pytest.fixture(scope="module", params=[10, 8])
+def problem(request):
+    D = request.param
+    T = decaying_site_tensor((D,) * 4, seed=101 if D == 10 else 81)
     Tn = T / np.sqrt(np.sum(T * T))
     choices = [hotrg.isometry(Tn, 0, nu, D) for nu in (1, 2, 3)]
     U = {ch.nu: ch.U for ch in choices}
     blocks = {}
-    for (x0, x2, y, yp, z, zp) in BLOCKS:
+    for (x0, x2, y, yp, z, zp) in BLOCKS[D]:
         Ub, Uf = dict(U), dict(U)
         Ub[1], Uf[1] = U[1][:, :, [y]], U[1][:, :, [yp]]
         Ub[2], Uf[2] = U[2][:, :, [z]], U[2][:, :, [zp]]
         blk = hotrg.coarse_grain(Tn, Tn, Ub, 0, x0s=[x0], x2s=[x2], U_forward=Uf)
         blocks[(x0, x2, y, yp, z, zp)] = blk[0, 0, 0, 0, 0, 0]
-    return T, choices, blocks
+    return D, T, choices, blocks
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 2e-4), ("bf16x6", 1e-5)])
 def test_dcut10_step_on_sampled_blocks(problem, precision, tol):
     need_gpu()
     from paper_1911_12954_amd import trg_init_tensor
-    T, choices, blocks = problem
+    D, T, choices, blocks = problem
     announce("full-size step", precision, "D", D)
     ctx = trg_init_tensor(T, precision=precision)
     ctx.hotrg_step(0, D)
@@ -65,4 +67,50 @@ def test_dcut10_step_on_sampled_blocks(problem, precision, tol):
     assert abs(np.sqrt(np.sum(got * got)) - 1.0) < 1e-12
     assert np.all(np.isfinite(got))
     assert rec.kept[1:] == (D, D, D)
+    ctx.close()
+
+
+def test_dcut8_ising_step_after_the_ramp():
+    """The accuracy runs' configuration (4D Ising, beta 0.1497, h 1e-5, Dcut
+    8): the GPU (FP64) and the oracle each run the ramp from their own
+    initial tensor -- steps along axes 1, 2, 3 take every leg from 2 to 8 --
+    and then the first step with every leg at 8, along axis 0.  That step's
+    isometries, ln c and sampled output blocks (recomputed one by one by the
+    oracle: the whole D^15 step is beyond the CPU) agree to 1e-10."""
+    need_gpu()
+    from paper_1911_12954_amd import trg_init_ising
+    from oracle import ising
+    beta, h, Dc = 0.1497, 1e-5, 8
+    announce("full-size step after the Ising ramp", "D", Dc)
+    T0 = ising.site_tensors(beta, h, 4)[0]
+    T = T0 / np.sqrt(np.sum(T0 * T0))
+    for ax in (1, 2, 3):
+        T, _, _, _ = hotrg.hotrg_step(T, ax, Dc)
+    assert T.shape == (Dc,) * 8
+    choices = [hotrg.isometry(T, 0, nu, Dc) for nu in (1, 2, 3)]
+    U = {ch.nu: ch.U for ch in choices}
+    ctx = trg_init_ising(beta, h, 4, dcut=Dc, precision="fp64")
+    for ax in (1, 2, 3):
+        ctx.hotrg_step(ax, Dc)
+    ctx.hotrg_step(0, Dc)
+    got = ctx.tensor()
+    rec = ctx.step_log()[-1]
+    c = math.exp(rec.ln_c)
+    for ch in choices:
+        Ug, _ = ctx.isometry(ch.nu)
+        assert rec.side[ch.nu] == ch.side and rec.kept[ch.nu] == ch.k
+        assert np.max(np.abs(Ug - ch.U.reshape(Dc * Dc, Dc))) < 1e-10
+    worst = 0.0
+    for (x0, x2, y, yp, z, zp) in BLOCKS[8]:
+        Ub, Uf = dict(U), dict(U)
+        Ub[1], Uf[1] = U[1][:, :, [y]], U[1][:, :, [yp]]
+        Ub[2], Uf[2] = U[2][:, :, [z]], U[2][:, :, [zp]]
+        ref = hotrg.coarse_grain(T, T, Ub, 0, x0s=[x0], x2s=[x2], U_forward=Uf)[0, 0, 0, 0, 0, 0]
+        blk = c * got[x0, x2, y, yp, z, zp]
+        worst = max(worst, np.max(np.abs(blk - ref)) / np.max(np.abs(ref)))
+    print(f"[full-size ising dcut 8] worst block error {worst:.3e}", flush=True)
+    assert worst < 1e-10
+    # the step's norm: ||coarse_grain(T, T)|| on the blocks is not the whole
+    # norm, so c is checked through the unit norm of the GPU tensor
+    assert abs(np.sqrt(np.sum(got * got)) - 1.0) < 1e-12
     ctx.close()
