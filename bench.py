@@ -47,6 +47,12 @@ JOIN_TRAFFIC = {
     ("bf16x6", 10): {"bytes_per_launch": 4.912e12, "algorithmic_bytes_per_launch": 8.51e10,
                      "gemm_sha16": "372fd768a9adad15",
                      "source": "profiles/join_gemm_hotrg_dcut10_bf16x6.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"},
+    ("fp64", 10): {"bytes_per_launch": 1.510e13, "algorithmic_bytes_per_launch": 1.202e11,
+                   "gemm_sha16": "372fd768a9adad15",
+                   "source": "profiles/join_gemm_hotrg_dcut10_fp64.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"},
+    ("fp32", 10): {"bytes_per_launch": 3.121e12, "algorithmic_bytes_per_launch": 6.01e10,
+                   "gemm_sha16": "372fd768a9adad15",
+                   "source": "profiles/join_gemm_hotrg_dcut10_fp32.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"},
 }
 GEMM_SRC = os.path.join(ROOT, "paper_1911_12954_amd", "csrc", "gemm.hip")
 
