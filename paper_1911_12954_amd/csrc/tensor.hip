@@ -193,6 +193,34 @@ __global__ void reduce_splits_kernel(const double *part, int splits, int64_t row
   out[r * ldo + c] = s;
 }
 
+// The same sum with eight threads per output: thread (o, g) of a 32 x 8
+// workgroup adds the splits k = g (mod 8) in increasing k, and the eight
+// partial sums are added in a fixed tree, so the result is deterministic;
+// 32 consecutive outputs read 256 contiguous bytes of a split.  For few
+// outputs and many splits (the slabs of a tall-skinny Gram).
+constexpr int RS_OUT = 32, RS_GROUPS = 8;
+
+__global__ void __launch_bounds__(RS_OUT * RS_GROUPS)
+reduce_splits_grouped_kernel(const double *part, int splits, int64_t rows, int64_t cols, int64_t ldp,
+                             int64_t sstride, double *out, int64_t ldo) {
+  __shared__ double sh[RS_GROUPS][RS_OUT];
+  const int o = threadIdx.x % RS_OUT, g = threadIdx.x / RS_OUT;
+  const int64_t i = int64_t(blockIdx.x) * RS_OUT + o;
+  double s = 0.0;
+  if (i < rows * cols) {
+    const int64_t r = i / cols, c = i % cols;
+    const double *p = part + r * ldp + c;
+    for (int k = g; k < splits; k += RS_GROUPS) s += p[int64_t(k) * sstride];
+  }
+  sh[g][o] = s;
+  __syncthreads();
+  if (g == 0 && i < rows * cols) {
+    const double t = ((sh[0][o] + sh[1][o]) + (sh[2][o] + sh[3][o])) + ((sh[4][o] + sh[5][o]) + (sh[6][o] + sh[7][o]));
+    const int64_t r = i / cols, c = i % cols;
+    out[r * ldo + c] = t;
+  }
+}
+
 __global__ void gram_combine_kernel(const double *P, const double *Q, int dmu, int dn, double *G) {
   // G[(a,b),(a2,b2)] = sum_{i,i2} P[(i,a),(i2,a2)] Q[(i,b),(i2,b2)]
   const int n = dn * dn;
@@ -473,8 +501,13 @@ void fill_zero(void *buf, size_t bytes, hipStream_t st) {
 void reduce_splits(const double *part, int splits, int64_t rows, int64_t cols, int64_t ldp,
                    int64_t split_stride, double *out, int64_t ldo, hipStream_t st) {
   const int64_t n = rows * cols;
-  hipLaunchKernelGGL(reduce_splits_kernel, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, st, part, splits,
-                     rows, cols, ldp, split_stride, out, ldo);
+  if (splits >= 2 * RS_GROUPS && n < int64_t(256) * 1024) {
+    hipLaunchKernelGGL(reduce_splits_grouped_kernel, dim3(uint32_t((n + RS_OUT - 1) / RS_OUT)),
+                       dim3(RS_OUT * RS_GROUPS), 0, st, part, splits, rows, cols, ldp, split_stride, out, ldo);
+  } else {
+    hipLaunchKernelGGL(reduce_splits_kernel, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, st, part, splits,
+                       rows, cols, ldp, split_stride, out, ldo);
+  }
   TRG_HIP_CHECK(hipGetLastError());
 }
 

@@ -28,6 +28,10 @@ def _oracle_step(T, mu, dcut):
     (4, (3, 3, 3, 3), 0, 9, 6),
     (4, (4, 4, 4, 4), 3, 6, 7),
     (4, (5, 4, 3, 2), 1, 7, 8),
+    # transverse orders 169 and 256 > 160: the selection eigensolver
+    # (bisection + inverse iteration), a cut at 14 inside the spectrum
+    (2, (13, 16), 0, 14, 9),
+    (3, (13, 3, 2), 2, 14, 10),
 ])
 def test_single_step_matches_oracle(d, dims, mu, dcut, seed):
     need_gpu()
