@@ -133,8 +133,9 @@ def parse():
                         "full-slice join of the Dcut = 10 step): the BF16x3 (or bf16x6) join kernel against one "
                         "plain BF16 torch.matmul (hipBLASLt) of the same shape, in MFMA TFLOP/s issued")
     p.add_argument("--accuracy", default=None,
-                   help="instead of timing: run 'dcut,L,beta,h[,pure]' in FP64, FP32 and BF16x3 with impure E "
-                        "and M (not with 'pure') and print the relative errors of f, E, M against the FP64 path")
+                   help="instead of timing: run 'dcut,L,beta,h[,pure|E|M]' in FP64 and the variants with impure E "
+                        "and M (neither with 'pure', one with 'E' or 'M') and print the relative errors of f, "
+                        "E, M against the FP64 path")
     p.add_argument("--accuracy-variants", default="fp32:0,bf16x3:0",
                    help="precision:fp64_steps pairs compared with the FP64 path")
     return p.parse_args()
@@ -205,24 +206,29 @@ def accuracy(spec, variants):
     import torch
     from paper_1911_12954_amd import trg_init_ising
     fields = spec.split(",")
-    pure = len(fields) > 4 and fields[4] == "pure"
+    # fifth field: "pure" (ln Z/V only), "E" or "M" (that impurity alone, a
+    # third of the joins of both), absent: both
+    which = fields[4] if len(fields) > 4 else "EM"
+    if which not in ("pure", "E", "M", "EM"):
+        raise SystemExit(f"--accuracy: unknown fifth field {which!r}")
+    pure = which == "pure"
+    impure = () if pure else tuple(which)
     dcut, L, beta, h = int(fields[0]), int(fields[1]), float(fields[2]), float(fields[3])
     runs = [("fp64", 0)] + [(v.split(":")[0], int(v.split(":")[1])) for v in variants.split(",") if v]
     res = {}
     for prec, n64 in runs:
         key = prec if n64 == 0 else f"{prec}+fp64x{n64}"
         t0 = time.perf_counter()
-        ctx = trg_init_ising(beta, h, 4, dcut=dcut, precision=prec, impure=() if pure else ("E", "M"),
-                             fp64_steps=n64)
+        ctx = trg_init_ising(beta, h, 4, dcut=dcut, precision=prec, impure=impure, fp64_steps=n64)
         m = L.bit_length() - 1
         for n in range(1, 4 * m + 1):
             ctx.hotrg_step((n - 1) % 4, dcut)
-            if n % 2 == 0:
+            if n % 2 == 0 or impure:
                 ctx.sync()
                 progress(f"accuracy {key}: step {n}/{4 * m} at {time.perf_counter() - t0:.1f} s")
         log = ctx.step_log()
-        res[key] = {"f": ctx.free_energy(), "E": float("nan") if pure else ctx.impure_energy(),
-                    "M": float("nan") if pure else ctx.impure_magnetization(),
+        res[key] = {"f": ctx.free_energy(), "E": ctx.impure_energy() if "E" in impure else float("nan"),
+                    "M": ctx.impure_magnetization() if "M" in impure else float("nan"),
                     "seconds": time.perf_counter() - t0,
                     "fp64_join_steps": sum(r.join_precision == "fp64" for r in log),
                     "degenerate_cuts": sum(sum(r.degenerate_cut) for r in log)}
@@ -231,7 +237,7 @@ def accuracy(spec, variants):
         progress(f"accuracy {key}: {res[key]}")
     ref = res["fp64"]
     out = {"workload": f"4D Ising HOTRG Dcut={dcut} L={L} beta={beta} h={h}, "
-                       + ("ln Z/V only" if pure else "impure E and M"), "runs": res}
+                       + ("ln Z/V only" if pure else "impure " + " and ".join(impure)), "runs": res}
     for key in res:
         if key == "fp64":
             continue
