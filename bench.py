@@ -257,6 +257,8 @@ def step_error(spec):
     from trg_inputs import decaying_site_tensor
     fields = spec.split(",")
     D, precs = int(fields[0]), [p for p in fields[1:] if p != "fp64"]
+    if "TRG_PROGRESS" not in os.environ:
+        progress("step-error: set TRG_PROGRESS=1 to see each join of the step finish")
     t0 = time.perf_counter()
     T = decaying_site_tensor((D,) * 4, seed=1201)
     progress(f"step-error: D = {D} input built in {time.perf_counter() - t0:.1f} s")

@@ -23,6 +23,10 @@
  *   or zero norm, eigensolver not converged) is reported by the next call
  *   that synchronises; the context is then poisoned and every later call on
  *   it returns TRG_ESTATE.  trg_last_error() describes the latest error.
+ * - Diagnostics from the environment, both off by default: TRG_PROGRESS
+ *   makes every join launch synchronise its stream and print one line on
+ *   stderr when it is done (for steps that run for minutes); TRG_DEBUG
+ *   copies back and summarises each intermediate of an ATRG step on stderr.
  */
 #ifndef TRG_H
 #define TRG_H

@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -351,6 +353,17 @@ void join(trg_ctx &c, int prec, const char *A, size_t a_slot, const char *Bt, si
   record_join(c, a, b, false);
   c.join_launches += 1;
   c.join_flops_pending += 2.0 * double(Mpad) * double(Npad) * double(Kpad) * nb;
+  // With TRG_PROGRESS set in the environment, wait for each join and report
+  // it on stderr: a long step (minutes at Dcut 12 in FP64) then shows its
+  // progress launch by launch.  Off by default (one cached getenv).
+  static const bool progress = std::getenv("TRG_PROGRESS") != nullptr;
+  if (progress) {
+    TRG_HIP_CHECK(hipStreamSynchronize(c.st));
+    std::fprintf(stderr, "[trg] join %lld done: %lld x %lld x %lld, %d product(s)\n",
+                 static_cast<long long>(c.join_launches), static_cast<long long>(Mpad),
+                 static_cast<long long>(Npad), static_cast<long long>(Kpad), nb);
+    std::fflush(stderr);
+  }
 }
 
 struct StepPrep {
