@@ -18,6 +18,7 @@ CASES = [
     ("4d_dcut4_L16_h1e-5", 0.1497, 1e-5, 4, 4, 16),
     ("3d_dcut6_L16_h1e-4", 0.2200, 1e-4, 3, 6, 16),
     ("2d_dcut8_L1024_h0", 0.4000, 0.0, 2, 8, 1024),
+    ("4d_dcut6_L16_h1e-5", 0.1497, 1e-5, 4, 6, 16),
 ]
 
 
