@@ -241,7 +241,7 @@ def test_fp64_steps_schedule():
 
 
 @pytest.mark.parametrize("name", ["4d_dcut4_L16_h0", "4d_dcut4_L16_h1e-5", "3d_dcut6_L16_h1e-4",
-                                  "2d_dcut8_L1024_h0"])
+                                  "2d_dcut8_L1024_h0", "4d_dcut6_L16_h1e-5"])
 def test_fp64_path_matches_stored_oracle_values(name):
     """The FP64 path against the oracle's stored results (tests/golden)."""
     need_gpu()
