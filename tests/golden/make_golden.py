@@ -27,6 +27,7 @@ ATRG_CASES = [
     ("atrg_4d_dcut4_L4_h1e-3", 0.1497, 1e-3, 4, 4, 4, 5, False),
     ("atrg_2d_dcut8_L64_h1e-2", 0.4000, 1e-2, 2, 8, 64, 1, False),
     ("atrg_z2_4d_dcut6_L1024_b0.2", 0.2000, 0.0, 4, 6, 1024, 0, True),
+    ("atrg_4d_dcut10_L16_h1e-3", 0.1497, 1e-3, 4, 10, 16, 3, False),
 ]
 
 
