@@ -146,8 +146,9 @@ def test_impure_matches_stored_oracle_values(name):
     (written by the oracle alone).  The 4D Dcut 10 case runs at h = 1e-3:
     at h = 1e-5, 0.45 % from the transition, the same run's M (0.011)
     differed between GPU and oracle by 2.0e-11 (1.8e-9 relative) while f
-    and E agreed to 1e-10 and 1e-9, the field response amplifying the
-    rounding of two FP64 evaluations."""
+    and E agreed to 1e-10 and 1e-9.  There M is ill-conditioned: in the
+    oracle alone a seeded one-ulp perturbation of the initial pieces moves
+    it by up to 4e-10 relative (f by 1e-15)."""
     import json
     import os
     need_gpu()
