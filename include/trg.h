@@ -139,7 +139,9 @@ int trg_init_tensor(trg_ctx **out, int d, const int *dims, const double *host_te
 
 /* One HOTRG coarse-graining step along `axis` (0 <= axis < d) with bond
  * dimension `dcut` (Sec. 2, Fig. 1): HOSVD isometries from the two-site Gram
- * matrices (FP64, Jacobi eigensolver on the device), the block-spin
+ * matrices (FP64 on the device: cyclic Jacobi up to order 160; above it
+ * Householder tridiagonalisation, bisection for every eigenvalue and inverse
+ * iteration for the kept eigenvectors), the block-spin
  * contraction in the configured precision, Frobenius normalisation and
  * acc += 2^{-n} ln c_n.  Impure tensors follow with the same isometries and
  * c_n.  Asynchronous.  Errors: TRG_EINVAL, TRG_ESTATE, TRG_ENOMEM, TRG_EHIP. */
