@@ -316,6 +316,9 @@ def atrg_scan(spec):
         if "fp64" in row and "fp32" in row:
             row["rel_diff_fp32"] = abs(row["fp32"] - row["fp64"]) / abs(row["fp64"])
         out["runs"].append(row)
+        # each finished point in full precision, so that a scan cut short
+        # still leaves its completed rows
+        progress("atrg-scan row " + json.dumps(row))
     return out
 
 
